@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the self-gravity Poisson hot path on one MI355X.
+
+Workload (default): 256^3 intervals on the unit box (255^3 unknowns), density
+of 16 seeded Gaussian clumps (centres U[0.2,0.8]^3, widths U[0.02,0.08],
+masses lognormal(0, 0.5)), open boundary from the multipole expansion with
+lmax = 8, FP64 geometric multigrid V(2,2) with red-black Gauss-Seidel,
+full-weighting restriction, trilinear prolongation and an exact 7^3 coarsest
+solve.  One step = one whole poisson_solve from a cold start (phi = 0):
+multipole boundary + V-cycles until the relative residual is <= 1e-8.
+
+Printed: one JSON line.  value = unknowns x V-cycles / wall time per step
+(Gcell-updates/s of the whole job, multipole included).  The roofline entry
+times the dominant kernel (the fine-level red-black colour pass) with HIP
+events on the plan's stream in its solver launch configuration.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget-s", type=float, default=12.0,
+                    help="seconds of oracle V-cycles for the CPU baseline (at least one cycle)")
+    ap.add_argument("--cpu-multipole", action="store_true",
+                    help="also time the oracle's multipole boundary (about 25 s at 255^3)")
+    ap.add_argument("--no-mixed", action="store_true")
+    return ap.parse_args()
+
+
+def traffic_from_profiles(kernel_tag: str):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, when it was taken on the current kernel."""
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    try:
+        return float(vals["bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(rho_host, n, budget_s, with_multipole):
+    from threadpoolctl import threadpool_limits
+
+    from oracle import multipole as OM
+    from oracle import smoothers as OS
+
+    unknowns = (n - 1) ** 3
+    with threadpool_limits(limits=1):
+        t_mp = None
+        if with_multipole:
+            t0 = time.perf_counter()
+            ghost, _ = OM.cart_boundary(rho_host, n, 1, 8)
+            t_mp = time.perf_counter() - t0
+        else:
+            ghost = rho_host * 0.0
+        u = ghost.copy()
+        cache = {}
+        cycles = 0
+        t0 = time.perf_counter()
+        while True:
+            OS.vcycle(u, rho_host, n, 1.0 / n, 2, 1, _cache=cache)
+            cycles += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s:
+                break
+    sample = (f"{cycles} V(2,2) cycle(s) of the oracle's NumPy reference V-cycle on the same "
+              f"{n - 1}^3-unknown input, single thread, {el:.1f} s")
+    if t_mp is not None:
+        sample += f"; oracle multipole boundary (lmax 8) took {t_mp:.1f} s (not in value)"
+    return {"value": unknowns * cycles / el / 1e9, "unit": "Gcell-updates/s", "cores": 1,
+            "kind": "oracle", "sample": sample}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one MI355X; --gpus above 1 is not supported "
+              "(the multi-GPU sharding is a design note, not part of the build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2605_03563_amd as pg
+    import workloads as W
+
+    dev = "cuda:0"
+    n = args.n
+    unknowns = (n - 1) ** 3
+    wl = W.config_c2(n=n, device=dev)
+    rho = wl.rho.contiguous()
+    grid = pg.cart_grid(n)
+    plan = pg.Plan(grid, pg.options("mg", lmax=8), device=dev)
+    phi = torch.zeros_like(rho)
+
+    def run(p, steps):
+        its, t_mp, t_it, rels = [], [], [], []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            phi.zero_()
+            r = p.solve(rho, phi, tol=args.tol)
+            if not r.converged:
+                raise RuntimeError(f"solve did not converge: {r}")
+            its.append(r.iterations)
+            t_mp.append(r.t_multipole_ms)
+            t_it.append(r.t_iter_ms)
+            rels.append(r.rel_residual)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, its, t_mp, t_it, rels
+
+    run(plan, args.warmup)
+    sec, its, t_mp, t_it, rels = run(plan, args.steps)
+    ms_per_step = sec * 1e3
+    cycles = statistics.mean(its)
+    value = unknowns * cycles / sec / 1e9
+
+    # dominant kernel: the fine-level red-black colour pass, timed alone with
+    # HIP events on the plan's stream (same arrays and launch configuration)
+    sweeps = 20
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(plan.stream):
+        pg.sweep_resident(plan, 2)
+        ev0.record(plan.stream)
+        pg.sweep_resident(plan, sweeps)
+        ev1.record(plan.stream)
+    torch.cuda.synchronize()
+    pass_ms = ev0.elapsed_time(ev1) / (2 * sweeps)
+    bytes_per_pass = 12.0 * unknowns          # FP64 GS colour pass: 24 B per unknown per full sweep
+    achieved = bytes_per_pass / (pass_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles("rb_pass7_f64_c2_255")
+
+    # plain copy bandwidth on the same device for context
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(10):
+        b.copy_(a)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * a.numel() * 4 * 10 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del a, b
+
+    extra = {}
+    if not args.no_mixed:
+        plan32 = pg.Plan(grid, pg.options("mg_ir32", lmax=8), device=dev)
+        run(plan32, max(1, args.warmup))
+        sec32, its32, _, _, _ = run(plan32, args.steps)
+        extra["mixed_fp32_mg_in_fp64_ir"] = {
+            "time_to_tol_ms": sec32 * 1e3, "refinement_steps": statistics.mean(its32),
+            "speedup_vs_fp64_mg": sec / sec32}
+        del plan32
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(rho.cpu().numpy(), n, args.cpu_budget_s, args.cpu_multipole)
+
+    out = {
+        "metric": "Gcell-updates/s", "value": value, "unit": "Gcell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"c2_clumps16_{n}^3_fp64_mg_v22_rbgs_lmax8_tol{args.tol:g}",
+                   "unknowns": unknowns, "solver": "MG V(2,2) red-black GS, FW restriction, "
+                   "trilinear prolongation, 7^3 exact coarsest", "parallelism": "single-gpu"},
+        "time_to_1e-8_ms": ms_per_step,
+        "v_cycles": cycles,
+        "t_multipole_ms": statistics.mean(t_mp),
+        "t_iter_ms": statistics.mean(t_it),
+        "rel_residual": max(rels),
+        "s_t_gzups": unknowns / sec / 1e9,
+        "smoother_pass_ms": pass_ms,
+        "smoother_gcell_updates_per_s": unknowns / (2 * pass_ms * 1e-3) / 1e9,
+        "copy_GBps": copy_gbps,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": traffic,
+                     "kernel": "k_pass7<double,false> (fine-level red-black GS colour pass)",
+                     "algorithmic_bytes_per_launch": bytes_per_pass},
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

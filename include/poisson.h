@@ -1,0 +1,206 @@
+/*
+ * poisson.h -- C ABI of the MI355X (gfx950) self-gravity Poisson library.
+ *
+ * Problem (Sections 2 and 2.1 of Krasnopolsky et al., "Iterative Poisson
+ * Solvers for Self-gravity with the GPU Code Astaroth"): given the mass
+ * density rho on a 3-D structured grid, find the potential Phi with
+ *     lap Phi = 4 pi G rho                                   (Eqs. 1, 2)
+ * under Dirichlet ghost values, iterating until the residual falls below a
+ * tolerance and warning when a maximum iteration count is reached
+ * (Section 2.1).  The ghost values come from the multipole expansion of rho
+ * with a user-chosen lmax (Section 2.2, Eqs. outer_expansion ..
+ * inner_multipole) or are supplied by the caller (analytic test mode).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All device pointers are HIP device memory owned by the caller (the
+ *   library never allocates or frees caller buffers).  The caller also owns
+ *   the workspace handed to poisson_plan; a plan keeps non-owning views into
+ *   it and must be destroyed before the workspace is released.
+ * - Every call is ordered on the plan's stream.  A plan is not thread-safe;
+ *   distinct plans (with distinct workspaces) are independent.
+ * - Cartesian arrays (rho, Phi) are vertex-centred node arrays in natural
+ *   layout, x fastest: element (i, j, k) of node array indices
+ *   0 <= i, j, k < n + 1 + 2(ghost - 1) lives at  k*pitch[1] + j*pitch[0] + i.
+ *   Nodes ghost..ghost+n-2 along every axis are unknowns; the others hold the
+ *   Dirichlet (ghost) values.  The box is [lo, hi]^3, h = (hi-lo)/n.
+ * - Log-spherical arrays are [phi][theta][r]: element (i, j, k) with
+ *   0 <= i < nr + 2 (radial ghosts at i = 0 and i = nr + 1),
+ *   0 <= j < ntheta, 0 <= k < nphi lives at k*pitch[1] + j*pitch[0] + i.
+ *   Radii r_i = r_min * exp((i-1) ds), ds = ln(r_max/r_min)/(nr-1);
+ *   theta_j = (j + 1/2) pi / ntheta; phi_k = 2 pi k / nphi (periodic).  The
+ *   colatitude neighbour past a pole is the node at phi + pi.
+ * - Functions return a status (POISSON_OK or a negative error); no exception
+ *   crosses the boundary.  poisson_last_error() gives the detail of the most
+ *   recent failure on the calling thread.
+ */
+#ifndef POISSON_MI355X_H
+#define POISSON_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define POISSON_OK            0   /* converged / done */
+#define POISSON_WARN_MAXITER  1   /* tolerance not met within max_iter (Section 2.1); Phi holds the last iterate */
+#define POISSON_EINVAL       -1   /* null pointer, bad option, tol <= 0, pitch too small */
+#define POISSON_EGRID        -2   /* grid unsuited to the method (multigrid needs n = 2^L * coarsest, Section 2.1.3) */
+#define POISSON_EWORKSPACE   -3   /* workspace missing, too small or misaligned */
+#define POISSON_EHIP         -4   /* a HIP runtime call failed */
+#define POISSON_ENUMERIC     -5   /* NaN/Inf residual or Krylov breakdown */
+#define POISSON_EADMIT       -6   /* serving: request larger than the whole memory budget */
+
+/* ---- enumerations ---------------------------------------------------- */
+#define POISSON_CARTESIAN      0
+#define POISSON_SPHERICAL_LOG  1
+
+#define POISSON_SOR            0  /* red-black SOR (Section 2.1.1) */
+#define POISSON_CG             1  /* conjugate gradients (Section 2.1.2) */
+#define POISSON_BICGSTAB       2  /* BiCGSTAB, spherical grids (Section 2.1.2) */
+#define POISSON_MG             3  /* FP64 geometric multigrid V-cycles (Section 2.1.3) */
+#define POISSON_MG_IR32        4  /* FP32 V-cycles inside FP64 iterative refinement */
+#define POISSON_BICGSTAB_MG32  5  /* BiCGSTAB right-preconditioned by one FP32 V-cycle */
+
+#define POISSON_OMEGA_OPT       0 /* 2/(1+sqrt(1-rJ^2)), rJ from Eq. rjac */
+#define POISSON_OMEGA_OPT_A     1 /* 2/(1+pi/N) */
+#define POISSON_OMEGA_CHEBYSHEV 2 /* Eq. omega_n started from n = 1, one term per colour pass */
+#define POISSON_OMEGA_FIXED     3 /* opts.omega */
+
+typedef struct poisson_plan_s* poisson_plan_t;   /* opaque */
+
+typedef struct {
+    int32_t coord;      /* POISSON_CARTESIAN or POISSON_SPHERICAL_LOG */
+    int32_t n[3];       /* Cartesian: intervals per axis (all three equal);
+                           spherical: nr, ntheta, nphi unknowns (ntheta, nphi even) */
+    double  lo[3];      /* Cartesian box corner; spherical: lo[0] = r_min */
+    double  hi[3];      /* Cartesian box corner; spherical: hi[0] = r_max */
+    int32_t ghost;      /* Cartesian ghost layers: 1 (7-point) or 3 (19-point star); spherical: 1 */
+    int32_t pad_;
+    int64_t pitch[2];   /* elements per row, elements per plane of caller arrays */
+} poisson_grid_t;
+
+typedef struct {
+    int32_t method;      /* POISSON_SOR .. POISSON_BICGSTAB_MG32 */
+    int32_t order;       /* Cartesian: 2 (7-point) or 6 (19-point star); spherical: 2 */
+    int32_t lmax;        /* >= 0: multipole boundary of this order (<= 8);
+                            -1: ghost values are read from Phi as given (Section 2.2 test mode) */
+    int32_t nu1, nu2;    /* multigrid pre/post smoothing sweeps */
+    int32_t coarsest;    /* multigrid coarsest intervals per axis (solved exactly) */
+    int32_t omega_mode;  /* SOR: POISSON_OMEGA_* */
+    int32_t max_iter;    /* iteration / cycle cap */
+    int32_t check_every; /* iterations between residual checks (>= 1) */
+    int32_t pad_;
+    double  omega;       /* SOR with POISSON_OMEGA_FIXED */
+    double  four_pi_G;   /* 4 pi G */
+    double  point_mass;  /* mass of a point at the expansion origin (central sink), 0 for none */
+} poisson_opts_t;
+
+typedef struct {
+    int32_t iterations;       /* sweeps / Krylov steps / V-cycles / refinement steps done */
+    int32_t status;           /* same as the return value */
+    double  rel_residual;     /* ||b - A Phi|| / ||b|| at exit (2-norm over unknowns) */
+    double  b_norm;           /* ||b||: residual of Phi with zero unknowns */
+    double  rate;             /* mean convergence rate (rel_residual)^(1/iterations) (Eq. rho) */
+    double  t_multipole_ms;   /* time of the multipole boundary phase */
+    double  t_iter_ms;        /* time of the iteration phase */
+    double* residual_history; /* optional caller-owned host array, rel residual per check */
+    int32_t history_cap;      /* its capacity */
+    int32_t history_len;      /* entries written */
+} poisson_stats_t;
+
+/* Default options for a method (order 2, lmax 8, V(2,2) to 8 intervals,
+   max_iter 10000, check_every 1, four_pi_G 1). */
+void poisson_default_opts(poisson_opts_t* opts, int32_t method);
+
+/* Bytes of device workspace a plan for (grid, opts) needs.  Returns 0 and
+   sets the last error when the combination is invalid. */
+size_t poisson_workspace_bytes(const poisson_grid_t* grid, const poisson_opts_t* opts);
+
+/* Build a plan: validate the grid (multigrid: n = 2^L * coarsest,
+   Section 2.1.3), carve d_workspace (256-byte aligned, >= the size above)
+   into level arrays, precompute omega (Eqs. omega_final, rjac, omega_n) and
+   the exact inverse of the coarsest operator, and record the stream
+   (a hipStream_t; NULL = default stream).  *out is set only on success. */
+int poisson_plan(poisson_plan_t* out, const poisson_grid_t* grid, const poisson_opts_t* opts,
+                 void* d_workspace, size_t ws_bytes, void* stream);
+
+/* Section 2.2: compute the multipole moments of d_rho (sums over the
+   unknown nodes with weight h^3, or r^3 ds sin(theta) dtheta dphi on the
+   spherical grid; expansion origin at the box centre / r = 0) and overwrite
+   every ghost node of d_phi with the expansion's potential (Cartesian: all
+   faces, edges and corners of every ghost layer; spherical: the outer shell
+   from the outer expansion, the inner shell from the inner expansion plus
+   the central point mass).  lmax in 0..8.  If h_q is not NULL it receives
+   (lmax+1)^2 outer moments (index l*l + l + m; m < 0 sine, m >= 0 cosine
+   real harmonics, orthonormal, no Condon-Shortley phase) followed, on the
+   spherical grid, by (lmax+1)^2 inner moments; it is written after a
+   stream synchronisation. */
+int multipole_boundary(poisson_plan_t plan, const double* d_rho, double* d_phi, int32_t lmax,
+                       double* h_q);
+
+/* Solve lap Phi = 4 pi G rho (Cartesian) or r^2 lap Phi = r^2 4 pi G rho
+   (spherical, Eq. 2 in s = ln r) for the unknowns of d_phi.  On entry the
+   unknowns are the initial guess (warm start, Section 2.1); with
+   opts.lmax >= 0 the ghosts are first set by multipole_boundary, otherwise
+   read as given.  Stops when ||b - A Phi|| <= tol ||b|| (checked every
+   check_every iterations) or after max_iter; returns POISSON_OK or
+   POISSON_WARN_MAXITER.  grid must equal the plan's grid.  stats may be
+   NULL. */
+int poisson_solve(poisson_plan_t plan, const double* d_rho, double* d_phi,
+                  const poisson_grid_t* grid, double tol, poisson_stats_t* stats);
+
+void poisson_plan_destroy(poisson_plan_t plan);
+
+const char* poisson_strerror(int status);
+const char* poisson_last_error(void);
+
+/* ---- single-operator entry points (same plan, same layouts) ------------
+   These expose the individual hot-path operations for verification and
+   profiling; all are asynchronous on the plan stream unless a host output
+   is requested. */
+
+/* d_out[unknowns] = (L_h Phi) on the unknown nodes (Cartesian: 7-point or
+   19-point star by opts.order; spherical: the r^2-scaled operator).  Other
+   entries of d_out are left untouched. */
+int poisson_op_apply(poisson_plan_t plan, const double* d_phi, double* d_out);
+
+/* d_res[unknowns] = 4 pi G rho - L_h Phi (spherical: r^2-scaled), and
+   *h_norm2 = sum of squares over the unknowns (NULL to skip; synchronises). */
+int poisson_op_residual(poisson_plan_t plan, const double* d_rho, const double* d_phi,
+                        double* d_res, double* h_norm2);
+
+/* `sweeps` full Gauss-Seidel/SOR sweeps in place on the unknowns of d_phi
+   (Cartesian): colours in increasing order when forward != 0, reversed
+   otherwise; red-black with relaxation omega for order 2 (Section 2.1.1),
+   four colours with omega = 1 for order 6 (Section 2.1.2). */
+int poisson_op_smooth(poisson_plan_t plan, const double* d_rho, double* d_phi, int32_t sweeps,
+                      int32_t forward, double omega);
+
+/* Full-weighting restriction (Section 2.1.3) of a dense (n-1)^3 array of
+   unknown values to a dense (n/2-1)^3 array (both x fastest, no ghosts). */
+int poisson_op_restrict(poisson_plan_t plan, const double* d_fine, double* d_coarse);
+
+/* d_fine += P d_coarse, P = 8 R^T (trilinear), dense interior arrays as above. */
+int poisson_op_prolong_add(poisson_plan_t plan, const double* d_coarse, double* d_fine);
+
+/* `cycles` V(nu1,nu2) cycles (MG or MG_IR32 plans use their own precision;
+   for MG_IR32 one cycle = one refinement step) on d_phi with the ghosts as
+   given, no convergence test. */
+int poisson_op_vcycle(poisson_plan_t plan, const double* d_rho, double* d_phi, int32_t cycles);
+
+/* `sweeps` forward Gauss-Seidel sweeps (omega = 1) on the plan's resident
+   fine-level arrays exactly as the last poisson_solve / poisson_op_* call
+   left them, with no layout conversion: the smoother kernel alone, for
+   timing it in its solver launch configuration.  MG / MG_IR32 plans sweep
+   their cycle's finest level (FP64 or FP32); other Cartesian plans the FP64
+   potential. */
+int poisson_op_sweep_resident(poisson_plan_t plan, int32_t sweeps);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POISSON_MI355X_H */

@@ -1,0 +1,216 @@
+"""MI355X (gfx950) iterative Poisson solvers for self-gravity.
+
+Thin Python binding of the C ABI in ``include/poisson.h``: it only marshals
+torch device tensors (as raw pointers) and structures; every step of the
+solve runs in the HIP library ``libpoisson_mi355x.so``.  There is no CPU
+fallback: when the library is missing every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from . import _lib as L
+from ._lib import (BICGSTAB, BICGSTAB_MG32, CARTESIAN, CG, MG, MG_IR32, OMEGA_CHEBYSHEV, OMEGA_FIXED,
+                   OMEGA_OPT, OMEGA_OPT_A, SOR, SPHERICAL_LOG, WARN_MAXITER)
+
+METHODS = {"sor": SOR, "cg": CG, "bicgstab": BICGSTAB, "mg": MG, "mg_ir32": MG_IR32,
+           "bicgstab_mg32": BICGSTAB_MG32}
+
+
+class PoissonError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        lib = L.load()
+        msg = lib.poisson_strerror(status).decode()
+        detail = lib.poisson_last_error().decode()
+        super().__init__(f"{where}: {msg} ({status}): {detail}")
+        self.status = status
+
+
+def _check(status: int, where: str) -> int:
+    if status < 0:
+        raise PoissonError(status, where)
+    return status
+
+
+def _ptr(t: Optional[torch.Tensor], need: int = 0):
+    """Raw device pointer of a float64 device tensor holding >= need elements."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("device tensor expected")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("contiguous float64 tensor expected")
+    if t.numel() < need:
+        raise ValueError(f"tensor holds {t.numel()} elements, {need} needed")
+    return C.c_void_p(t.data_ptr())
+
+
+def cart_grid(n: int, ghost: int = 1, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), pitch_x: Optional[int] = None):
+    m = n + 1 + 2 * (ghost - 1)
+    px = m if pitch_x is None else pitch_x
+    g = L.Grid()
+    g.coord = CARTESIAN
+    g.n[:] = [n, n, n]
+    g.lo[:] = list(lo)
+    g.hi[:] = list(hi)
+    g.ghost = ghost
+    g.pitch[:] = [px, px * m]
+    return g
+
+
+def sph_grid(nr: int, nth: int, nph: int, r_min=1e-3, r_max=1.0, pitch_r: Optional[int] = None):
+    pr = nr + 2 if pitch_r is None else pitch_r
+    g = L.Grid()
+    g.coord = SPHERICAL_LOG
+    g.n[:] = [nr, nth, nph]
+    g.lo[:] = [r_min, 0.0, 0.0]
+    g.hi[:] = [r_max, math.pi, 2 * math.pi]
+    g.ghost = 1
+    g.pitch[:] = [pr, pr * nth]
+    return g
+
+
+def array_shape(grid) -> tuple:
+    """Shape (planes, rows, pitch) of a caller array for `grid`."""
+    if grid.coord == CARTESIAN:
+        m = grid.n[0] + 1 + 2 * (grid.ghost - 1)
+        return (m, m, grid.pitch[0])
+    return (grid.n[2], grid.n[1], grid.pitch[0])
+
+
+def options(method="mg", order=2, lmax=8, nu1=2, nu2=2, coarsest=8, omega_mode=OMEGA_OPT, omega=1.0,
+            max_iter=10000, check_every=1, four_pi_G=1.0, point_mass=0.0):
+    o = L.Opts()
+    L.load().poisson_default_opts(C.byref(o), METHODS[method] if isinstance(method, str) else method)
+    o.order, o.lmax, o.nu1, o.nu2, o.coarsest = order, lmax, nu1, nu2, coarsest
+    o.omega_mode, o.omega, o.max_iter, o.check_every = omega_mode, omega, max_iter, check_every
+    o.four_pi_G, o.point_mass = four_pi_G, point_mass
+    return o
+
+
+def workspace_bytes(grid, opts) -> int:
+    nbytes = L.load().poisson_workspace_bytes(C.byref(grid), C.byref(opts))
+    if nbytes == 0:
+        raise PoissonError(L.EINVAL, "poisson_workspace_bytes")
+    return int(nbytes)
+
+
+@dataclass
+class SolveResult:
+    status: int
+    iterations: int
+    rel_residual: float
+    b_norm: float
+    rate: float
+    t_multipole_ms: float
+    t_iter_ms: float
+    history: list
+
+    @property
+    def converged(self) -> bool:
+        return self.status == 0
+
+
+class Plan:
+    """A solver plan with its device workspace (a torch uint8 tensor)."""
+
+    def __init__(self, grid, opts, device="cuda:0", stream: Optional[torch.cuda.Stream] = None):
+        self.lib = L.load()
+        self.grid, self.opts = grid, opts
+        self.device = torch.device(device)
+        nbytes = workspace_bytes(grid, opts)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        handle = C.c_void_p()
+        _check(self.lib.poisson_plan(C.byref(handle), C.byref(grid), C.byref(opts),
+                                     C.c_void_p(self._ws_ptr), nbytes, C.c_void_p(self.stream.cuda_stream)),
+               "poisson_plan")
+        self.handle = handle
+
+    @property
+    def node_elems(self) -> int:
+        """Elements a caller rho / phi array must hold."""
+        p, r, _ = array_shape(self.grid)
+        return int(p * self.grid.pitch[1])
+
+    def _dense_elems(self, level: int) -> int:
+        e = self.grid.n[0] // (2 ** level) - 1
+        return e ** 3
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.poisson_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ hot path
+    def solve(self, rho: torch.Tensor, phi: torch.Tensor, tol: float = 1e-8, history: int = 0) -> SolveResult:
+        st = L.Stats()
+        buf = None
+        if history > 0:
+            buf = (C.c_double * history)()
+            st.residual_history = C.cast(buf, C.POINTER(C.c_double))
+            st.history_cap = history
+        ne = self.node_elems
+        status = _check(self.lib.poisson_solve(self.handle, _ptr(rho, ne), _ptr(phi, ne), C.byref(self.grid), tol,
+                                               C.byref(st)), "poisson_solve")
+        hist = [buf[i] for i in range(st.history_len)] if buf is not None else []
+        return SolveResult(status, st.iterations, st.rel_residual, st.b_norm, st.rate, st.t_multipole_ms,
+                           st.t_iter_ms, hist)
+
+    def multipole_boundary(self, rho: torch.Tensor, phi: torch.Tensor, lmax: int):
+        nq = (lmax + 1) ** 2 * (2 if self.grid.coord == SPHERICAL_LOG else 1)
+        q = (C.c_double * nq)()
+        ne = self.node_elems
+        _check(self.lib.multipole_boundary(self.handle, _ptr(rho, ne), _ptr(phi, ne), lmax, q), "multipole_boundary")
+        return [q[i] for i in range(nq)]
+
+    # ------------------------------------------------------------ single operators
+    def apply(self, phi: torch.Tensor, out: torch.Tensor):
+        ne = self.node_elems
+        _check(self.lib.poisson_op_apply(self.handle, _ptr(phi, ne), _ptr(out, ne)), "poisson_op_apply")
+
+    def residual(self, rho, phi, res) -> float:
+        n2 = C.c_double()
+        ne = self.node_elems
+        _check(self.lib.poisson_op_residual(self.handle, _ptr(rho, ne), _ptr(phi, ne), _ptr(res, ne), C.byref(n2)),
+               "poisson_op_residual")
+        return n2.value
+
+    def smooth(self, rho, phi, sweeps=1, forward=True, omega=1.0):
+        ne = self.node_elems
+        _check(self.lib.poisson_op_smooth(self.handle, _ptr(rho, ne), _ptr(phi, ne), sweeps, 1 if forward else 0,
+                                          omega),
+               "poisson_op_smooth")
+
+    def restrict(self, fine, coarse):
+        _check(self.lib.poisson_op_restrict(self.handle, _ptr(fine, self._dense_elems(0)),
+                                            _ptr(coarse, self._dense_elems(1))), "poisson_op_restrict")
+
+    def prolong_add(self, coarse, fine):
+        _check(self.lib.poisson_op_prolong_add(self.handle, _ptr(coarse, self._dense_elems(1)),
+                                               _ptr(fine, self._dense_elems(0))), "poisson_op_prolong_add")
+
+    def vcycle(self, rho, phi, cycles=1):
+        ne = self.node_elems
+        _check(self.lib.poisson_op_vcycle(self.handle, _ptr(rho, ne), _ptr(phi, ne), cycles), "poisson_op_vcycle")
+
+
+def sweep_resident(plan: "Plan", sweeps: int):
+    _check(plan.lib.poisson_op_sweep_resident(plan.handle, sweeps), "poisson_op_sweep_resident")
+
+
+def library_path() -> str:
+    return L.LIB_PATH

@@ -1,0 +1,146 @@
+// Internal declarations of the gfx950 Poisson library: level geometry,
+// device helpers and the host-side launch wrappers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/poisson.h"
+
+namespace psn {
+
+constexpr int kLmaxMax = 8;
+constexpr int kNqMax = (kLmaxMax + 1) * (kLmaxMax + 1);  // 81 real moments
+constexpr int kRowAlign = 32;       // compact rows padded to 32 elements
+constexpr int kMomBlocks = 1024;    // blocks of the moment kernels (partials per moment)
+
+// ---------------------------------------------------------------------------
+// Colour-split level layout.
+//
+// A level with n intervals and g ghost layers has M = n + 1 + 2(g-1) nodes
+// per axis, node array indices a, b, k in [0, M) (x, y, z).  The node's
+// colour is (a + b + k + off) mod C with off chosen so that the colour equals
+// (i + j + k) mod C in global node indices i = a - (g-1) (Sections 2.1.1 and
+// 2.1.2: two colours for the 7-point operator, four for the 19-point star).
+// Nodes are stored per colour, compacted along x: node (a, b, k) lives in
+// colour array c = colour(a,b,k) at row (k*M + b) and column a / C.  A pass
+// over one colour therefore streams whole rows of that colour and reads the
+// other colours at the same or adjacent columns.
+// ---------------------------------------------------------------------------
+struct Geom {
+  int n;      // intervals per axis
+  int g;      // ghost layers (stencil radius)
+  int C;      // colours (power of two: 2 or 4)
+  int lc;     // log2(C)
+  int M;      // nodes per axis
+  int W;      // row pitch of a colour array (elements)
+  int off;    // colour offset
+  int pad_;
+  long long cs;  // elements per colour array (M*M*W)
+  double h;
+
+  __host__ __device__ long long row(int b, int k) const { return ((long long)k * M + b) * W; }
+  __host__ __device__ int colour(int a, int b, int k) const { return (a + b + k + off) & (C - 1); }
+  __host__ __device__ long long at(int a, int b, int k) const {
+    return (long long)colour(a, b, k) * cs + row(b, k) + (a >> lc);
+  }
+  __host__ __device__ bool inner(int a) const { return a >= g && a <= g + n - 2; }
+  __host__ __device__ long long total() const { return cs * C; }
+  // number of compact columns that can hold an unknown
+  __host__ __device__ int mlo() const { return g >> lc; }
+  __host__ __device__ int mhi() const { return (g + n - 2) >> lc; }
+};
+
+Geom make_geom(int n, int g, int C, double h);
+
+// ---------------------------------------------------------------------------
+// Log-spherical natural layout (radius fastest, one ghost at each end).
+// ---------------------------------------------------------------------------
+struct SGeom {
+  int nr, nth, nph;
+  int pad_;
+  long long p0, p1;   // row pitch (>= nr + 2), plane pitch (>= nth * p0)
+  double ds, dth, dph, r_min;
+  __host__ __device__ long long at(int i, int j, int k) const { return (long long)k * p1 + (long long)j * p0 + i; }
+};
+
+// Per-plan device scalars used by the Krylov solvers and reductions.
+struct Scalars {
+  double v[32];
+};
+
+// ---------------------------------------------------------------------------
+// Launch wrappers (all asynchronous on `st`).
+// ---------------------------------------------------------------------------
+// natural <-> split conversions; scale multiplies the values (4 pi G for rho).
+void split_from_natural(const double* src, long long p0, long long p1, void* dst, bool dst_f32,
+                        const Geom& G, double scale, hipStream_t st);
+void merge_to_natural(const double* src_split, double* dst, long long p0, long long p1, const Geom& G,
+                      bool unknowns_only, double scale, hipStream_t st);
+void fill_zero(void* x, bool f32, long long count, hipStream_t st);
+void zero_unknowns(void* x, bool f32, const Geom& G, hipStream_t st);
+void copy_ghosts_split(const double* src, void* dst, bool dst_f32, const Geom& G, hipStream_t st);
+
+// one colour pass of Gauss-Seidel / SOR in place (order 2: 7-point, order 6: star)
+void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, int colour,
+                 double omega, hipStream_t st);
+
+// r = f - L phi on the unknowns (split in, split out or nullptr); partial sums
+// of r^2 go to partial[kReduceBlocks].  zero_unknowns_in treats the unknowns of
+// phi as 0 (norm of b).  out_f32 selects the output precision.
+void residual(const void* phi, const void* f, bool in_f32, void* r_out, bool out_f32, const Geom& G,
+              int order, bool zero_unknowns_in, double* partial, hipStream_t st);
+int residual_blocks(const Geom& G);   // partials written by residual()
+void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom& Gc, bool f32,
+                 hipStream_t st);
+void prolong_add(const void* e_coarse, const Geom& Gc, void* phi_fine, const Geom& Gf, bool f32,
+                 hipStream_t st);
+void coarse_solve(const double* inv, const void* f, void* phi, bool f32, const Geom& G, hipStream_t st);
+// phi64 (unknowns) += e (f32 or f64)
+void add_correction(double* phi, const void* e, bool e_f32, const Geom& G, hipStream_t st);
+
+// dense interior (n-1)^3 <-> split helpers for the single-operator entry points
+void dense_to_split(const double* dense, void* split, bool f32, const Geom& G, hipStream_t st);
+void split_to_dense(const void* split, bool f32, double* dense, const Geom& G, hipStream_t st);
+
+// reductions: sum nb partials of each of nslots slots (stride kPartialCap)
+// into scal->v[dst + slot]
+void finish_sum(const double* partial, int nb, int nslots, Scalars* scal, int dst, hipStream_t st);
+
+// CG (A = -L, zero-ghost direction vectors, split layout, FP64)
+void cg_direction_apply(const double* r, const double* p_old, double* p_new, double* q, const Geom& G,
+                        int order, const Scalars* scal, double* partial, hipStream_t st);
+void cg_update(double* x, double* r, const double* p, const double* q, const Geom& G, const Scalars* scal,
+               double* partial, hipStream_t st);
+void cg_scalars(const double* partial, int nb, Scalars* scal, int stage, hipStream_t st);
+int cg_blocks(const Geom& G);
+
+// multipole (Section 2.2)
+void cart_moments(const double* rho, long long p0, long long p1, int n, int g, double h, double cx,
+                  double cy, double cz, int lmax, double* partial, hipStream_t st);
+void sph_moments(const double* rho, const SGeom& S, int lmax, bool inner, double* partial, hipStream_t st);
+void finish_moments(const double* partial, int nq, double point_mass, double* q, hipStream_t st);
+void cart_ghosts(double* phi, long long p0, long long p1, int n, int g, double h, double lo, double cx,
+                 double cy, double cz, int lmax, const double* q, double G, hipStream_t st);
+void sph_ghosts(double* phi, const SGeom& S, int lmax, const double* q, const double* qbar,
+                double point_mass, double G, hipStream_t st);
+
+// spherical operator and BiCGSTAB building blocks (FP64, natural layout)
+struct SphCoef { const double* cot; const double* isin2; const double* r2; };
+void sph_residual(const double* u, const double* rho, double* r, const SGeom& S, const SphCoef& c,
+                  double four_pi_G, bool zero_unknowns_in, double* partial, hipStream_t st);
+void sph_apply(const double* u, double* out, const SGeom& S, const SphCoef& c, hipStream_t st);
+void bicg_p_v(const double* r, const double* p_old, const double* v_old, double* p, double* v,
+              const double* rhat, const SGeom& S, const SphCoef& c, const Scalars* scal, double* partial,
+              hipStream_t st);
+void bicg_s_t(const double* r, const double* v, double* s, double* t, const SGeom& S, const SphCoef& c,
+              const Scalars* scal, double* partial, hipStream_t st);
+void bicg_xr(double* x, double* r, const double* p, const double* s, const double* t, const double* rhat,
+             const SGeom& S, const Scalars* scal, double* partial, hipStream_t st);
+void bicg_scalars(const double* partial, int nb, Scalars* scal, int stage, hipStream_t st);
+int sph_blocks(const SGeom& S);
+void sph_fill_zero(double* x, const SGeom& S, hipStream_t st);
+void sph_copy(const double* src, double* dst, const SGeom& S, hipStream_t st);
+
+}  // namespace psn

@@ -1,0 +1,1051 @@
+// Host side of the gfx950 Poisson library: workspace layout, plan
+// construction, the solver drivers (red-black SOR, CG, geometric multigrid,
+// FP32 multigrid inside FP64 iterative refinement, BiCGSTAB on the
+// log-spherical grid) and the C ABI declared in include/poisson.h.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+#include "reduce.h"
+
+using namespace psn;
+
+// ============================================================ error state
+static thread_local char g_err[512] = "";
+
+static void set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+}
+
+#define HIPCHK(expr)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (expr);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      set_error("%s failed: %s", #expr, hipGetErrorString(e_));                      \
+      return POISSON_EHIP;                                                           \
+    }                                                                                \
+  } while (0)
+
+#define CHK(expr)                      \
+  do {                                 \
+    int s_ = (expr);                   \
+    if (s_ < 0) return s_;             \
+  } while (0)
+
+static int launch_check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    set_error("kernel launch in %s failed: %s", what, hipGetErrorString(e));
+    return POISSON_EHIP;
+  }
+  return POISSON_OK;
+}
+
+// ============================================================ plan
+namespace {
+
+struct Level {
+  Geom G;
+  void* phi = nullptr;
+  void* f = nullptr;
+  void* tmp = nullptr;
+};
+
+enum ScalarSlot { kRR = 0, kBnorm2 = 8, kRes2 = 9 };
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  void* take(size_t bytes) {
+    off = (off + 255) & ~(size_t)255;
+    void* p = base ? base + off : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+}  // namespace
+
+struct poisson_plan_s {
+  poisson_grid_t grid{};
+  poisson_opts_t opts{};
+  hipStream_t st = nullptr;
+  hipStream_t cap = nullptr;  // private stream used only to capture graphs
+  bool sph = false;
+  int order = 2;
+  int C = 2;
+  // Cartesian level 0 (FP64, colour split)
+  Geom G0{};
+  double* phi64 = nullptr;
+  double* f64 = nullptr;
+  double* t64 = nullptr;
+  // multigrid hierarchy: lv[0] is the finest level of the cycle
+  std::vector<Level> lv;
+  bool mg32 = false;
+  double* cinv = nullptr;
+  int ncoarse = 0;
+  // CG
+  double *cr = nullptr, *cp0 = nullptr, *cp1 = nullptr, *cq = nullptr;
+  // spherical
+  SGeom S{};
+  SphCoef sc{};
+  double *sr = nullptr, *srh = nullptr, *sp[2] = {nullptr, nullptr}, *sv[2] = {nullptr, nullptr};
+  double *ss = nullptr, *stt = nullptr;
+  // reductions and moments
+  double* partial = nullptr;
+  Scalars* scal = nullptr;
+  double* qlm = nullptr;  // 2 * kNqMax
+  double* host = nullptr; // pinned scalars
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t step_exec = nullptr;
+  std::vector<double> omega_seq;
+};
+
+namespace {
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
+  if (!g || !o) {
+    set_error("null grid or options");
+    return POISSON_EINVAL;
+  }
+  if (o->lmax < -1 || o->lmax > kLmaxMax) {
+    set_error("lmax must be in -1..%d", kLmaxMax);
+    return POISSON_EINVAL;
+  }
+  if (o->max_iter < 1 || o->check_every < 1) {
+    set_error("max_iter and check_every must be >= 1");
+    return POISSON_EINVAL;
+  }
+  if (!(o->four_pi_G > 0.0)) {
+    set_error("four_pi_G must be positive");
+    return POISSON_EINVAL;
+  }
+  if (g->coord == POISSON_SPHERICAL_LOG) {
+    if (o->method != POISSON_BICGSTAB) {
+      set_error("the log-spherical grid is solved by BiCGSTAB");
+      return POISSON_EINVAL;
+    }
+    if (g->n[0] < 3 || g->n[1] < 2 || g->n[2] < 2 || (g->n[1] & 1) || (g->n[2] & 1)) {
+      set_error("spherical grid needs nr >= 3 and even ntheta, nphi");
+      return POISSON_EGRID;
+    }
+    if (!(g->lo[0] > 0.0) || !(g->hi[0] > g->lo[0])) {
+      set_error("spherical grid needs 0 < r_min < r_max");
+      return POISSON_EGRID;
+    }
+    if (g->pitch[0] < g->n[0] + 2 || g->pitch[1] < (int64_t)g->n[1] * g->pitch[0]) {
+      set_error("pitch too small for the spherical grid");
+      return POISSON_EINVAL;
+    }
+    if (o->order != 2) {
+      set_error("the spherical operator is 2nd order");
+      return POISSON_EINVAL;
+    }
+    SGeom S{};
+    S.nr = g->n[0];
+    S.nth = g->n[1];
+    S.nph = g->n[2];
+    if (sph_blocks(S) > kPartialCap) {
+      set_error("grid too large for the reduction buffers");
+      return POISSON_EGRID;
+    }
+    return POISSON_OK;
+  }
+  if (g->coord != POISSON_CARTESIAN) {
+    set_error("unknown coordinate system %d", g->coord);
+    return POISSON_EINVAL;
+  }
+  const int n = g->n[0];
+  if (g->n[1] != n || g->n[2] != n) {
+    set_error("Cartesian grids must have the same interval count on every axis");
+    return POISSON_EGRID;
+  }
+  if (n < 2) {
+    set_error("need at least 2 intervals");
+    return POISSON_EGRID;
+  }
+  const double h = (g->hi[0] - g->lo[0]) / n;
+  for (int d = 0; d < 3; ++d) {
+    const double hd = (g->hi[d] - g->lo[d]) / n;
+    if (!(hd > 0.0) || fabs(hd - h) > 1e-12 * h) {
+      set_error("Cartesian grids must be isotropic (equal spacing on all axes)");
+      return POISSON_EGRID;
+    }
+  }
+  if (o->order != 2 && o->order != 6) {
+    set_error("order must be 2 (7-point) or 6 (19-point star)");
+    return POISSON_EINVAL;
+  }
+  const int need_g = o->order == 2 ? 1 : 3;
+  if (g->ghost != need_g) {
+    set_error("order %d needs ghost = %d", o->order, need_g);
+    return POISSON_EGRID;
+  }
+  const int M = n + 1 + 2 * (g->ghost - 1);
+  if (residual_blocks(make_geom(n, g->ghost, o->order == 6 ? 4 : 2, 1.0)) > kPartialCap) {
+    set_error("grid too large for the reduction buffers");
+    return POISSON_EGRID;
+  }
+  if (g->pitch[0] < M || g->pitch[1] < (int64_t)M * g->pitch[0]) {
+    set_error("pitch too small: need pitch[0] >= %d and pitch[1] >= %d*pitch[0]", M, M);
+    return POISSON_EINVAL;
+  }
+  switch (o->method) {
+    case POISSON_SOR:
+      if (o->order != 2) {
+        set_error("red-black SOR is defined for the 7-point operator");
+        return POISSON_EINVAL;
+      }
+      break;
+    case POISSON_CG:
+      break;
+    case POISSON_MG:
+    case POISSON_MG_IR32: {
+      if (o->coarsest < 2 || o->nu1 < 0 || o->nu2 < 0) {
+        set_error("multigrid needs coarsest >= 2, nu >= 0");
+        return POISSON_EINVAL;
+      }
+      if (n % o->coarsest != 0 || !is_pow2(n / o->coarsest)) {
+        set_error("multigrid needs n = 2^L * coarsest (n = %d, coarsest = %d)", n, o->coarsest);
+        return POISSON_EGRID;
+      }
+      const int Nc = (o->coarsest - 1) * (o->coarsest - 1) * (o->coarsest - 1);
+      if (Nc > 4096) {
+        set_error("coarsest level too large for the dense solve (%d unknowns)", Nc);
+        return POISSON_EGRID;
+      }
+      break;
+    }
+    default:
+      set_error("method %d is not available on Cartesian grids", o->method);
+      return POISSON_EINVAL;
+  }
+  return POISSON_OK;
+}
+
+// Lay out (or measure, when base == nullptr) the workspace of a plan.
+void carve(poisson_plan_s* P, Carver& cv) {
+  const poisson_grid_t& g = P->grid;
+  const poisson_opts_t& o = P->opts;
+  P->partial = (double*)cv.take(sizeof(double) * std::max<long long>(2 * kPartialCap, (long long)kNqMax * kMomBlocks));
+  P->scal = (Scalars*)cv.take(sizeof(Scalars));
+  P->qlm = (double*)cv.take(sizeof(double) * 2 * kNqMax);
+  if (P->sph) {
+    const long long elems = g.pitch[1] * (long long)g.n[2];
+    const size_t vb = sizeof(double) * elems;
+    P->sc.cot = (const double*)cv.take(sizeof(double) * g.n[1]);
+    P->sc.isin2 = (const double*)cv.take(sizeof(double) * g.n[1]);
+    P->sc.r2 = (const double*)cv.take(sizeof(double) * (g.n[0] + 2));
+    P->sr = (double*)cv.take(vb);
+    P->srh = (double*)cv.take(vb);
+    for (int i = 0; i < 2; ++i) {
+      P->sp[i] = (double*)cv.take(vb);
+      P->sv[i] = (double*)cv.take(vb);
+    }
+    P->ss = (double*)cv.take(vb);
+    P->stt = (double*)cv.take(vb);
+    return;
+  }
+  const int n = g.n[0];
+  const double h = (g.hi[0] - g.lo[0]) / n;
+  P->G0 = make_geom(n, g.ghost, P->C, h);
+  const size_t b64 = sizeof(double) * P->G0.total();
+  P->phi64 = (double*)cv.take(b64);
+  P->f64 = (double*)cv.take(b64);
+  P->t64 = (double*)cv.take(b64);
+  if (o.method == POISSON_CG) {
+    P->cr = (double*)cv.take(b64);
+    P->cp0 = (double*)cv.take(b64);
+    P->cp1 = (double*)cv.take(b64);
+    P->cq = (double*)cv.take(b64);
+  }
+  if (o.method == POISSON_MG || o.method == POISSON_MG_IR32) {
+    P->mg32 = o.method == POISSON_MG_IR32;
+    const size_t es = P->mg32 ? sizeof(float) : sizeof(double);
+    P->lv.clear();
+    int nl = n;
+    double hl = h;
+    bool first = true;
+    while (true) {
+      Level L;
+      L.G = make_geom(nl, g.ghost, P->C, hl);
+      if (first && !P->mg32) {
+        L.phi = P->phi64;
+        L.f = P->f64;
+        L.tmp = P->t64;
+      } else {
+        L.phi = cv.take(es * L.G.total());
+        L.f = cv.take(es * L.G.total());
+        L.tmp = (nl == o.coarsest) ? nullptr : cv.take(es * L.G.total());
+      }
+      P->lv.push_back(L);
+      first = false;
+      if (nl == o.coarsest) break;
+      nl /= 2;
+      hl *= 2.0;
+    }
+    const int E = o.coarsest - 1;
+    P->ncoarse = E * E * E;
+    P->cinv = (double*)cv.take(sizeof(double) * (size_t)P->ncoarse * P->ncoarse);
+  }
+}
+
+// Dense matrix of L_h on the (E)^3 unknowns of a level with zero ghosts
+// (7-point or 19-point star), inverted through a Cholesky factorisation of
+// the SPD matrix -L_h.  Returns false if the factorisation fails.
+bool coarse_inverse(int nc, double h, int order, std::vector<double>& inv) {
+  const int E = nc - 1;
+  const int N = E * E * E;
+  std::vector<double> A((size_t)N * N, 0.0);
+  const double ih2 = 1.0 / (h * h);
+  const double w[4] = {-49.0 / 18.0, 1.5, -3.0 / 20.0, 1.0 / 90.0};
+  auto id = [&](int i, int j, int k) { return (k * E + j) * E + i; };
+  for (int k = 0; k < E; ++k)
+    for (int j = 0; j < E; ++j)
+      for (int i = 0; i < E; ++i) {
+        const int row = id(i, j, k);
+        // -L: SPD
+        if (order == 2) {
+          A[(size_t)row * N + row] = 6.0 * ih2;
+          const int di[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+          for (auto& d : di) {
+            const int a = i + d[0], b = j + d[1], c = k + d[2];
+            if (a >= 0 && a < E && b >= 0 && b < E && c >= 0 && c < E) A[(size_t)row * N + id(a, b, c)] -= ih2;
+          }
+        } else {
+          A[(size_t)row * N + row] = -3.0 * w[0] * ih2;
+          for (int q = 1; q <= 3; ++q) {
+            const int di[6][3] = {{q, 0, 0}, {-q, 0, 0}, {0, q, 0}, {0, -q, 0}, {0, 0, q}, {0, 0, -q}};
+            for (auto& d : di) {
+              const int a = i + d[0], b = j + d[1], c = k + d[2];
+              if (a >= 0 && a < E && b >= 0 && b < E && c >= 0 && c < E)
+                A[(size_t)row * N + id(a, b, c)] -= w[q] * ih2;
+            }
+          }
+        }
+      }
+  // Cholesky A = U^T U (upper), in place
+  std::vector<double> U = A;
+  for (int i = 0; i < N; ++i) {
+    for (int k = 0; k < i; ++k) {
+      const double f = U[(size_t)k * N + i];
+      if (f == 0.0) continue;
+      for (int j = i; j < N; ++j) U[(size_t)i * N + j] -= f * U[(size_t)k * N + j];
+    }
+    const double d = U[(size_t)i * N + i];
+    if (!(d > 0.0)) return false;
+    const double s = 1.0 / sqrt(d);
+    for (int j = i; j < N; ++j) U[(size_t)i * N + j] *= s;
+  }
+  // inverse of -L: solve U^T U x = e_c for every column, then negate
+  inv.assign((size_t)N * N, 0.0);
+  std::vector<double> y(N);
+  for (int c = 0; c < N; ++c) {
+    for (int i = 0; i < N; ++i) {
+      double s = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) s -= U[(size_t)k * N + i] * y[k];
+      y[i] = s / U[(size_t)i * N + i];
+    }
+    for (int i = N - 1; i >= 0; --i) {
+      double s = y[i];
+      for (int k = i + 1; k < N; ++k) s -= U[(size_t)i * N + k] * y[k];
+      y[i] = s / U[(size_t)i * N + i];
+    }
+    for (int r = 0; r < N; ++r) inv[(size_t)r * N + c] = -y[r];
+  }
+  return true;
+}
+
+// ------------------------------------------------------------ solver pieces
+void vcycle(poisson_plan_s* P, int l, hipStream_t st) {
+  Level& L = P->lv[l];
+  const bool f32 = P->mg32;
+  const poisson_opts_t& o = P->opts;
+  if (l + 1 == (int)P->lv.size()) {
+    coarse_solve(P->cinv, L.f, L.phi, f32, L.G, st);
+    return;
+  }
+  for (int s = 0; s < o.nu1; ++s)
+    for (int c = 0; c < P->C; ++c) colour_pass(L.phi, L.f, f32, L.G, P->order, c, 1.0, st);
+  residual(L.phi, L.f, f32, L.tmp, f32, L.G, P->order, false, nullptr, st);
+  Level& Lc = P->lv[l + 1];
+  restrict_fw(L.tmp, L.G, Lc.f, Lc.G, f32, st);
+  zero_unknowns(Lc.phi, f32, Lc.G, st);
+  vcycle(P, l + 1, st);
+  prolong_add(Lc.phi, Lc.G, L.phi, L.G, f32, st);
+  for (int s = 0; s < o.nu2; ++s)
+    for (int c = P->C - 1; c >= 0; --c) colour_pass(L.phi, L.f, f32, L.G, P->order, c, 1.0, st);
+}
+
+// One multigrid iteration followed by the fine residual norm into
+// scal->v[kRes2].  MG: a V-cycle on (phi64; f64).  MG_IR32: the FP32
+// V-cycle for the correction e of the current FP32 residual r32, phi64 += e,
+// and the new FP64 residual, stored as FP32 for the next step.
+void mg_step(poisson_plan_s* P, hipStream_t st) {
+  const int nb = residual_blocks(P->G0);
+  if (P->mg32) {
+    Level& L0 = P->lv[0];
+    zero_unknowns(L0.phi, true, L0.G, st);
+    vcycle(P, 0, st);
+    add_correction(P->phi64, L0.phi, true, P->G0, st);
+    residual(P->phi64, P->f64, false, L0.f, true, P->G0, P->order, false, P->partial, st);
+  } else {
+    vcycle(P, 0, st);
+    residual(P->phi64, P->f64, false, nullptr, false, P->G0, P->order, false, P->partial, st);
+  }
+  finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
+}
+
+int capture_step(poisson_plan_s* P) {
+  if (P->step_exec) return POISSON_OK;
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
+  mg_step(P, P->cap);
+  hipError_t e = hipStreamEndCapture(P->cap, &graph);
+  if (e != hipSuccess) {
+    set_error("graph capture failed: %s", hipGetErrorString(e));
+    return POISSON_EHIP;
+  }
+  e = hipGraphInstantiate(&P->step_exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    P->step_exec = nullptr;
+    set_error("graph instantiation failed: %s", hipGetErrorString(e));
+    return POISSON_EHIP;
+  }
+  return POISSON_OK;
+}
+
+int read_scalars(poisson_plan_s* P, int first, int count) {
+  HIPCHK(hipMemcpyAsync(P->host, &P->scal->v[first], sizeof(double) * count, hipMemcpyDeviceToHost, P->st));
+  HIPCHK(hipStreamSynchronize(P->st));
+  return POISSON_OK;
+}
+
+double rjac(const poisson_plan_s* P) { return cos(M_PI / P->grid.n[0]); }
+
+int do_multipole(poisson_plan_s* P, const double* rho, double* phi, int lmax, double* h_q) {
+  const poisson_grid_t& g = P->grid;
+  const int nq = (lmax + 1) * (lmax + 1);
+  const double G = P->opts.four_pi_G / (4.0 * M_PI);
+  hipStream_t st = P->st;
+  if (!P->sph) {
+    const int n = g.n[0];
+    const double h = (g.hi[0] - g.lo[0]) / n;
+    const double cx = 0.5 * (g.lo[0] + g.hi[0]), cy = 0.5 * (g.lo[1] + g.hi[1]), cz = 0.5 * (g.lo[2] + g.hi[2]);
+    cart_moments(rho, g.pitch[0], g.pitch[1], n, g.ghost, h, cx, cy, cz, lmax, P->partial, st);
+    finish_moments(P->partial, nq, P->opts.point_mass, P->qlm, st);
+    cart_ghosts(phi, g.pitch[0], g.pitch[1], n, g.ghost, h, g.lo[0], cx, cy, cz, lmax, P->qlm, G, st);
+  } else {
+    sph_moments(rho, P->S, lmax, false, P->partial, st);
+    finish_moments(P->partial, nq, P->opts.point_mass, P->qlm, st);
+    sph_moments(rho, P->S, lmax, true, P->partial, st);
+    finish_moments(P->partial, nq, 0.0, P->qlm + kNqMax, st);
+    sph_ghosts(phi, P->S, lmax, P->qlm, P->qlm + kNqMax, P->opts.point_mass, G, st);
+  }
+  CHK(launch_check("multipole_boundary"));
+  if (h_q) {
+    HIPCHK(hipMemcpyAsync(h_q, P->qlm, sizeof(double) * nq, hipMemcpyDeviceToHost, st));
+    if (P->sph) HIPCHK(hipMemcpyAsync(h_q + nq, P->qlm + kNqMax, sizeof(double) * nq, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return POISSON_OK;
+}
+
+struct Tracker {
+  poisson_stats_t* stats;
+  double bnorm = 0.0;
+  void push(double rel) {
+    if (stats && stats->residual_history && stats->history_len < stats->history_cap)
+      stats->residual_history[stats->history_len++] = rel;
+  }
+};
+
+int finish_status(poisson_plan_s* P, Tracker& T, int it, double rel, bool converged, float t_mp, float t_it) {
+  const int status = converged ? POISSON_OK : POISSON_WARN_MAXITER;
+  if (T.stats) {
+    T.stats->iterations = it;
+    T.stats->status = status;
+    T.stats->rel_residual = rel;
+    T.stats->b_norm = T.bnorm;
+    T.stats->rate = (it > 0 && rel > 0.0) ? pow(rel, 1.0 / it) : 0.0;
+    T.stats->t_multipole_ms = t_mp;
+    T.stats->t_iter_ms = t_it;
+  }
+  (void)P;
+  return status;
+}
+
+double rel_of(double r2, double bnorm) {
+  const double r = sqrt(std::max(r2, 0.0));
+  return bnorm > 0.0 ? r / bnorm : r;
+}
+
+// ------------------------------------------------------------ Cartesian solve
+int solve_cart(poisson_plan_s* P, const double* rho, double* phi, double tol, poisson_stats_t* stats) {
+  const poisson_grid_t& g = P->grid;
+  const poisson_opts_t& o = P->opts;
+  hipStream_t st = P->st;
+  Tracker T{stats};
+  if (stats) stats->history_len = 0;
+  HIPCHK(hipEventRecord(P->ev[0], st));
+  if (o.lmax >= 0) CHK(do_multipole(P, rho, phi, o.lmax, nullptr));
+  HIPCHK(hipEventRecord(P->ev[1], st));
+  const Geom& G = P->G0;
+  split_from_natural(phi, g.pitch[0], g.pitch[1], P->phi64, false, G, 1.0, st);
+  split_from_natural(rho, g.pitch[0], g.pitch[1], P->f64, false, G, o.four_pi_G, st);
+  const int nb = residual_blocks(G);
+  residual(P->phi64, P->f64, false, nullptr, false, G, P->order, true, P->partial, st);
+  finish_sum(P->partial, nb, 1, P->scal, kBnorm2, st);
+  // initial residual (MG_IR32 keeps it as the FP32 right-hand side; CG keeps it)
+  void* rout = nullptr;
+  bool rout32 = false;
+  if (o.method == POISSON_MG_IR32) {
+    rout = P->lv[0].f;
+    rout32 = true;
+  } else if (o.method == POISSON_CG) {
+    rout = P->cr;
+  }
+  residual(P->phi64, P->f64, false, rout, rout32, G, P->order, false, P->partial, st);
+  finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
+  CHK(launch_check("solve setup"));
+  CHK(read_scalars(P, kBnorm2, 2));
+  T.bnorm = sqrt(P->host[0]);
+  double rel = rel_of(P->host[1], T.bnorm);
+  T.push(rel);
+  if (!isfinite(rel)) {
+    set_error("non-finite initial residual (NaN/Inf in rho or phi)");
+    return POISSON_ENUMERIC;
+  }
+  int it = 0;
+  bool conv = rel <= tol;
+  if (o.method == POISSON_SOR) {
+    const double rj = rjac(P);
+    double w_opt = 2.0 / (1.0 + sqrt(1.0 - rj * rj));
+    if (o.omega_mode == POISSON_OMEGA_OPT_A) w_opt = 2.0 / (1.0 + M_PI / g.n[0]);
+    if (o.omega_mode == POISSON_OMEGA_FIXED) w_opt = o.omega;
+    double wc = 1.0 / (1.0 - rj * rj / 2.0);  // Chebyshev sequence from n = 1
+    while (!conv && it < o.max_iter) {
+      for (int c = 0; c < 2; ++c) {
+        double w = w_opt;
+        if (o.omega_mode == POISSON_OMEGA_CHEBYSHEV) {
+          w = wc;
+          wc = 1.0 / (1.0 - rj * rj * wc / 4.0);
+        }
+        colour_pass(P->phi64, P->f64, false, G, 2, c, w, st);
+      }
+      ++it;
+      if (it % o.check_every == 0 || it == o.max_iter) {
+        residual(P->phi64, P->f64, false, nullptr, false, G, 2, false, P->partial, st);
+        finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
+        CHK(launch_check("SOR"));
+        CHK(read_scalars(P, kRes2, 1));
+        rel = rel_of(P->host[0], T.bnorm);
+        T.push(rel);
+        if (!isfinite(rel)) {
+          set_error("SOR diverged (non-finite residual)");
+          return POISSON_ENUMERIC;
+        }
+        conv = rel <= tol;
+      }
+    }
+  } else if (o.method == POISSON_CG) {
+    const int cb = cg_blocks(G);
+    // rr = r.r ; beta = 0 ; p_old = 0
+    finish_sum(P->partial, nb, 1, P->scal, kRR, st);
+    const double zero = 0.0;
+    HIPCHK(hipMemcpyAsync(&P->scal->v[2], &zero, sizeof(double), hipMemcpyHostToDevice, st));
+    fill_zero(P->cp0, false, G.total(), st);
+    double* pold = P->cp0;
+    double* pnew = P->cp1;
+    while (!conv && it < o.max_iter) {
+      cg_direction_apply(P->cr, pold, pnew, P->cq, G, P->order, P->scal, P->partial, st);
+      cg_scalars(P->partial, cb, P->scal, 0, st);
+      cg_update(P->phi64, P->cr, pnew, P->cq, G, P->scal, P->partial, st);
+      cg_scalars(P->partial, cb, P->scal, 1, st);
+      std::swap(pold, pnew);
+      ++it;
+      if (it % o.check_every == 0 || it == o.max_iter) {
+        CHK(launch_check("CG"));
+        CHK(read_scalars(P, kRR, 1));
+        rel = rel_of(P->host[0], T.bnorm);
+        T.push(rel);
+        if (!isfinite(rel)) {
+          set_error("CG breakdown (non-finite residual)");
+          return POISSON_ENUMERIC;
+        }
+        conv = rel <= tol;
+      }
+    }
+  } else {  // multigrid
+    CHK(capture_step(P));
+    while (!conv && it < o.max_iter) {
+      HIPCHK(hipGraphLaunch(P->step_exec, st));
+      ++it;
+      if (it % o.check_every == 0 || it == o.max_iter) {
+        CHK(read_scalars(P, kRes2, 1));
+        rel = rel_of(P->host[0], T.bnorm);
+        T.push(rel);
+        if (!isfinite(rel)) {
+          set_error("multigrid diverged (non-finite residual)");
+          return POISSON_ENUMERIC;
+        }
+        conv = rel <= tol;
+      }
+    }
+  }
+  merge_to_natural(P->phi64, phi, g.pitch[0], g.pitch[1], G, true, 1.0, st);
+  HIPCHK(hipEventRecord(P->ev[2], st));
+  CHK(launch_check("solve"));
+  HIPCHK(hipEventSynchronize(P->ev[2]));
+  float t_mp = 0.f, t_it = 0.f;
+  HIPCHK(hipEventElapsedTime(&t_mp, P->ev[0], P->ev[1]));
+  HIPCHK(hipEventElapsedTime(&t_it, P->ev[1], P->ev[2]));
+  return finish_status(P, T, it, rel, conv, t_mp, t_it);
+}
+
+// ------------------------------------------------------------ spherical solve
+int solve_sph(poisson_plan_s* P, const double* rho, double* phi, double tol, poisson_stats_t* stats) {
+  const poisson_opts_t& o = P->opts;
+  hipStream_t st = P->st;
+  const SGeom& S = P->S;
+  Tracker T{stats};
+  if (stats) stats->history_len = 0;
+  HIPCHK(hipEventRecord(P->ev[0], st));
+  if (o.lmax >= 0) CHK(do_multipole(P, rho, phi, o.lmax, nullptr));
+  HIPCHK(hipEventRecord(P->ev[1], st));
+  const int nb = sph_blocks(S);
+  sph_residual(phi, rho, nullptr, S, P->sc, o.four_pi_G, true, P->partial, st);
+  finish_sum(P->partial, nb, 1, P->scal, kBnorm2, st);
+  sph_residual(phi, rho, P->sr, S, P->sc, o.four_pi_G, false, P->partial, st);
+  finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
+  CHK(launch_check("spherical setup"));
+  CHK(read_scalars(P, kBnorm2, 2));
+  T.bnorm = sqrt(P->host[0]);
+  double rel = rel_of(P->host[1], T.bnorm);
+  T.push(rel);
+  if (!isfinite(rel)) {
+    set_error("non-finite initial residual (NaN/Inf in rho or phi)");
+    return POISSON_ENUMERIC;
+  }
+  int it = 0;
+  bool conv = rel <= tol;
+  int restarts = 0;
+  auto restart = [&]() -> int {
+    // rhat = r, rho = r.r, alpha = omega = 1, beta = 0, p = v = 0
+    sph_copy(P->sr, P->srh, S, st);
+    double init[4] = {P->host[0], 1.0, 1.0, 0.0};
+    HIPCHK(hipMemcpyAsync(P->scal->v, init, sizeof init, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return POISSON_OK;
+  };
+  if (!conv) {
+    P->host[0] = P->host[1];
+    CHK(restart());
+  }
+  int cur = 0;
+  while (!conv && it < o.max_iter) {
+    const int nxt = cur ^ 1;
+    bicg_p_v(P->sr, P->sp[cur], P->sv[cur], P->sp[nxt], P->sv[nxt], P->srh, S, P->sc, P->scal, P->partial, st);
+    bicg_scalars(P->partial, nb, P->scal, 0, st);
+    bicg_s_t(P->sr, P->sv[nxt], P->ss, P->stt, S, P->sc, P->scal, P->partial, st);
+    bicg_scalars(P->partial, nb, P->scal, 1, st);
+    bicg_xr(phi, P->sr, P->sp[nxt], P->ss, P->stt, P->srh, S, P->scal, P->partial, st);
+    bicg_scalars(P->partial, nb, P->scal, 2, st);
+    cur = nxt;
+    ++it;
+    if (it % o.check_every == 0 || it == o.max_iter) {
+      CHK(launch_check("BiCGSTAB"));
+      CHK(read_scalars(P, 0, 8));
+      const double rr = P->host[7];
+      rel = rel_of(rr, T.bnorm);
+      T.push(rel);
+      if (!isfinite(rel)) {
+        set_error("BiCGSTAB breakdown (non-finite residual)");
+        return POISSON_ENUMERIC;
+      }
+      conv = rel <= tol;
+      // breakdown: rho or omega vanishing relative to the residual
+      const double rho_ = P->host[0], om = P->host[2];
+      if (!conv && (fabs(rho_) < 1e-30 * rr || om == 0.0)) {
+        if (++restarts > 8) {
+          set_error("BiCGSTAB breakdown persisted after restarts");
+          return POISSON_ENUMERIC;
+        }
+        sph_fill_zero(P->sp[cur], S, st);
+        sph_fill_zero(P->sv[cur], S, st);
+        P->host[0] = rr;
+        CHK(restart());
+      }
+    }
+  }
+  HIPCHK(hipEventRecord(P->ev[2], st));
+  HIPCHK(hipEventSynchronize(P->ev[2]));
+  float t_mp = 0.f, t_it = 0.f;
+  HIPCHK(hipEventElapsedTime(&t_mp, P->ev[0], P->ev[1]));
+  HIPCHK(hipEventElapsedTime(&t_it, P->ev[1], P->ev[2]));
+  return finish_status(P, T, it, rel, conv, t_mp, t_it);
+}
+
+bool same_grid(const poisson_grid_t* a, const poisson_grid_t* b) {
+  if (a->coord != b->coord || a->ghost != b->ghost) return false;
+  for (int d = 0; d < 3; ++d)
+    if (a->n[d] != b->n[d] || a->lo[d] != b->lo[d] || a->hi[d] != b->hi[d]) return false;
+  return a->pitch[0] == b->pitch[0] && a->pitch[1] == b->pitch[1];
+}
+
+}  // namespace
+
+// ============================================================ C ABI
+extern "C" {
+
+void poisson_default_opts(poisson_opts_t* o, int32_t method) {
+  if (!o) return;
+  memset(o, 0, sizeof *o);
+  o->method = method;
+  o->order = 2;
+  o->lmax = 8;
+  o->nu1 = 2;
+  o->nu2 = 2;
+  o->coarsest = 8;
+  o->omega_mode = POISSON_OMEGA_OPT;
+  o->max_iter = 10000;
+  o->check_every = 1;
+  o->omega = 1.0;
+  o->four_pi_G = 1.0;
+  o->point_mass = 0.0;
+}
+
+size_t poisson_workspace_bytes(const poisson_grid_t* grid, const poisson_opts_t* opts) {
+  if (validate(grid, opts) != POISSON_OK) return 0;
+  poisson_plan_s P;
+  P.grid = *grid;
+  P.opts = *opts;
+  P.sph = grid->coord == POISSON_SPHERICAL_LOG;
+  P.order = opts->order;
+  P.C = opts->order == 6 ? 4 : 2;
+  Carver cv(nullptr);
+  carve(&P, cv);
+  return cv.off + 256;
+}
+
+int poisson_plan(poisson_plan_t* out, const poisson_grid_t* grid, const poisson_opts_t* opts, void* d_workspace,
+                 size_t ws_bytes, void* stream) {
+  if (!out) {
+    set_error("null plan output");
+    return POISSON_EINVAL;
+  }
+  CHK(validate(grid, opts));
+  const size_t need = poisson_workspace_bytes(grid, opts);
+  if (!d_workspace || ws_bytes < need) {
+    set_error("workspace of %zu bytes given, %zu needed", ws_bytes, need);
+    return POISSON_EWORKSPACE;
+  }
+  if (((uintptr_t)d_workspace & 255u) != 0) {
+    set_error("workspace must be 256-byte aligned");
+    return POISSON_EWORKSPACE;
+  }
+  poisson_plan_s* P = new poisson_plan_s();
+  P->grid = *grid;
+  P->opts = *opts;
+  P->st = (hipStream_t)stream;
+  P->sph = grid->coord == POISSON_SPHERICAL_LOG;
+  P->order = opts->order;
+  P->C = opts->order == 6 ? 4 : 2;
+  Carver cv(d_workspace);
+  carve(P, cv);
+  int status = POISSON_OK;
+  auto fail = [&](int s) {
+    poisson_plan_destroy(P);
+    return s;
+  };
+  if (hipHostMalloc((void**)&P->host, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    set_error("pinned host allocation failed");
+    P->host = nullptr;
+    return fail(POISSON_EHIP);
+  }
+  for (int i = 0; i < 3; ++i)
+    if (hipEventCreate(&P->ev[i]) != hipSuccess) {
+      set_error("event creation failed");
+      return fail(POISSON_EHIP);
+    }
+  if (hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess) {
+    set_error("stream creation failed");
+    P->cap = nullptr;
+    return fail(POISSON_EHIP);
+  }
+  hipStream_t st = P->st;
+  // zero the whole workspace once: ghosts of correction and direction
+  // vectors must stay zero and are never written afterwards
+  fill_zero(d_workspace, false, (long long)(need / sizeof(double)), st);
+  if (P->sph) {
+    const poisson_grid_t& g = *grid;
+    SGeom& S = P->S;
+    S.nr = g.n[0];
+    S.nth = g.n[1];
+    S.nph = g.n[2];
+    S.p0 = g.pitch[0];
+    S.p1 = g.pitch[1];
+    S.r_min = g.lo[0];
+    S.ds = log(g.hi[0] / g.lo[0]) / (S.nr - 1);
+    S.dth = M_PI / S.nth;
+    S.dph = 2.0 * M_PI / S.nph;
+    std::vector<double> cot(S.nth), isin2(S.nth), r2(S.nr + 2);
+    for (int j = 0; j < S.nth; ++j) {
+      const double th = (j + 0.5) * S.dth;
+      cot[j] = cos(th) / sin(th) / (2.0 * S.dth);
+      isin2[j] = 1.0 / (sin(th) * sin(th));
+    }
+    for (int i = 0; i < S.nr + 2; ++i) {
+      const double r = S.r_min * exp((i - 1) * S.ds);
+      r2[i] = r * r;
+    }
+    if (hipMemcpyAsync((void*)P->sc.cot, cot.data(), sizeof(double) * S.nth, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync((void*)P->sc.isin2, isin2.data(), sizeof(double) * S.nth, hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync((void*)P->sc.r2, r2.data(), sizeof(double) * (S.nr + 2), hipMemcpyHostToDevice, st) !=
+            hipSuccess) {
+      set_error("upload of spherical coefficients failed");
+      return fail(POISSON_EHIP);
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) {
+      set_error("stream synchronisation failed");
+      return fail(POISSON_EHIP);
+    }
+  } else if (!P->lv.empty()) {
+    const Level& Lc = P->lv.back();
+    std::vector<double> inv;
+    if (!coarse_inverse(Lc.G.n, Lc.G.h, P->order, inv)) {
+      set_error("coarsest-level factorisation failed");
+      return fail(POISSON_ENUMERIC);
+    }
+    if (hipMemcpyAsync(P->cinv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      set_error("upload of the coarsest inverse failed");
+      return fail(POISSON_EHIP);
+    }
+  }
+  status = launch_check("poisson_plan");
+  if (status == POISSON_OK && hipStreamSynchronize(st) != hipSuccess) {
+    set_error("stream synchronisation failed");
+    status = POISSON_EHIP;
+  }
+  if (status != POISSON_OK) return fail(status);
+  *out = P;
+  return POISSON_OK;
+}
+
+void poisson_plan_destroy(poisson_plan_t P) {
+  if (!P) return;
+  if (P->step_exec) hipGraphExecDestroy(P->step_exec);
+  for (int i = 0; i < 3; ++i)
+    if (P->ev[i]) hipEventDestroy(P->ev[i]);
+  if (P->cap) hipStreamDestroy(P->cap);
+  if (P->host) hipHostFree(P->host);
+  delete P;
+}
+
+int multipole_boundary(poisson_plan_t P, const double* d_rho, double* d_phi, int32_t lmax, double* h_q) {
+  if (!P || !d_rho || !d_phi) {
+    set_error("null argument");
+    return POISSON_EINVAL;
+  }
+  if (lmax < 0 || lmax > kLmaxMax) {
+    set_error("lmax must be in 0..%d", kLmaxMax);
+    return POISSON_EINVAL;
+  }
+  return do_multipole(P, d_rho, d_phi, lmax, h_q);
+}
+
+int poisson_solve(poisson_plan_t P, const double* d_rho, double* d_phi, const poisson_grid_t* grid, double tol,
+                  poisson_stats_t* stats) {
+  if (!P || !d_rho || !d_phi || !grid) {
+    set_error("null argument");
+    return POISSON_EINVAL;
+  }
+  if (!(tol > 0.0)) {
+    set_error("tol must be positive");
+    return POISSON_EINVAL;
+  }
+  if (!same_grid(grid, &P->grid)) {
+    set_error("grid differs from the plan's grid");
+    return POISSON_EGRID;
+  }
+  int s = P->sph ? solve_sph(P, d_rho, d_phi, tol, stats) : solve_cart(P, d_rho, d_phi, tol, stats);
+  if (stats && s < 0) stats->status = s;
+  return s;
+}
+
+const char* poisson_strerror(int s) {
+  switch (s) {
+    case POISSON_OK: return "converged";
+    case POISSON_WARN_MAXITER: return "tolerance not reached within max_iter";
+    case POISSON_EINVAL: return "invalid argument";
+    case POISSON_EGRID: return "grid unsuited to the method";
+    case POISSON_EWORKSPACE: return "workspace missing, too small or misaligned";
+    case POISSON_EHIP: return "HIP runtime error";
+    case POISSON_ENUMERIC: return "non-finite residual or breakdown";
+    case POISSON_EADMIT: return "request exceeds the memory budget";
+    default: return "unknown status";
+  }
+}
+
+const char* poisson_last_error(void) { return g_err; }
+
+// ------------------------------------------------------------ single operators
+static int need_cart(poisson_plan_t P) {
+  if (!P) {
+    set_error("null plan");
+    return POISSON_EINVAL;
+  }
+  if (P->sph) {
+    set_error("operation defined on Cartesian plans only");
+    return POISSON_EINVAL;
+  }
+  return POISSON_OK;
+}
+
+int poisson_op_apply(poisson_plan_t P, const double* d_phi, double* d_out) {
+  if (!P || !d_phi || !d_out) {
+    set_error("null argument");
+    return POISSON_EINVAL;
+  }
+  hipStream_t st = P->st;
+  if (P->sph) {
+    sph_apply(d_phi, d_out, P->S, P->sc, st);
+    return launch_check("poisson_op_apply");
+  }
+  const poisson_grid_t& g = P->grid;
+  split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);
+  fill_zero(P->f64, false, P->G0.total(), st);
+  residual(P->phi64, P->f64, false, P->t64, false, P->G0, P->order, false, nullptr, st);
+  merge_to_natural(P->t64, d_out, g.pitch[0], g.pitch[1], P->G0, true, -1.0, st);
+  return launch_check("poisson_op_apply");
+}
+
+int poisson_op_residual(poisson_plan_t P, const double* d_rho, const double* d_phi, double* d_res,
+                        double* h_norm2) {
+  if (!P || !d_rho || !d_phi || !d_res) {
+    set_error("null argument");
+    return POISSON_EINVAL;
+  }
+  hipStream_t st = P->st;
+  if (P->sph) {
+    sph_residual(d_phi, d_rho, d_res, P->S, P->sc, P->opts.four_pi_G, false, P->partial, st);
+    finish_sum(P->partial, sph_blocks(P->S), 1, P->scal, kRes2, st);
+  } else {
+    const poisson_grid_t& g = P->grid;
+    split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);
+    split_from_natural(d_rho, g.pitch[0], g.pitch[1], P->f64, false, P->G0, P->opts.four_pi_G, st);
+    residual(P->phi64, P->f64, false, P->t64, false, P->G0, P->order, false, P->partial, st);
+    finish_sum(P->partial, residual_blocks(P->G0), 1, P->scal, kRes2, st);
+    merge_to_natural(P->t64, d_res, g.pitch[0], g.pitch[1], P->G0, true, 1.0, st);
+  }
+  CHK(launch_check("poisson_op_residual"));
+  if (h_norm2) {
+    CHK(read_scalars(P, kRes2, 1));
+    *h_norm2 = P->host[0];
+  }
+  return POISSON_OK;
+}
+
+int poisson_op_smooth(poisson_plan_t P, const double* d_rho, double* d_phi, int32_t sweeps, int32_t forward,
+                      double omega) {
+  CHK(need_cart(P));
+  if (!d_rho || !d_phi || sweeps < 0) {
+    set_error("bad argument");
+    return POISSON_EINVAL;
+  }
+  if (P->order == 6 && omega != 1.0) {
+    set_error("the four-colour sweep is plain Gauss-Seidel (omega = 1)");
+    return POISSON_EINVAL;
+  }
+  hipStream_t st = P->st;
+  const poisson_grid_t& g = P->grid;
+  split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);
+  split_from_natural(d_rho, g.pitch[0], g.pitch[1], P->f64, false, P->G0, P->opts.four_pi_G, st);
+  for (int s = 0; s < sweeps; ++s)
+    for (int i = 0; i < P->C; ++i) {
+      const int c = forward ? i : P->C - 1 - i;
+      colour_pass(P->phi64, P->f64, false, P->G0, P->order, c, omega, st);
+    }
+  merge_to_natural(P->phi64, d_phi, g.pitch[0], g.pitch[1], P->G0, true, 1.0, st);
+  return launch_check("poisson_op_smooth");
+}
+
+int poisson_op_restrict(poisson_plan_t P, const double* d_fine, double* d_coarse) {
+  CHK(need_cart(P));
+  if (P->lv.size() < 2 || P->mg32) {
+    set_error("restriction needs an FP64 multigrid plan with at least two levels");
+    return POISSON_EINVAL;
+  }
+  hipStream_t st = P->st;
+  Level& L1 = P->lv[1];
+  dense_to_split(d_fine, P->t64, false, P->G0, st);
+  restrict_fw(P->t64, P->G0, L1.f, L1.G, false, st);
+  split_to_dense(L1.f, false, d_coarse, L1.G, st);
+  return launch_check("poisson_op_restrict");
+}
+
+int poisson_op_prolong_add(poisson_plan_t P, const double* d_coarse, double* d_fine) {
+  CHK(need_cart(P));
+  if (P->lv.size() < 2 || P->mg32) {
+    set_error("prolongation needs an FP64 multigrid plan with at least two levels");
+    return POISSON_EINVAL;
+  }
+  hipStream_t st = P->st;
+  Level& L1 = P->lv[1];
+  dense_to_split(d_coarse, L1.phi, false, L1.G, st);
+  dense_to_split(d_fine, P->t64, false, P->G0, st);
+  prolong_add(L1.phi, L1.G, P->t64, P->G0, false, st);
+  split_to_dense(P->t64, false, d_fine, P->G0, st);
+  return launch_check("poisson_op_prolong_add");
+}
+
+int poisson_op_vcycle(poisson_plan_t P, const double* d_rho, double* d_phi, int32_t cycles) {
+  CHK(need_cart(P));
+  if (P->lv.empty() || !d_rho || !d_phi || cycles < 0) {
+    set_error("V-cycles need a multigrid plan");
+    return POISSON_EINVAL;
+  }
+  hipStream_t st = P->st;
+  const poisson_grid_t& g = P->grid;
+  split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);
+  split_from_natural(d_rho, g.pitch[0], g.pitch[1], P->f64, false, P->G0, P->opts.four_pi_G, st);
+  if (P->mg32) residual(P->phi64, P->f64, false, P->lv[0].f, true, P->G0, P->order, false, nullptr, st);
+  for (int c = 0; c < cycles; ++c) mg_step(P, st);
+  merge_to_natural(P->phi64, d_phi, g.pitch[0], g.pitch[1], P->G0, true, 1.0, st);
+  return launch_check("poisson_op_vcycle");
+}
+
+int poisson_op_sweep_resident(poisson_plan_t P, int32_t sweeps) {
+  CHK(need_cart(P));
+  if (sweeps < 0) {
+    set_error("sweeps must be >= 0");
+    return POISSON_EINVAL;
+  }
+  void* phi = P->phi64;
+  const void* f = P->f64;
+  bool f32 = false;
+  if (!P->lv.empty()) {
+    phi = P->lv[0].phi;
+    f = P->lv[0].f;
+    f32 = P->mg32;
+  }
+  for (int s = 0; s < sweeps; ++s)
+    for (int c = 0; c < P->C; ++c) colour_pass(phi, f, f32, P->G0, P->order, c, 1.0, P->st);
+  return launch_check("poisson_op_sweep_resident");
+}
+
+}  // extern "C"

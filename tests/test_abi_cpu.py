@@ -1,0 +1,116 @@
+"""CPU checks of the C ABI: the library loads, exports every function the
+header declares, and validates grids / options on the host (no GPU work)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2605_03563_amd as pg
+from paper_2605_03563_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if not fn.endswith(".h"):
+            continue
+        text = open(os.path.join(inc, fn)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_library_exports_every_declared_function():
+    lib = L.load()
+    declared = _declared_functions()
+    assert "poisson_solve" in declared and "multipole_boundary" in declared and "poisson_plan" in declared
+    for name in declared:
+        assert hasattr(lib, name), f"{name} declared but not exported"
+        assert name in L.SIGNATURES, f"{name} has no ctypes signature"
+
+
+def test_struct_layouts_match_header_sizes():
+    assert C.sizeof(L.Grid) == 4 + 12 + 24 + 24 + 4 + 4 + 16
+    assert C.sizeof(L.Opts) == 10 * 4 + 3 * 8
+    assert C.sizeof(L.Stats) == 8 + 5 * 8 + 8 + 8
+
+
+def test_default_options_and_strerror():
+    o = pg.options("mg")
+    assert (o.order, o.lmax, o.nu1, o.nu2, o.coarsest) == (2, 8, 2, 2, 8)
+    lib = L.load()
+    assert lib.poisson_strerror(0) == b"converged"
+    assert b"max_iter" in lib.poisson_strerror(1)
+
+
+@pytest.mark.parametrize("n,ok", [(256, True), (64, True), (8, True), (96, False), (250, False)])
+def test_multigrid_grid_rule(n, ok):
+    """Multigrid needs n = 2^L * coarsest intervals (Section 2.1.3)."""
+    grid = pg.cart_grid(n)
+    opts = pg.options("mg")
+    nbytes = L.load().poisson_workspace_bytes(C.byref(grid), C.byref(opts))
+    assert (nbytes > 0) == ok
+    if not ok:
+        assert b"2^L" in L.load().poisson_last_error()
+
+
+def test_workspace_sizes_are_sane():
+    grid = pg.cart_grid(256)
+    nb = pg.workspace_bytes(grid, pg.options("mg"))
+    # three FP64 colour-split fine arrays dominate: ~3 * 257^2 * 2 * 160 * 8 bytes
+    assert 3 * 257 * 257 * 320 * 8 < nb < 5 * 257 * 257 * 320 * 8
+    nb32 = pg.workspace_bytes(grid, pg.options("mg_ir32"))
+    assert nb32 < 1.6 * nb
+    g19 = pg.cart_grid(512, ghost=3)
+    nb19 = pg.workspace_bytes(g19, pg.options("mg_ir32", order=6))
+    assert nb19 < 12e9
+
+
+@pytest.mark.parametrize("kw,err", [
+    (dict(order=4), "order"),
+    (dict(lmax=9), "lmax"),
+    (dict(max_iter=0), "max_iter"),
+    (dict(four_pi_G=0.0), "four_pi_G"),
+])
+def test_invalid_options_rejected(kw, err):
+    grid = pg.cart_grid(32)
+    opts = pg.options("cg", **kw)
+    assert L.load().poisson_workspace_bytes(C.byref(grid), C.byref(opts)) == 0
+    assert err.encode() in L.load().poisson_last_error()
+
+
+def test_ghost_layers_must_match_order():
+    assert L.load().poisson_workspace_bytes(C.byref(pg.cart_grid(32, ghost=1)),
+                                            C.byref(pg.options("cg", order=6))) == 0
+    assert L.load().poisson_workspace_bytes(C.byref(pg.cart_grid(32, ghost=3)),
+                                            C.byref(pg.options("cg", order=6))) > 0
+
+
+def test_pitch_and_spherical_checks():
+    g = pg.cart_grid(32, pitch_x=20)
+    assert L.load().poisson_workspace_bytes(C.byref(g), C.byref(pg.options("cg"))) == 0
+    s = pg.sph_grid(64, 32, 32)
+    assert L.load().poisson_workspace_bytes(C.byref(s), C.byref(pg.options("bicgstab"))) > 0
+    assert L.load().poisson_workspace_bytes(C.byref(s), C.byref(pg.options("mg"))) == 0
+    s_odd = pg.sph_grid(64, 31, 32)
+    assert L.load().poisson_workspace_bytes(C.byref(s_odd), C.byref(pg.options("bicgstab"))) == 0
+
+
+def test_plan_rejects_small_or_misaligned_workspace_before_any_device_call():
+    lib = L.load()
+    grid = pg.cart_grid(32)
+    opts = pg.options("cg")
+    h = C.c_void_p()
+    need = lib.poisson_workspace_bytes(C.byref(grid), C.byref(opts))
+    st = lib.poisson_plan(C.byref(h), C.byref(grid), C.byref(opts), C.c_void_p(0x100000), need - 1, None)
+    assert st == L.EWORKSPACE
+    st = lib.poisson_plan(C.byref(h), C.byref(grid), C.byref(opts), C.c_void_p(0x100010), need, None)
+    assert st == L.EWORKSPACE
+    st = lib.poisson_plan(C.byref(h), C.byref(grid), C.byref(opts), None, need, None)
+    assert st == L.EWORKSPACE
+    assert h.value is None

@@ -1,0 +1,164 @@
+"""Converged parity of every solver path against the oracle's exact discrete
+solution (relative L2 error <= 1e-10 once the residual is driven to round-off
+level), error paths, and determinism."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2605_03563_amd as pg
+from oracle import analytic as OA
+from oracle import direct as OD
+from oracle import multipole as OM
+from tests.gpu_util import dev, host, rel_l2, say
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+CONV_TOL = 1e-10   # converged parity bar (relative L2 potential error)
+
+
+def _oracle_cart(rho, n, g, order, lmax):
+    ghost, _ = OM.cart_boundary(rho, n, g, lmax)
+    return OD.solve_cart(ghost, rho, n, 1.0 / n, order, g)
+
+
+def _solve(n, g, method, order, rho, lmax, tol, **kw):
+    plan = pg.Plan(pg.cart_grid(n, ghost=g), pg.options(method, order=order, lmax=lmax, **kw))
+    phi = torch.zeros(rho.shape, dtype=torch.float64, device="cuda:0")
+    res = plan.solve(dev(rho), phi, tol=tol, history=4096)
+    return host(phi), res
+
+
+@pytest.mark.parametrize("method,kw", [("sor", {}), ("sor", {"omega_mode": pg.OMEGA_CHEBYSHEV}),
+                                       ("cg", {})])
+def test_c1_uniform_sphere(method, kw):
+    say(f"C1 32^3 uniform sphere {method} {kw}")
+    n, g, lmax = 32, 1, 4
+    wl = W.config_c1()
+    rho = wl.rho.numpy()
+    phi, res = _solve(n, g, method, 2, rho, lmax, 1e-13, **kw)
+    assert res.converged, res
+    ref = _oracle_cart(rho, n, g, 2, lmax)
+    s = slice(1, n)
+    assert rel_l2(phi[s, s, s], ref[s, s, s]) < CONV_TOL
+    mask = OM.cart_ghost_mask(n, g)
+    assert np.max(np.abs(phi[mask] - ref[mask])) < 1e-12 * np.max(np.abs(ref[mask]))
+    # against the analytic potential (informational bar from the staircase sphere)
+    x = OM.cart_coords(n, g)[1:n]
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    ana = OA.uniform_sphere(np.stack([X, Y, Z], -1), (0.5, 0.5, 0.5), 0.25)
+    assert rel_l2(phi[s, s, s], ana) < 0.05
+    if method == "sor" and not kw:
+        # red-black 7-point SOR at omega_opt: asymptotic rate omega_opt - 1
+        hist = np.array(res.history)
+        rate = (hist[-1] / hist[-41]) ** (1 / 40)
+        assert rate < 0.83
+
+
+def test_c1_cg_iterations_grow_and_bound():
+    say("CG 1e-10 stop on C1: error bound kappa * rel")
+    n = 32
+    rho = W.config_c1().rho.numpy()
+    phi, res = _solve(n, 1, "cg", 2, rho, 4, 1e-10)
+    ref = _oracle_cart(rho, n, 1, 2, 4)
+    s = slice(1, n)
+    kappa = 1.0 / math.tan(math.pi / (2 * n)) ** 2
+    assert rel_l2(phi[s, s, s], ref[s, s, s]) <= kappa * 1e-10
+    assert 30 < res.iterations < 200
+
+
+@pytest.mark.parametrize("method", ["mg", "mg_ir32"])
+def test_c2_clumps_multigrid_reduced(method):
+    say(f"C2 reduced 64^3 {method}")
+    n, g = 64, 1
+    wl = W.config_c2(n=n)
+    rho = wl.rho.numpy()
+    phi, res = _solve(n, g, method, 2, rho, 8, 1e-13)
+    assert res.converged, res
+    assert res.iterations < 25
+    ref = _oracle_cart(rho, n, g, 2, 8)
+    s = slice(1, n)
+    assert rel_l2(phi[s, s, s], ref[s, s, s]) < CONV_TOL
+    if method == "mg":
+        assert res.rate < 0.15
+
+
+@pytest.mark.parametrize("method", ["mg", "mg_ir32"])
+def test_c3_star19_multigrid_reduced(method):
+    say(f"C3 reduced 32^3 19-point {method}")
+    n, g = 32, 3
+    wl = W.config_c3(n=n, n_clumps=8)
+    rho = wl.rho.numpy()
+    phi, res = _solve(n, g, method, 6, rho, 8, 1e-13)
+    assert res.converged, res
+    ref = _oracle_cart(rho, n, g, 6, 8)
+    s = slice(g, g + n - 1)
+    assert rel_l2(phi[s, s, s], ref[s, s, s]) < CONV_TOL
+
+
+def test_c4_spherical_bicgstab_reduced():
+    say("C4 reduced 32x16x16 BiCGSTAB")
+    nr, nth, nph = 32, 16, 16
+    wl = W.config_c4(nr=nr, nth=nth, nph=nph)
+    rho = wl.rho.numpy()
+    r, th, ph, ds = OM.sph_axes(nr, nth, nph)
+    mc = 4 * math.pi * 1e-3
+    plan = pg.Plan(pg.sph_grid(nr, nth, nph), pg.options("bicgstab", lmax=8, point_mass=mc, max_iter=4000))
+    phi = torch.zeros(rho.shape, dtype=torch.float64, device="cuda:0")
+    res = plan.solve(dev(rho), phi, tol=1e-12)
+    assert res.converged, res
+    ghost, _, _ = OM.sph_boundary(rho, nr, nth, nph, 8, point_mass=mc)
+    ref = OD.solve_sph(ghost, rho, r, ds, th)
+    got = host(phi)
+    assert rel_l2(got[:, :, 1:nr + 1], ref[:, :, 1:nr + 1]) < CONV_TOL
+    assert np.max(np.abs(got[:, :, [0, -1]] - ref[:, :, [0, -1]])) < 1e-12 * np.max(np.abs(ref[:, :, [0, -1]]))
+
+
+def test_c2_full_size_multigrid():
+    """255^3 unknowns, the benchmark's launch configuration: converged MG
+    solution against the DST oracle."""
+    say("C2 full size 256^3 FP64 MG")
+    n = 256
+    wl = W.config_c2(n=n)
+    rho = wl.rho.numpy()
+    phi, res = _solve(n, 1, "mg", 2, rho, 8, 1e-12)
+    assert res.converged, res
+    ref = _oracle_cart(rho, n, 1, 2, 8)
+    s = slice(1, n)
+    assert rel_l2(phi[s, s, s], ref[s, s, s]) < CONV_TOL
+
+
+def test_warm_start_and_determinism():
+    say("determinism + warm start")
+    n = 64
+    rho = W.config_c2(n=n).rho.numpy()
+    a, ra = _solve(n, 1, "mg_ir32", 2, rho, 8, 1e-8)
+    b, rb = _solve(n, 1, "mg_ir32", 2, rho, 8, 1e-8)
+    assert ra.iterations == rb.iterations
+    assert np.array_equal(a, b)
+    plan = pg.Plan(pg.cart_grid(n), pg.options("mg_ir32", lmax=8))
+    phi = dev(a)
+    res = plan.solve(dev(rho), phi, tol=1e-8)
+    assert res.iterations <= 1
+
+
+def test_error_paths():
+    say("error paths")
+    n = 32
+    rho = W.config_c1().rho.numpy()
+    phi, res = _solve(n, 1, "cg", 2, rho, 4, 1e-12, max_iter=1)
+    assert res.status == pg.WARN_MAXITER and res.iterations == 1
+    bad = rho.copy()
+    bad[10, 10, 10] = np.nan
+    with pytest.raises(pg.PoissonError) as e:
+        _solve(n, 1, "mg", 2, bad, 4, 1e-8)
+    assert e.value.status == -5
+    plan = pg.Plan(pg.cart_grid(n), pg.options("cg", lmax=4))
+    t = torch.zeros(rho.shape, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(pg.PoissonError) as e:
+        plan.solve(dev(rho), t, tol=0.0)
+    assert e.value.status == -1
+    # grid differs from the plan's grid
+    st = plan.lib.poisson_solve(plan.handle, pg._ptr(dev(rho)), pg._ptr(t), pg.cart_grid(16), 1e-8, None)
+    assert st == -2
