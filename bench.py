@@ -43,7 +43,35 @@ def parse():
     ap.add_argument("--cpu-multipole", action="store_true",
                     help="also time the oracle's multipole boundary (about 25 s at 255^3)")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="for hardware-counter runs: one solve to populate the arrays, then "
+                         "--sweeps resident smoother sweeps and one 1 GiB reference copy; "
+                         "prints no bench line")
+    ap.add_argument("--sweeps", type=int, default=10)
     return ap.parse_args()
+
+
+def kernels_only(args):
+    """Dispatch the dominant kernel and a copy kernel of known size so that
+    rocprofv3 counters (FETCH_SIZE, WRITE_SIZE) can be read per dispatch."""
+    import torch
+
+    import paper_2605_03563_amd as pg
+    import workloads as W
+
+    dev = "cuda:0"
+    wl = W.config_c2(n=args.n, device=dev)
+    rho = wl.rho.contiguous()
+    plan = pg.Plan(pg.cart_grid(args.n), pg.options("mg", lmax=8), device=dev)
+    phi = torch.zeros_like(rho)
+    plan.solve(rho, phi, tol=args.tol)
+    pg.sweep_resident(plan, args.sweeps)
+    a = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(f"kernels-only: {args.sweeps} sweeps = {2 * args.sweeps} colour passes, "
+          f"copy of {a.numel() * 8} bytes", flush=True)
 
 
 def traffic_from_profiles(kernel_tag: str):
@@ -103,6 +131,10 @@ def main():
         print("bench.py: this build measures one MI355X; --gpus above 1 is not supported "
               "(the multi-GPU sharding is a design note, not part of the build)", file=sys.stderr)
         sys.exit(2)
+
+    if args.kernels_only:
+        kernels_only(args)
+        return
 
     import torch
 
