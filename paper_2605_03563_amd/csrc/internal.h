@@ -82,9 +82,11 @@ void fill_zero(void* x, bool f32, long long count, hipStream_t st);
 void zero_unknowns(void* x, bool f32, const Geom& G, hipStream_t st);
 void copy_ghosts_split(const double* src, void* dst, bool dst_f32, const Geom& G, hipStream_t st);
 
-// one colour pass of Gauss-Seidel / SOR in place (order 2: 7-point, order 6: star)
+// one colour pass of Gauss-Seidel / SOR in place (order 2: 7-point, order 6:
+// star); colours whose bit is set in zmask are read as zero (first sweep on a
+// zero initial guess, which then needs no separate clearing pass)
 void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, int colour,
-                 double omega, hipStream_t st);
+                 double omega, hipStream_t st, int zmask = 0);
 
 // r = f - L phi on the unknowns (split in, split out or nullptr); partial sums
 // of r^2 go to partial[kReduceBlocks].  zero_unknowns_in treats the unknowns of

@@ -20,11 +20,18 @@ constexpr int KZ = 8;    // planes marched per thread
 // 19-point star weights (6th-order central second difference per axis)
 constexpr double kC0 = -49.0 / 18.0, kC1 = 1.5, kC2 = -3.0 / 20.0, kC3 = 1.0 / 90.0;
 
+// Planes marched per thread: KZ on large levels; one on small levels, where
+// parallelism rather than reuse along z hides the latency.
+inline int kz_for(const Geom& G) { return G.n >= 128 ? KZ : 1; }
+
 inline dim3 col_grid(const Geom& G) {
   const int mc = G.mhi() - G.mlo() + 1;
   const int E = G.n - 1;
-  return dim3((mc + BX - 1) / BX, (E + BY - 1) / BY, (E + KZ - 1) / KZ);
+  const int kz = kz_for(G);
+  return dim3((mc + BX - 1) / BX, (E + BY - 1) / BY, (E + kz - 1) / kz);
 }
+
+__device__ inline int planes_per_block(const Geom& G) { return (G.n - 1 + (int)gridDim.z - 1) / (int)gridDim.z; }
 
 inline dim3 node_grid(int M) { return dim3((M + BX - 1) / BX, (M + BY - 1) / BY, M); }
 
@@ -56,7 +63,16 @@ __device__ inline T lap_at(const T* __restrict__ X, const Geom& G, int a, int b,
 }
 
 // ---------------------------------------------------------------- colour passes
-template <typename T, bool SOR>
+template <typename T>
+__device__ inline void store_stream(T* p, T v) { __builtin_nontemporal_store(v, p); }
+
+// 7-point red-black pass of colour c.  The thread owns compact column m of
+// row b and marches planes k0..k1.  The other colour's value at compact m of
+// plane k is, for the node updated on plane k, one x-neighbour, and the
+// z-neighbour of the nodes updated on planes k-1 and k+1, so it is loaded
+// once and kept in registers (zm, zc, zp).  ZG: zero initial guess -- the
+// other colour is taken as 0 (first pass of a cycle on a zeroed correction).
+template <typename T, bool SOR, bool ZG>
 __global__ __launch_bounds__(256) void k_pass7(T* __restrict__ X, const T* __restrict__ F, Geom G, int c,
                                                T omega, T h2) {
   int bx, by, bz;
@@ -65,37 +81,57 @@ __global__ __launch_bounds__(256) void k_pass7(T* __restrict__ X, const T* __res
   const int b = G.g + by * BY + (int)threadIdx.y;
   const int last = G.g + G.n - 2;
   if (m > G.mhi() || b > last) return;
-  const int k0 = G.g + bz * KZ;
-  const int k1 = min(k0 + KZ - 1, last);
+  const int kz = planes_per_block(G);
+  const int k0 = G.g + bz * kz;
+  const int k1 = min(k0 + kz - 1, last);
   T* __restrict__ Xc = X + (long long)c * G.cs;
   const T* __restrict__ Xo = X + (long long)(c ^ 1) * G.cs;
   const T* __restrict__ Fc = F + (long long)c * G.cs;
   const T sixth = (T)(1.0 / 6.0);
+  const long long plane = (long long)G.M * G.W;
+  const T* __restrict__ col = Xo + G.row(b, 0) + m;
+  T zm = (T)0, zc = (T)0;
+  if (!ZG) {
+    zm = col[(k0 - 1) * plane];
+    zc = col[k0 * plane];
+  }
+#pragma unroll 4
   for (int k = k0; k <= k1; ++k) {
-    const int a = 2 * m + ((c - b - k - G.off) & 1);
-    if (!G.inner(a)) continue;
+    T zp = (T)0;
+    if (!ZG) zp = col[(k + 1) * plane];
+    const int r = (c - b - k - G.off) & 1;
+    const int a = 2 * m + r;
     const long long row = G.row(b, k);
-    const T s = Xo[row + ((a - 1) >> 1)] + Xo[row + ((a + 1) >> 1)] + Xo[G.row(b - 1, k) + m] +
-                Xo[G.row(b + 1, k) + m] + Xo[G.row(b, k - 1) + m] + Xo[G.row(b, k + 1) + m];
-    const T gs = (s - h2 * Fc[row + m]) * sixth;
-    if (SOR)
-      Xc[row + m] = ((T)1 - omega) * Xc[row + m] + omega * gs;
-    else
-      Xc[row + m] = gs;
+    if (G.inner(a)) {
+      T s = (T)0;
+      if (!ZG) s = zc + Xo[row + m - 1 + 2 * r] + Xo[row - G.W + m] + Xo[row + G.W + m] + zm + zp;
+      const T gs = (s - h2 * Fc[row + m]) * sixth;
+      if (SOR)
+        Xc[row + m] = ((T)1 - omega) * Xc[row + m] + omega * gs;
+      else
+        store_stream(Xc + row + m, gs);
+    }
+    zm = zc;
+    zc = zp;
   }
 }
 
+// four-colour pass of the 19-point star; colours whose bit is set in zmask
+// are taken as 0 (first forward sweep on a zeroed correction).
 template <typename T>
 __global__ __launch_bounds__(256) void k_pass19(T* __restrict__ X, const T* __restrict__ F, Geom G, int c,
-                                                T h2) {
+                                                T h2, int zmask) {
   int bx, by, bz;
   xcd_block(bx, by, bz);
   const int m = G.mlo() + bx * BX + (int)threadIdx.x;
   const int b = G.g + by * BY + (int)threadIdx.y;
   const int last = G.g + G.n - 2;
   if (m > G.mhi() || b > last) return;
-  const int k0 = G.g + bz * KZ;
-  const int k1 = min(k0 + KZ - 1, last);
+  const int kz = planes_per_block(G);
+  const int k0 = G.g + bz * kz;
+  const int k1 = min(k0 + kz - 1, last);
+  const bool z1 = (zmask >> ((c + 1) & 3)) & 1, z2 = (zmask >> ((c + 2) & 3)) & 1,
+             z3 = (zmask >> ((c + 3) & 3)) & 1;
   const T* __restrict__ X1 = X + (long long)((c + 1) & 3) * G.cs;  // colour c+1 (= c-3)
   const T* __restrict__ X2 = X + (long long)((c + 2) & 3) * G.cs;  // colour c+2 (= c-2)
   const T* __restrict__ X3 = X + (long long)((c + 3) & 3) * G.cs;  // colour c+3 (= c-1)
@@ -106,25 +142,33 @@ __global__ __launch_bounds__(256) void k_pass19(T* __restrict__ X, const T* __re
     const int a = 4 * m + ((c - b - k - G.off) & 3);
     if (!G.inner(a)) continue;
     const long long row = G.row(b, k);
-    const T s1 = X1[row + ((a + 1) >> 2)] + X3[row + ((a - 1) >> 2)] + X1[G.row(b + 1, k) + m] +
-                 X3[G.row(b - 1, k) + m] + X1[G.row(b, k + 1) + m] + X3[G.row(b, k - 1) + m];
-    const T s2 = X2[row + ((a + 2) >> 2)] + X2[row + ((a - 2) >> 2)] + X2[G.row(b + 2, k) + m] +
-                 X2[G.row(b - 2, k) + m] + X2[G.row(b, k + 2) + m] + X2[G.row(b, k - 2) + m];
-    const T s3 = X3[row + ((a + 3) >> 2)] + X1[row + ((a - 3) >> 2)] + X3[G.row(b + 3, k) + m] +
-                 X1[G.row(b - 3, k) + m] + X3[G.row(b, k + 3) + m] + X1[G.row(b, k - 3) + m];
+    // offset +d has colour c+d, offset -d colour c-d (mod 4)
+    T s1 = (T)0, s2 = (T)0, s3 = (T)0;
+    if (!z1) s1 += X1[row + ((a + 1) >> 2)] + X1[G.row(b + 1, k) + m] + X1[G.row(b, k + 1) + m];
+    if (!z3) s1 += X3[row + ((a - 1) >> 2)] + X3[G.row(b - 1, k) + m] + X3[G.row(b, k - 1) + m];
+    if (!z2)
+      s2 = X2[row + ((a + 2) >> 2)] + X2[row + ((a - 2) >> 2)] + X2[G.row(b + 2, k) + m] +
+           X2[G.row(b - 2, k) + m] + X2[G.row(b, k + 2) + m] + X2[G.row(b, k - 2) + m];
+    if (!z3) s3 += X3[row + ((a + 3) >> 2)] + X3[G.row(b + 3, k) + m] + X3[G.row(b, k + 3) + m];
+    if (!z1) s3 += X1[row + ((a - 3) >> 2)] + X1[G.row(b - 3, k) + m] + X1[G.row(b, k - 3) + m];
     const T s = (T)kC1 * s1 + (T)kC2 * s2 + (T)kC3 * s3;
-    Xc[row + m] = (h2 * Fc[row + m] - s) * inv;
+    store_stream(Xc + row + m, (h2 * Fc[row + m] - s) * inv);
   }
 }
 
 // ---------------------------------------------------------------- residual
-// r = f - L u for every unknown; one thread handles the C nodes of a compact
-// column position in a row and marches KZ planes.  Partial sums of r^2 (in
-// FP64) per block when partial != nullptr.
+// r = f - L u for every unknown.  One thread handles the C consecutive nodes
+// a = C*m .. C*m+C-1 of row (b, k) and marches KZ planes.  In a row whose
+// colour shift is s = (b + k + off) mod C, the node at position q of any
+// compact column has colour (q + s) mod C, so per row the thread builds the
+// C colour pointers rotated by s once and then indexes them with compile-time
+// positions.  Partial sums of r^2 (in FP64) per block when partial != nullptr;
+// ZU treats the unknowns of u as zero (norm of b).
 template <typename T, typename TO, int ORDER, bool ZU>
 __global__ __launch_bounds__(256) void k_residual(const T* __restrict__ X, const T* __restrict__ F,
                                                   TO* __restrict__ R, Geom G, T ih2,
                                                   double* __restrict__ partial) {
+  constexpr int C = ORDER == 2 ? 2 : 4;
   int bx, by, bz;
   xcd_block(bx, by, bz);
   const int m = G.mlo() + bx * BX + (int)threadIdx.x;
@@ -132,22 +176,133 @@ __global__ __launch_bounds__(256) void k_residual(const T* __restrict__ X, const
   const int last = G.g + G.n - 2;
   double acc = 0.0;
   if (m <= G.mhi() && b <= last) {
-    const int k0 = G.g + bz * KZ;
-    const int k1 = min(k0 + KZ - 1, last);
+    const int kz = planes_per_block(G);
+    const int k0 = G.g + bz * kz;
+    const int k1 = min(k0 + kz - 1, last);
+    const bool bin = G.inner(b);
     for (int k = k0; k <= k1; ++k) {
-      for (int r = 0; r < G.C; ++r) {
-        const int a = (m << G.lc) + r;
+      const int s = (b + k + G.off) & (C - 1);
+      const T* P[C];
+#pragma unroll
+      for (int q = 0; q < C; ++q) P[q] = X + (long long)((q + s) & (C - 1)) * G.cs;
+      const long long row = G.row(b, k);
+      // centre row: positions a' = C*(m+t) + q for t = -1, 0, 1
+      T ext[3 * C];
+#pragma unroll
+      for (int t = -1; t <= 1; ++t)
+#pragma unroll
+        for (int q = 0; q < C; ++q) {
+          const int a2 = C * (m + t) + q;
+          T v = (T)0;
+          if (a2 >= 0 && a2 < G.M && !(ZU && G.inner(a2) && bin && G.inner(k))) v = P[q][row + m + t];
+          ext[(t + 1) * C + q] = v;
+        }
+#pragma unroll
+      for (int q = 0; q < C; ++q) {
+        const int a = C * m + q;
         if (!G.inner(a)) continue;
-        const long long idx = G.at(a, b, k);
-        const T res = F[idx] - lap_at<T, ORDER, ZU>(X, G, a, b, k, ih2);
+        const int e = C + q;
+        T lap;
+        if (ORDER == 2) {
+          // y / z neighbours sit at the same a with colour (q + s + 1) mod 2;
+          // with ZU only those that are ghost nodes contribute
+          const T* Po = P[(q + 1) & 1];
+          T sy = (T)0;
+          if (!ZU || !G.inner(b - 1)) sy += Po[G.row(b - 1, k) + m];
+          if (!ZU || !G.inner(b + 1)) sy += Po[G.row(b + 1, k) + m];
+          if (!ZU || !G.inner(k - 1)) sy += Po[G.row(b, k - 1) + m];
+          if (!ZU || !G.inner(k + 1)) sy += Po[G.row(b, k + 1) + m];
+          const T sx = ext[e - 1] + ext[e + 1];
+          lap = ((sx + sy) - (T)6 * ext[e]) * ih2;
+        } else {
+          T sd[3];
+#pragma unroll
+          for (int d = 1; d <= 3; ++d) {
+            const T* Pp = P[(q + d) & 3];
+            const T* Pm = P[(q - d) & 3];
+            T v = ext[e - d] + ext[e + d];
+            const bool gy_m = !G.inner(b - d), gy_p = !G.inner(b + d);
+            const bool gz_m = !G.inner(k - d), gz_p = !G.inner(k + d);
+            if (!ZU || gy_p) v += Pp[G.row(b + d, k) + m];
+            if (!ZU || gy_m) v += Pm[G.row(b - d, k) + m];
+            if (!ZU || gz_p) v += Pp[G.row(b, k + d) + m];
+            if (!ZU || gz_m) v += Pm[G.row(b, k - d) + m];
+            sd[d - 1] = v;
+          }
+          lap = ((T)(3.0 * kC0) * ext[e] + (T)kC1 * sd[0] + (T)kC2 * sd[1] + (T)kC3 * sd[2]) * ih2;
+        }
+        const long long idx = (long long)((q + s) & (C - 1)) * G.cs + row + m;
+        const T res = F[idx] - lap;
         if (R) R[idx] = (TO)res;
         acc += (double)res * (double)res;
       }
     }
   }
   if (partial) {
-    const double s = block_sum(acc);
-    if (threadIdx.x == 0 && threadIdx.y == 0) partial[linear_block()] = s;
+    const double sum = block_sum(acc);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partial[linear_block()] = sum;
+  }
+}
+
+// 7-point residual (no zero-unknown option): the thread owns the two nodes
+// a = 2m (colour s) and a = 2m+1 (colour 1-s) of row (b, k) and keeps both
+// colours' values at compact m of planes k-1, k, k+1 in registers, so each
+// plane costs two new centre loads, two x-neighbour loads, four y-neighbour
+// loads and the two right-hand sides.
+template <typename T, typename TO>
+__global__ __launch_bounds__(256) void k_residual7(const T* __restrict__ X, const T* __restrict__ F,
+                                                   TO* __restrict__ R, Geom G, T ih2,
+                                                   double* __restrict__ partial) {
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int m = G.mlo() + bx * BX + (int)threadIdx.x;
+  const int b = G.g + by * BY + (int)threadIdx.y;
+  const int last = G.g + G.n - 2;
+  double acc = 0.0;
+  if (m <= G.mhi() && b <= last) {
+    const int kz = planes_per_block(G);
+    const int k0 = G.g + bz * kz;
+    const int k1 = min(k0 + kz - 1, last);
+    const T* __restrict__ X0 = X;
+    const T* __restrict__ X1 = X + G.cs;
+    const long long plane = (long long)G.M * G.W;
+    const long long cb = G.row(b, 0) + m;
+    T lo0 = X0[cb + (k0 - 1) * plane], lo1 = X1[cb + (k0 - 1) * plane];
+    T cu0 = X0[cb + k0 * plane], cu1 = X1[cb + k0 * plane];
+    const bool inA = G.inner(2 * m), inB = G.inner(2 * m + 1);
+    for (int k = k0; k <= k1; ++k) {
+      const T hi0 = X0[cb + (k + 1) * plane], hi1 = X1[cb + (k + 1) * plane];
+      const int s = (b + k + G.off) & 1;  // colour of node a = 2m
+      const T* __restrict__ Pa = s ? X1 : X0;  // colour of A
+      const T* __restrict__ Pb = s ? X0 : X1;  // colour of B
+      const long long row = G.row(b, k);
+      const T uA = s ? cu1 : cu0, uB = s ? cu0 : cu1;
+      if (inA) {
+        // neighbours of A have B's colour
+        const T sx = Pb[row + m - 1] + uB;
+        const T sy = Pb[row - G.W + m] + Pb[row + G.W + m] + (s ? lo0 : lo1) + (s ? hi0 : hi1);
+        const long long idx = (long long)s * G.cs + row + m;
+        const T res = F[idx] - ((sx + sy) - (T)6 * uA) * ih2;
+        if (R) R[idx] = (TO)res;
+        acc += (double)res * (double)res;
+      }
+      if (inB) {
+        const T sx = uA + Pa[row + m + 1];
+        const T sy = Pa[row - G.W + m] + Pa[row + G.W + m] + (s ? lo1 : lo0) + (s ? hi1 : hi0);
+        const long long idx = (long long)(s ^ 1) * G.cs + row + m;
+        const T res = F[idx] - ((sx + sy) - (T)6 * uB) * ih2;
+        if (R) R[idx] = (TO)res;
+        acc += (double)res * (double)res;
+      }
+      lo0 = cu0;
+      lo1 = cu1;
+      cu0 = hi0;
+      cu1 = hi1;
+    }
+  }
+  if (partial) {
+    const double sum = block_sum(acc);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partial[linear_block()] = sum;
   }
 }
 
@@ -173,26 +328,126 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ Rf, Geom
   Fc[Gc.at(A, B, K)] = s;
 }
 
+// phi_fine += P e_coarse, P = 8 R^T (trilinear interpolation).  One thread
+// handles the C fine nodes at compact column m of row (b, k), marching KZ
+// planes; fine node i takes coarse node i/2 when i is even and the mean of
+// (i-1)/2 and (i+1)/2 when odd, independently along each axis.
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ Ec, Geom Gc, T* __restrict__ Xf,
                                                      Geom Gf) {
-  const int a = blockIdx.x * BX + threadIdx.x;
-  const int b = blockIdx.y * BY + threadIdx.y;
-  const int k = blockIdx.z;
-  if (a >= Gf.M || b >= Gf.M || !Gf.inner(a) || !Gf.inner(b) || !Gf.inner(k)) return;
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int m = Gf.mlo() + bx * BX + (int)threadIdx.x;
+  const int b = Gf.g + by * BY + (int)threadIdx.y;
+  const int last = Gf.g + Gf.n - 2;
+  if (m > Gf.mhi() || b > last) return;
+  const int C = Gf.C;
   const int sh = Gf.g - 1;
-  const int i = a - sh, j = b - sh, l = k - sh;       // global fine node indices
-  const int I = (i >> 1) + sh, J = (j >> 1) + sh, L = (l >> 1) + sh;  // coarse array indices
-  const int oi = i & 1, oj = j & 1, ol = l & 1;
+  const int kz = planes_per_block(Gf);
+  const int k1 = min(Gf.g + bz * kz + kz - 1, last);
+  const int j = b - sh;
+  const int J = (j >> 1) + sh, oj = j & 1;
   const T half = (T)0.5;
-  T s = (T)0;
-  for (int dk = 0; dk <= ol; ++dk)
-    for (int db = 0; db <= oj; ++db)
-      for (int da = 0; da <= oi; ++da) {
-        const T w = (oi ? half : (T)1) * (oj ? half : (T)1) * (ol ? half : (T)1);
-        s += w * Ec[Gc.at(I + da, J + db, L + dk)];
+  for (int k = Gf.g + bz * kz; k <= k1; ++k) {
+    const int l = k - sh;
+    const int L = (l >> 1) + sh, ol = l & 1;
+    T acc[4] = {(T)0, (T)0, (T)0, (T)0};
+    for (int dk = 0; dk <= ol; ++dk)
+      for (int db = 0; db <= oj; ++db) {
+        const int Bc = J + db, Kc = L + dk;
+        const int sc = Bc + Kc + Gc.off;
+        const long long crow = Gc.row(Bc, Kc);
+        const T wyz = (oj ? half : (T)1) * (ol ? half : (T)1);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (q >= C) break;
+          const int a = C * m + q;
+          if (!Gf.inner(a)) continue;
+          const int i = a - sh;
+          const int I = (i >> 1) + sh;
+          T v = Ec[(long long)((I + sc) & (C - 1)) * Gc.cs + crow + (I >> Gc.lc)];
+          if (i & 1) v = half * (v + Ec[(long long)((I + 1 + sc) & (C - 1)) * Gc.cs + crow + ((I + 1) >> Gc.lc)]);
+          acc[q] += wyz * v;
+        }
       }
-  Xf[Gf.at(a, b, k)] += s;
+    const int s = (b + k + Gf.off) & (C - 1);
+    const long long row = Gf.row(b, k);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q >= C) break;
+      if (!Gf.inner(C * m + q)) continue;
+      Xf[(long long)((q + s) & (C - 1)) * Gf.cs + row + m] += acc[q];
+    }
+  }
+}
+
+// Two-colour (7-point hierarchy, one ghost layer) prolongation: the fine
+// nodes 2m and 2m+1 of a row need the coarse values at coarse columns m and
+// m+1 of one or two coarse rows on one or two coarse planes; the coarse plane
+// values are cached in registers while the thread marches fine planes.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong2(const T* __restrict__ Ec, Geom Gc, T* __restrict__ Xf, Geom Gf) {
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int m = Gf.mlo() + bx * BX + (int)threadIdx.x;
+  const int b = Gf.g + by * BY + (int)threadIdx.y;
+  const int last = Gf.g + Gf.n - 2;
+  if (m > Gf.mhi() || b > last) return;
+  const int kz = planes_per_block(Gf);
+  const int k0 = Gf.g + bz * kz;
+  const int k1 = min(k0 + kz - 1, last);
+  const int J = b >> 1, oj = b & 1;
+  const T half = (T)0.5;
+  const bool inA = Gf.inner(2 * m), inB = Gf.inner(2 * m + 1);
+  // coarse value pair (column m, column m+1) of coarse row Bc on plane K,
+  // already interpolated along y when oj = 1
+  auto plane_vals = [&](int K, T& vm, T& vp) {
+    T am, ap;
+    {
+      const int sc = (m + J + K + Gc.off) & 1;
+      const long long crow = Gc.row(J, K);
+      am = Ec[(long long)sc * Gc.cs + crow + (m >> 1)];
+      ap = Ec[(long long)(sc ^ 1) * Gc.cs + crow + ((m + 1) >> 1)];
+    }
+    if (oj) {
+      const int sc = (m + J + 1 + K + Gc.off) & 1;
+      const long long crow = Gc.row(J + 1, K);
+      am = half * (am + Ec[(long long)sc * Gc.cs + crow + (m >> 1)]);
+      ap = half * (ap + Ec[(long long)(sc ^ 1) * Gc.cs + crow + ((m + 1) >> 1)]);
+    }
+    vm = am;
+    vp = ap;
+  };
+  int Kc = k0 >> 1;
+  T cm, cp, nm = (T)0, np = (T)0;
+  bool have_next = false;
+  plane_vals(Kc, cm, cp);
+  for (int k = k0; k <= k1; ++k) {
+    const int L = k >> 1;
+    if (L != Kc) {  // advanced one coarse plane
+      if (have_next) {
+        cm = nm;
+        cp = np;
+      } else {
+        plane_vals(L, cm, cp);
+      }
+      Kc = L;
+      have_next = false;
+    }
+    T em = cm, ep = cp;
+    if (k & 1) {
+      if (!have_next) {
+        plane_vals(L + 1, nm, np);
+        have_next = true;
+      }
+      em = half * (cm + nm);
+      ep = half * (cp + np);
+    }
+    const int s = (b + k + Gf.off) & 1;  // colour of fine node 2m
+    const long long row = Gf.row(b, k);
+    if (inA) Xf[(long long)s * Gf.cs + row + m] += em;
+    if (inB) Xf[(long long)(s ^ 1) * Gf.cs + row + m] += half * (em + ep);
+  }
 }
 
 // e = A_c^{-1} f on the coarsest level: one wavefront per row of the dense
@@ -266,8 +521,9 @@ __global__ __launch_bounds__(256) void k_zero_unknowns(T* __restrict__ X, Geom G
   const int b = G.g + by * BY + (int)threadIdx.y;
   const int last = G.g + G.n - 2;
   if (m > G.mhi() || b > last) return;
-  const int k1 = min(G.g + bz * KZ + KZ - 1, last);
-  for (int k = G.g + bz * KZ; k <= k1; ++k)
+  const int kz = planes_per_block(G);
+  const int k1 = min(G.g + bz * kz + kz - 1, last);
+  for (int k = G.g + bz * kz; k <= k1; ++k)
     for (int r = 0; r < G.C; ++r) {
       const int a = (m << G.lc) + r;
       if (G.inner(a)) X[G.at(a, b, k)] = (T)0;
@@ -282,8 +538,9 @@ __global__ __launch_bounds__(256) void k_add_corr(double* __restrict__ X, const 
   const int b = G.g + by * BY + (int)threadIdx.y;
   const int last = G.g + G.n - 2;
   if (m > G.mhi() || b > last) return;
-  const int k1 = min(G.g + bz * KZ + KZ - 1, last);
-  for (int k = G.g + bz * KZ; k <= k1; ++k)
+  const int kz = planes_per_block(G);
+  const int k1 = min(G.g + bz * kz + kz - 1, last);
+  for (int k = G.g + bz * kz; k <= k1; ++k)
     for (int r = 0; r < G.C; ++r) {
       const int a = (m << G.lc) + r;
       if (G.inner(a)) {
@@ -337,12 +594,13 @@ __global__ __launch_bounds__(256) void k_cg_dir(const double* __restrict__ R, co
   const double beta = scal->v[2];
   double acc = 0.0;
   if (m <= G.mhi() && b <= last) {
-    const int k1 = min(G.g + bz * KZ + KZ - 1, last);
+    const int kz = planes_per_block(G);
+    const int k1 = min(G.g + bz * kz + kz - 1, last);
     auto pv = [&](int aa, int bb, int kk) -> double {
       const long long i = G.at(aa, bb, kk);
       return R[i] + beta * Pold[i];  // ghosts of R and Pold are zero
     };
-    for (int k = G.g + bz * KZ; k <= k1; ++k)
+    for (int k = G.g + bz * kz; k <= k1; ++k)
       for (int r = 0; r < G.C; ++r) {
         const int a = (m << G.lc) + r;
         if (!G.inner(a)) continue;
@@ -384,8 +642,9 @@ __global__ __launch_bounds__(256) void k_cg_upd(double* __restrict__ X, double* 
   const double alpha = scal->v[3];
   double acc = 0.0;
   if (m <= G.mhi() && b <= last) {
-    const int k1 = min(G.g + bz * KZ + KZ - 1, last);
-    for (int k = G.g + bz * KZ; k <= k1; ++k)
+    const int kz = planes_per_block(G);
+    const int k1 = min(G.g + bz * kz + kz - 1, last);
+    for (int k = G.g + bz * kz; k <= k1; ++k)
       for (int r = 0; r < G.C; ++r) {
         const int a = (m << G.lc) + r;
         if (!G.inner(a)) continue;
@@ -481,29 +740,36 @@ void copy_ghosts_split(const double* src, void* dst, bool dst_f32, const Geom& G
 }
 
 void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, int colour, double omega,
-                 hipStream_t st) {
+                 hipStream_t st, int zmask) {
   const dim3 grid = col_grid(G), blk(BX, BY);
   const double h2 = G.h * G.h;
   if (order == 2) {
     const bool sor = omega != 1.0;
+    const bool zg = (zmask >> (colour ^ 1)) & 1;
     if (f32) {
+      float* x = (float*)phi;
+      const float* ff = (const float*)f;
       if (sor)
-        k_pass7<float, true><<<grid, blk, 0, st>>>((float*)phi, (const float*)f, G, colour, (float)omega,
-                                                   (float)h2);
+        k_pass7<float, true, false><<<grid, blk, 0, st>>>(x, ff, G, colour, (float)omega, (float)h2);
+      else if (zg)
+        k_pass7<float, false, true><<<grid, blk, 0, st>>>(x, ff, G, colour, 1.0f, (float)h2);
       else
-        k_pass7<float, false><<<grid, blk, 0, st>>>((float*)phi, (const float*)f, G, colour, 1.0f,
-                                                    (float)h2);
+        k_pass7<float, false, false><<<grid, blk, 0, st>>>(x, ff, G, colour, 1.0f, (float)h2);
     } else {
+      double* x = (double*)phi;
+      const double* ff = (const double*)f;
       if (sor)
-        k_pass7<double, true><<<grid, blk, 0, st>>>((double*)phi, (const double*)f, G, colour, omega, h2);
+        k_pass7<double, true, false><<<grid, blk, 0, st>>>(x, ff, G, colour, omega, h2);
+      else if (zg)
+        k_pass7<double, false, true><<<grid, blk, 0, st>>>(x, ff, G, colour, 1.0, h2);
       else
-        k_pass7<double, false><<<grid, blk, 0, st>>>((double*)phi, (const double*)f, G, colour, 1.0, h2);
+        k_pass7<double, false, false><<<grid, blk, 0, st>>>(x, ff, G, colour, 1.0, h2);
     }
   } else {
     if (f32)
-      k_pass19<float><<<grid, blk, 0, st>>>((float*)phi, (const float*)f, G, colour, (float)h2);
+      k_pass19<float><<<grid, blk, 0, st>>>((float*)phi, (const float*)f, G, colour, (float)h2, zmask);
     else
-      k_pass19<double><<<grid, blk, 0, st>>>((double*)phi, (const double*)f, G, colour, h2);
+      k_pass19<double><<<grid, blk, 0, st>>>((double*)phi, (const double*)f, G, colour, h2, zmask);
   }
 }
 
@@ -516,7 +782,7 @@ static void residual_t(const T* phi, const T* f, TO* r, const Geom& G, int order
     if (zu)
       k_residual<T, TO, 2, true><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
     else
-      k_residual<T, TO, 2, false><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
+      k_residual7<T, TO><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
   } else {
     if (zu)
       k_residual<T, TO, 6, true><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
@@ -549,7 +815,14 @@ void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom&
 
 void prolong_add(const void* e_coarse, const Geom& Gc, void* phi_fine, const Geom& Gf, bool f32,
                  hipStream_t st) {
-  const dim3 grid = node_grid(Gf.M), blk(BX, BY);
+  const dim3 grid = col_grid(Gf), blk(BX, BY);
+  if (Gf.C == 2 && Gf.g == 1) {
+    if (f32)
+      k_prolong2<float><<<grid, blk, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
+    else
+      k_prolong2<double><<<grid, blk, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
+    return;
+  }
   if (f32)
     k_prolong_add<float><<<grid, blk, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
   else

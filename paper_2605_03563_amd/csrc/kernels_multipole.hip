@@ -173,15 +173,14 @@ __global__ __launch_bounds__(kMomThreads) void k_sph_moments(const double* __res
   store_partials<LMAX>(acc, partial);
 }
 
-__global__ __launch_bounds__(256) void k_finish_moments(const double* __restrict__ partial, int nq,
-                                                        double point_mass, double* __restrict__ q) {
-  for (int c = 0; c < nq; ++c) {
-    double s = 0.0;
-    for (int b = threadIdx.x; b < kMomBlocks; b += blockDim.x) s += partial[(long long)c * kMomBlocks + b];
-    s = block_sum(s);
-    if (threadIdx.x == 0) q[c] = s + (c == 0 ? point_mass : 0.0);
-    __syncthreads();
-  }
+// one block per moment: fixed-order sum of its kMomBlocks partials
+__global__ __launch_bounds__(256) void k_finish_moments(const double* __restrict__ partial, double point_mass,
+                                                        double* __restrict__ q) {
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < kMomBlocks; b += blockDim.x) s += partial[(long long)c * kMomBlocks + b];
+  s = block_sum(s);
+  if (threadIdx.x == 0) q[c] = s + (c == 0 ? point_mass : 0.0);
 }
 
 // Every ghost node of the Cartesian node array: z ghost planes, then y ghost
@@ -285,7 +284,7 @@ void sph_moments(const double* rho, const SGeom& S, int lmax, bool inner, double
 }
 
 void finish_moments(const double* partial, int nq, double point_mass, double* q, hipStream_t st) {
-  k_finish_moments<<<1, 256, 0, st>>>(partial, nq, point_mass, q);
+  k_finish_moments<<<nq, 256, 0, st>>>(partial, point_mass, q);
 }
 
 void cart_ghosts(double* phi, long long p0, long long p1, int n, int g, double h, double lo, double cx, double cy,

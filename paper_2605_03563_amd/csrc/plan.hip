@@ -368,24 +368,33 @@ bool coarse_inverse(int nc, double h, int order, std::vector<double>& inv) {
 }
 
 // ------------------------------------------------------------ solver pieces
-void vcycle(poisson_plan_s* P, int l, hipStream_t st) {
+// One V(nu1, nu2) cycle from level l down.  zero_guess: the level's
+// unknowns start at zero (every coarse correction, and the FP32 correction of
+// a refinement step), so the first forward sweep reads colours it has not yet
+// updated as zero instead of clearing the array first.
+void vcycle(poisson_plan_s* P, int l, bool zero_guess, hipStream_t st) {
   Level& L = P->lv[l];
   const bool f32 = P->mg32;
   const poisson_opts_t& o = P->opts;
+  const int C = P->C;
   if (l + 1 == (int)P->lv.size()) {
     coarse_solve(P->cinv, L.f, L.phi, f32, L.G, st);
     return;
   }
+  if (zero_guess && o.nu1 == 0) zero_unknowns(L.phi, f32, L.G, st);
   for (int s = 0; s < o.nu1; ++s)
-    for (int c = 0; c < P->C; ++c) colour_pass(L.phi, L.f, f32, L.G, P->order, c, 1.0, st);
+    for (int c = 0; c < C; ++c) {
+      int zmask = 0;
+      if (zero_guess && s == 0) zmask = ((1 << C) - 1) & ~((1 << (c + 1)) - 1);  // colours > c
+      colour_pass(L.phi, L.f, f32, L.G, P->order, c, 1.0, st, zmask);
+    }
   residual(L.phi, L.f, f32, L.tmp, f32, L.G, P->order, false, nullptr, st);
   Level& Lc = P->lv[l + 1];
   restrict_fw(L.tmp, L.G, Lc.f, Lc.G, f32, st);
-  zero_unknowns(Lc.phi, f32, Lc.G, st);
-  vcycle(P, l + 1, st);
+  vcycle(P, l + 1, true, st);
   prolong_add(Lc.phi, Lc.G, L.phi, L.G, f32, st);
   for (int s = 0; s < o.nu2; ++s)
-    for (int c = P->C - 1; c >= 0; --c) colour_pass(L.phi, L.f, f32, L.G, P->order, c, 1.0, st);
+    for (int c = C - 1; c >= 0; --c) colour_pass(L.phi, L.f, f32, L.G, P->order, c, 1.0, st);
 }
 
 // One multigrid iteration followed by the fine residual norm into
@@ -396,12 +405,11 @@ void mg_step(poisson_plan_s* P, hipStream_t st) {
   const int nb = residual_blocks(P->G0);
   if (P->mg32) {
     Level& L0 = P->lv[0];
-    zero_unknowns(L0.phi, true, L0.G, st);
-    vcycle(P, 0, st);
+    vcycle(P, 0, true, st);
     add_correction(P->phi64, L0.phi, true, P->G0, st);
     residual(P->phi64, P->f64, false, L0.f, true, P->G0, P->order, false, P->partial, st);
   } else {
-    vcycle(P, 0, st);
+    vcycle(P, 0, false, st);
     residual(P->phi64, P->f64, false, nullptr, false, P->G0, P->order, false, P->partial, st);
   }
   finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
