@@ -200,6 +200,53 @@ int poisson_op_vcycle(poisson_plan_t plan, const double* d_rho, double* d_phi, i
    potential. */
 int poisson_op_sweep_resident(poisson_plan_t plan, int32_t sweeps);
 
+/* ---- serving loop: continuous batching of independent solves -----------
+   A persistent worker thread advances every admitted request by one
+   multigrid iteration at a time on its own stream slot, so requests of
+   different sizes overlap on the device; requests that arrive while others
+   run are admitted as slots and memory free up.  Device memory (plan
+   workspaces and one cached potential per stream id) is allocated by the
+   server within budget_bytes; idle plans and cached potentials are released
+   least-recently-used first.  Each stream id's last potential is the initial
+   guess of its next request (Section 2.1: the previous potential as initial
+   estimate).  A result depends only on its density and its stream's history,
+   not on what else is running. */
+typedef struct poisson_server_s* poisson_server_t;
+
+/* max_slots in 1..16 concurrent requests; mixed != 0: FP32 V-cycles inside
+   FP64 refinement (7-point), else FP64 V-cycles; lmax: multipole order of the
+   open boundary; nu: smoothing sweeps nu1 = nu2; tol: relative residual
+   target; warm_start: reuse each stream's previous potential; use_graphs:
+   launch each iteration as one captured graph.  Uses the current device. */
+int poisson_server_create(poisson_server_t* out, size_t budget_bytes, int32_t max_slots, int32_t mixed,
+                          int32_t lmax, int32_t nu, double tol, int32_t warm_start, int32_t use_graphs);
+/* Queue a solve on the unit box with n = 8 * 2^L intervals per axis.
+   d_rho and d_phi are caller-owned device arrays in natural layout with
+   pitch (n+1, (n+1)^2) elements; both must stay valid until the request is
+   done; the potential is written into d_phi.  Returns POISSON_EADMIT when the
+   request alone exceeds the budget, POISSON_EGRID for other sizes. */
+int poisson_server_submit(poisson_server_t srv, int32_t stream_id, int32_t n, const double* d_rho,
+                          double* d_phi, int64_t* ticket);
+/* *done = 1 once the request has finished; then returns its status
+   (POISSON_OK, POISSON_WARN_MAXITER or an error) and fills stats (NULL
+   allowed; t_iter_ms = start-to-finish time on the device) and the latency
+   from submission to completion in milliseconds. */
+int poisson_server_poll(poisson_server_t srv, int64_t ticket, int32_t* done, poisson_stats_t* stats,
+                        double* latency_ms);
+/* Block up to timeout_ms for a ticket; returns its status, or
+   POISSON_WARN_MAXITER on timeout. */
+int poisson_server_wait(poisson_server_t srv, int64_t ticket, double timeout_ms);
+/* Build `count` (<= 16) plans of size n with their captured graphs ahead of
+   traffic, within the budget, so that no request pays for plan construction;
+   blocks until done.  Returns POISSON_EADMIT if they do not fit. */
+int poisson_server_reserve(poisson_server_t srv, int32_t n, int32_t count);
+/* Device bytes one request of size n occupies (plan workspace + cached potential). */
+int poisson_server_footprint(poisson_server_t srv, int32_t n, size_t* bytes);
+/* Current device bytes held, queued and running request counts (any may be NULL). */
+int poisson_server_usage(poisson_server_t srv, size_t* used_bytes, int32_t* queued, int32_t* active);
+/* Waits for every queued and running request, then releases everything. */
+void poisson_server_destroy(poisson_server_t srv);
+
 #ifdef __cplusplus
 }
 #endif

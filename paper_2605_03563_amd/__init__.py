@@ -208,6 +208,66 @@ class Plan:
         _check(self.lib.poisson_op_vcycle(self.handle, _ptr(rho, ne), _ptr(phi, ne), cycles), "poisson_op_vcycle")
 
 
+class Server:
+    """Continuous-batching solve server (a persistent loop in the library)."""
+
+    def __init__(self, budget_bytes: int, max_slots=8, mixed=True, lmax=8, nu=2, tol=1e-8, warm_start=True,
+                 use_graphs=True):
+        self.lib = L.load()
+        h = C.c_void_p()
+        _check(self.lib.poisson_server_create(C.byref(h), int(budget_bytes), max_slots, int(mixed), lmax, nu, tol,
+                                              int(warm_start), int(use_graphs)), "poisson_server_create")
+        self.handle = h
+
+    def submit(self, stream_id: int, n: int, rho: torch.Tensor, phi: torch.Tensor) -> int:
+        t = C.c_int64()
+        need = (n + 1) ** 3
+        _check(self.lib.poisson_server_submit(self.handle, stream_id, n, _ptr(rho, need), _ptr(phi, need),
+                                              C.byref(t)), "poisson_server_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        done = C.c_int32()
+        st = L.Stats()
+        lat = C.c_double()
+        status = self.lib.poisson_server_poll(self.handle, ticket, C.byref(done), C.byref(st), C.byref(lat))
+        if not done.value:
+            _check(status, "poisson_server_poll")
+            return None
+        return SolveResult(status, st.iterations, st.rel_residual, st.b_norm, st.rate, 0.0, st.t_iter_ms, []), \
+            lat.value
+
+    def wait(self, ticket: int, timeout_ms: float = 120000.0) -> int:
+        return self.lib.poisson_server_wait(self.handle, ticket, timeout_ms)
+
+    def reserve(self, n: int, count: int):
+        _check(self.lib.poisson_server_reserve(self.handle, n, count), "poisson_server_reserve")
+
+    def footprint(self, n: int) -> int:
+        b = C.c_size_t()
+        _check(self.lib.poisson_server_footprint(self.handle, n, C.byref(b)), "poisson_server_footprint")
+        return b.value
+
+    def usage(self):
+        used = C.c_size_t()
+        q = C.c_int32()
+        a = C.c_int32()
+        _check(self.lib.poisson_server_usage(self.handle, C.byref(used), C.byref(q), C.byref(a)),
+               "poisson_server_usage")
+        return used.value, q.value, a.value
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.poisson_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def sweep_resident(plan: "Plan", sweeps: int):
     _check(plan.lib.poisson_op_sweep_resident(plan.handle, sweeps), "poisson_op_sweep_resident")
 

@@ -58,6 +58,18 @@ SIGNATURES = {
     "poisson_op_prolong_add": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "poisson_op_vcycle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "poisson_op_sweep_resident": (C.c_int, [C.c_void_p, C.c_int32]),
+    "poisson_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_size_t, C.c_int32, C.c_int32, C.c_int32,
+                                        C.c_int32, C.c_double, C.c_int32, C.c_int32]),
+    "poisson_server_submit": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                        C.POINTER(C.c_int64)]),
+    "poisson_server_poll": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32), C.POINTER(Stats),
+                                      C.POINTER(C.c_double)]),
+    "poisson_server_wait": (C.c_int, [C.c_void_p, C.c_int64, C.c_double]),
+    "poisson_server_reserve": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "poisson_server_footprint": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_size_t)]),
+    "poisson_server_usage": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32)]),
+    "poisson_server_destroy": (None, [C.c_void_p]),
 }
 
 _lib = None

@@ -8,9 +8,13 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "internal.h"
+#include "plan_impl.h"
 #include "reduce.h"
 
 using namespace psn;
@@ -18,7 +22,7 @@ using namespace psn;
 // ============================================================ error state
 static thread_local char g_err[512] = "";
 
-static void set_error(const char* fmt, ...) {
+void psn::set_error(const char* fmt, ...) {
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(g_err, sizeof g_err, fmt, ap);
@@ -40,7 +44,7 @@ static void set_error(const char* fmt, ...) {
     if (s_ < 0) return s_;             \
   } while (0)
 
-static int launch_check(const char* what) {
+int psn::launch_check(const char* what) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) {
     set_error("kernel launch in %s failed: %s", what, hipGetErrorString(e));
@@ -51,15 +55,6 @@ static int launch_check(const char* what) {
 
 // ============================================================ plan
 namespace {
-
-struct Level {
-  Geom G;
-  void* phi = nullptr;
-  void* f = nullptr;
-  void* tmp = nullptr;
-};
-
-enum ScalarSlot { kRR = 0, kBnorm2 = 8, kRes2 = 9 };
 
 struct Carver {
   char* base;
@@ -72,45 +67,6 @@ struct Carver {
     return p;
   }
 };
-
-}  // namespace
-
-struct poisson_plan_s {
-  poisson_grid_t grid{};
-  poisson_opts_t opts{};
-  hipStream_t st = nullptr;
-  hipStream_t cap = nullptr;  // private stream used only to capture graphs
-  bool sph = false;
-  int order = 2;
-  int C = 2;
-  // Cartesian level 0 (FP64, colour split)
-  Geom G0{};
-  double* phi64 = nullptr;
-  double* f64 = nullptr;
-  double* t64 = nullptr;
-  // multigrid hierarchy: lv[0] is the finest level of the cycle
-  std::vector<Level> lv;
-  bool mg32 = false;
-  double* cinv = nullptr;
-  int ncoarse = 0;
-  // CG
-  double *cr = nullptr, *cp0 = nullptr, *cp1 = nullptr, *cq = nullptr;
-  // spherical
-  SGeom S{};
-  SphCoef sc{};
-  double *sr = nullptr, *srh = nullptr, *sp[2] = {nullptr, nullptr}, *sv[2] = {nullptr, nullptr};
-  double *ss = nullptr, *stt = nullptr;
-  // reductions and moments
-  double* partial = nullptr;
-  Scalars* scal = nullptr;
-  double* qlm = nullptr;  // 2 * kNqMax
-  double* host = nullptr; // pinned scalars
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-  hipGraphExec_t step_exec = nullptr;
-  std::vector<double> omega_seq;
-};
-
-namespace {
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
@@ -304,7 +260,7 @@ void carve(poisson_plan_s* P, Carver& cv) {
 // Dense matrix of L_h on the (E)^3 unknowns of a level with zero ghosts
 // (7-point or 19-point star), inverted through a Cholesky factorisation of
 // the SPD matrix -L_h.  Returns false if the factorisation fails.
-bool coarse_inverse(int nc, double h, int order, std::vector<double>& inv) {
+bool coarse_inverse_compute(int nc, double h, int order, std::vector<double>& inv) {
   const int E = nc - 1;
   const int N = E * E * E;
   std::vector<double> A((size_t)N * N, 0.0);
@@ -364,6 +320,26 @@ bool coarse_inverse(int nc, double h, int order, std::vector<double>& inv) {
     }
     for (int r = 0; r < N; ++r) inv[(size_t)r * N + c] = -y[r];
   }
+  return true;
+}
+
+// The exact coarsest inverse depends only on (intervals, spacing, stencil);
+// plans of the same shape share one host copy instead of refactorising.
+bool coarse_inverse(int nc, double h, int order, std::vector<double>& inv) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, double, int>, std::vector<double>> cache;
+  const auto key = std::make_tuple(nc, h, order);
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      inv = it->second;
+      return true;
+    }
+  }
+  if (!coarse_inverse_compute(nc, h, order, inv)) return false;
+  std::lock_guard<std::mutex> lk(mu);
+  cache[key] = inv;
   return true;
 }
 
@@ -501,12 +477,10 @@ double rel_of(double r2, double bnorm) {
 }
 
 // ------------------------------------------------------------ Cartesian solve
-int solve_cart(poisson_plan_s* P, const double* rho, double* phi, double tol, poisson_stats_t* stats) {
+int cart_setup_impl(poisson_plan_s* P, const double* rho, double* phi) {
   const poisson_grid_t& g = P->grid;
   const poisson_opts_t& o = P->opts;
   hipStream_t st = P->st;
-  Tracker T{stats};
-  if (stats) stats->history_len = 0;
   HIPCHK(hipEventRecord(P->ev[0], st));
   if (o.lmax >= 0) CHK(do_multipole(P, rho, phi, o.lmax, nullptr));
   HIPCHK(hipEventRecord(P->ev[1], st));
@@ -527,7 +501,18 @@ int solve_cart(poisson_plan_s* P, const double* rho, double* phi, double tol, po
   }
   residual(P->phi64, P->f64, false, rout, rout32, G, P->order, false, P->partial, st);
   finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
-  CHK(launch_check("solve setup"));
+  return launch_check("solve setup");
+}
+
+int solve_cart(poisson_plan_s* P, const double* rho, double* phi, double tol, poisson_stats_t* stats) {
+  const poisson_grid_t& g = P->grid;
+  const poisson_opts_t& o = P->opts;
+  hipStream_t st = P->st;
+  Tracker T{stats};
+  if (stats) stats->history_len = 0;
+  const Geom& G = P->G0;
+  const int nb = residual_blocks(G);
+  CHK(cart_setup_impl(P, rho, phi));
   CHK(read_scalars(P, kBnorm2, 2));
   T.bnorm = sqrt(P->host[0]);
   double rel = rel_of(P->host[1], T.bnorm);
@@ -714,6 +699,36 @@ bool same_grid(const poisson_grid_t* a, const poisson_grid_t* b) {
 }
 
 }  // namespace
+
+int psn::cart_setup(poisson_plan_s* P, const double* rho, double* phi) { return cart_setup_impl(P, rho, phi); }
+
+int psn::cart_step(poisson_plan_s* P, bool use_graph) {
+  if (P->lv.empty()) {
+    set_error("multigrid plan expected");
+    return POISSON_EINVAL;
+  }
+  if (use_graph) {
+    CHK(capture_step(P));
+    HIPCHK(hipGraphLaunch(P->step_exec, P->st));
+    return POISSON_OK;
+  }
+  mg_step(P, P->st);
+  return launch_check("multigrid step");
+}
+
+int psn::cart_prepare_graph(poisson_plan_s* P) {
+  if (P->lv.empty()) {
+    set_error("multigrid plan expected");
+    return POISSON_EINVAL;
+  }
+  return capture_step(P);
+}
+
+int psn::cart_finish(poisson_plan_s* P, double* phi) {
+  const poisson_grid_t& g = P->grid;
+  merge_to_natural(P->phi64, phi, g.pitch[0], g.pitch[1], P->G0, true, 1.0, P->st);
+  return launch_check("solve finish");
+}
 
 // ============================================================ C ABI
 extern "C" {

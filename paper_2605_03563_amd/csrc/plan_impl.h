@@ -1,0 +1,73 @@
+// Internal definition of a solver plan, shared by the solver drivers and the
+// serving loop (not part of the C ABI).
+#pragma once
+
+#include <vector>
+
+#include "internal.h"
+
+namespace psn {
+
+void set_error(const char* fmt, ...);
+int launch_check(const char* what);
+
+struct Level {
+  Geom G;
+  void* phi = nullptr;
+  void* f = nullptr;
+  void* tmp = nullptr;
+};
+
+}  // namespace psn
+
+struct poisson_plan_s {
+  poisson_grid_t grid{};
+  poisson_opts_t opts{};
+  hipStream_t st = nullptr;
+  hipStream_t cap = nullptr;  // private stream used only to capture graphs
+  bool sph = false;
+  int order = 2;
+  int C = 2;
+  // Cartesian level 0 (FP64, colour split)
+  psn::Geom G0{};
+  double* phi64 = nullptr;
+  double* f64 = nullptr;
+  double* t64 = nullptr;
+  // multigrid hierarchy: lv[0] is the finest level of the cycle
+  std::vector<psn::Level> lv;
+  bool mg32 = false;
+  double* cinv = nullptr;
+  int ncoarse = 0;
+  // CG
+  double *cr = nullptr, *cp0 = nullptr, *cp1 = nullptr, *cq = nullptr;
+  // spherical
+  psn::SGeom S{};
+  psn::SphCoef sc{};
+  double *sr = nullptr, *srh = nullptr, *sp[2] = {nullptr, nullptr}, *sv[2] = {nullptr, nullptr};
+  double *ss = nullptr, *stt = nullptr;
+  // reductions and moments
+  double* partial = nullptr;
+  psn::Scalars* scal = nullptr;
+  double* qlm = nullptr;  // 2 * kNqMax
+  double* host = nullptr; // pinned scalars
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  hipGraphExec_t step_exec = nullptr;
+};
+
+namespace psn {
+
+enum ScalarSlot { kRR = 0, kBnorm2 = 8, kRes2 = 9 };
+
+// Asynchronous phases of a Cartesian multigrid solve on the plan's stream
+// (no host synchronisation): setup = multipole boundary (when lmax >= 0),
+// layout split, ||b||^2 into scal->v[kBnorm2] and the initial residual norm^2
+// into scal->v[kRes2]; step = one multigrid iteration (graph launch when
+// use_graph) leaving the new residual norm^2 in scal->v[kRes2]; finish =
+// write the unknowns back to the caller's array.
+int cart_setup(poisson_plan_s* P, const double* rho, double* phi);
+int cart_step(poisson_plan_s* P, bool use_graph);
+int cart_finish(poisson_plan_s* P, double* phi);
+// capture the step graph now (done lazily by the first graph step otherwise)
+int cart_prepare_graph(poisson_plan_s* P);
+
+}  // namespace psn

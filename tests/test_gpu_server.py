@@ -1,0 +1,125 @@
+"""Serving loop: results against the oracle, the same result alone and in the
+mix (bitwise, since every plan of a size computes identically and reductions
+run in a fixed order), warm starts, admission by memory budget."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2605_03563_amd as pg
+from oracle import direct as OD
+from oracle import multipole as OM
+from tests.gpu_util import host, rel_l2, say
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GB = 1 << 30
+
+
+def _stream(n_requests, sizes, n_streams, seed):
+    reqs = W.serving_stream(n_requests=n_requests, rate=1000.0, n_streams=n_streams, seed=seed, sizes=sizes,
+                            weights=tuple([1.0 / len(sizes)] * len(sizes)))
+    return reqs
+
+
+def _run(server, reqs, rhos):
+    outs, tickets = [], []
+    for r, rho in zip(reqs, rhos):
+        phi = torch.zeros_like(rho)
+        outs.append(phi)
+        tickets.append(server.submit(r.stream_id, r.n, rho, phi))
+    res = []
+    for t in tickets:
+        assert server.wait(t, 120000.0) in (0, 1)
+        res.append(server.poll(t))
+    torch.cuda.synchronize()
+    return outs, res
+
+
+def test_served_results_match_oracle():
+    say("server: results vs oracle")
+    reqs = _stream(12, (32, 64), 4, seed=11)
+    rhos = [r.density(DEV) for r in reqs]
+    srv = pg.Server(8 * GB, max_slots=4, mixed=True, tol=1e-10)
+    outs, res = _run(srv, reqs, rhos)
+    srv.close()
+    for r, rho, phi, (st, lat) in zip(reqs, rhos, outs, res):
+        assert st.status == 0 and st.rel_residual <= 1e-10, st
+        assert lat > 0.0
+        rh = host(rho)
+        ghost, _ = OM.cart_boundary(rh, r.n, 1, 8)
+        ref = OD.solve_cart(ghost, rh, r.n, 1.0 / r.n, 2, 1)
+        s = slice(1, r.n)
+        assert rel_l2(host(phi)[s, s, s], ref[s, s, s]) < 1e-7
+
+
+def test_same_result_alone_and_in_the_mix():
+    say("server: alone vs mix")
+    reqs = _stream(24, (32, 64, 128), 6, seed=12)
+    rhos = [r.density(DEV) for r in reqs]
+    target = reqs[0].stream_id
+    mine = [i for i, r in enumerate(reqs) if r.stream_id == target]
+    assert len(mine) >= 2
+    alone_srv = pg.Server(8 * GB, max_slots=1, mixed=True)
+    alone, _ = _run(alone_srv, [reqs[i] for i in mine], [rhos[i] for i in mine])
+    alone_srv.close()
+    mix_srv = pg.Server(8 * GB, max_slots=8, mixed=True)
+    mixed, res = _run(mix_srv, reqs, rhos)
+    mix_srv.close()
+    for j, i in enumerate(mine):
+        assert torch.equal(alone[j], mixed[i]), f"request {i} differs alone vs in the mix"
+    assert all(r[0].status == 0 for r in res)
+
+
+def test_warm_start_cuts_refinement_steps():
+    say("server: warm start")
+    reqs = _stream(40, (64,), 2, seed=13)
+    rhos = [r.density(DEV) for r in reqs]
+    srv = pg.Server(8 * GB, max_slots=2, mixed=True, warm_start=True)
+    _, res = _run(srv, reqs, rhos)
+    srv.close()
+    cold = [st.iterations for (st, _), r in zip(res, reqs) if r.version == 0]
+    warm = [st.iterations for (st, _), r in zip(res, reqs) if r.version > 0]
+    assert warm and cold
+    assert np.mean(warm) < np.mean(cold)
+
+
+def test_reserve_builds_idle_plans_within_budget():
+    say("server: reserve")
+    srv = pg.Server(4 * GB, max_slots=4, mixed=True)
+    one = srv.footprint(32)
+    srv.reserve(32, 3)
+    used, queued, active = srv.usage()
+    assert used >= 3 * (one - 33 ** 3 * 8) and queued == 0 and active == 0
+    srv.close()
+    small = pg.Server(int(1.5 * one), max_slots=4, mixed=True)
+    with pytest.raises(pg.PoissonError) as e:
+        small.reserve(32, 4)
+    assert e.value.status == -6
+    small.close()
+
+
+def test_admission_by_memory_budget():
+    say("server: admission by budget")
+    reqs = _stream(8, (64,), 3, seed=14)
+    rhos = [r.density(DEV) for r in reqs]
+    probe = pg.Server(8 * GB, max_slots=1)
+    one = probe.footprint(64)
+    probe.close()
+    tight = pg.Server(int(1.5 * one), max_slots=4, mixed=True)
+    outs_t, res_t = _run(tight, reqs, rhos)
+    used, queued, active = tight.usage()
+    assert used <= int(1.5 * one) and queued == 0 and active == 0
+    with pytest.raises(pg.PoissonError) as e:
+        tight.submit(0, 256, torch.zeros(257 ** 3, dtype=torch.float64, device=DEV),
+                     torch.zeros(257 ** 3, dtype=torch.float64, device=DEV))
+    assert e.value.status == -6
+    tight.close()
+    roomy = pg.Server(8 * GB, max_slots=4, mixed=True)
+    outs_r, _ = _run(roomy, reqs, rhos)
+    roomy.close()
+    assert all(st.status == 0 for st, _ in res_t)
+    # without room for a second potential every stream restarts cold, so the
+    # results agree to the solve tolerance rather than bitwise
+    for a, b in zip(outs_t, outs_r):
+        assert rel_l2(host(a), host(b)) < 1e-6
