@@ -48,7 +48,7 @@ def parse():
                          "--sweeps resident smoother sweeps and one 1 GiB reference copy; "
                          "prints no bench line")
     ap.add_argument("--sweeps", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["c2", "serving"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "serving"],
                     help="c2: the 255^3 FP64 multigrid solve (default bench line); serving: the "
                          "continuous-batching request stream (its own JSON line)")
     ap.add_argument("--requests", type=int, default=2000)
@@ -64,6 +64,114 @@ def _pct(xs, q):
         return float("nan")
     i = min(len(xs) - 1, max(0, int(math.ceil(q / 100.0 * len(xs))) - 1))
     return xs[i]
+
+
+def _time_solves(plan, rho, phi, tol, steps, warmup):
+    import torch
+    res = None
+    for _ in range(warmup):
+        phi.zero_()
+        res = plan.solve(rho, phi, tol=tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        phi.zero_()
+        res = plan.solve(rho, phi, tol=tol)
+        if not res.converged:
+            raise RuntimeError(f"solve did not converge: {res}")
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, res
+
+
+def c3(args):
+    """512^3 intervals (511^3 unknowns), 19-point 6th-order star, 64 Gaussian
+    clumps + 5% lognormal |k|^-2 floor, lmax 8: FP32 four-colour V(2,2) cycles
+    inside FP64 iterative refinement against the all-FP64 19-point multigrid."""
+    import torch
+
+    import paper_2605_03563_amd as pg
+    import workloads as W
+
+    dev = "cuda:0"
+    n = 512
+    wl = W.config_c3(n=n, device=dev)
+    rho = wl.rho.contiguous()
+    del wl
+    unknowns = (n - 1) ** 3
+    grid = pg.cart_grid(n, ghost=3)
+    p32 = pg.Plan(grid, pg.options("mg_ir32", order=6, lmax=8), device=dev)
+    phi32 = torch.zeros_like(rho)
+    sec32, r32 = _time_solves(p32, rho, phi32, args.tol, args.steps, args.warmup)
+    # dominant kernel: the fine-level FP32 four-colour pass
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pg.sweep_resident(p32, 1)
+    ev0.record(p32.stream)
+    pg.sweep_resident(p32, 5)
+    ev1.record(p32.stream)
+    torch.cuda.synchronize()
+    pass_ms = ev0.elapsed_time(ev1) / 20
+    bytes_per_pass = 5.0 * unknowns   # FP32: 3 other colours + f_c read, colour c written
+    achieved = bytes_per_pass / (pass_ms * 1e-3) / 1e9
+    del p32
+    p64 = pg.Plan(grid, pg.options("mg", order=6, lmax=8), device=dev)
+    phi64 = torch.zeros_like(rho)
+    sec64, r64 = _time_solves(p64, rho, phi64, args.tol, max(1, args.steps // 2), 1)
+    # reference: FP64 multigrid driven to round-off
+    ref = torch.zeros_like(rho)
+    rref = p64.solve(rho, ref, tol=1e-12)
+    s = slice(3, 3 + n - 1)
+    err32 = float(torch.linalg.vector_norm(phi32[s, s, s] - ref[s, s, s]) / torch.linalg.vector_norm(ref[s, s, s]))
+    err64 = float(torch.linalg.vector_norm(phi64[s, s, s] - ref[s, s, s]) / torch.linalg.vector_norm(ref[s, s, s]))
+    out = {
+        "metric": "Gcell-updates/s", "value": unknowns * r32.iterations / sec32 / 1e9, "unit": "Gcell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec32 * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "c3_clumps64_floor_512^3_star19_fp32mg_in_fp64ir_lmax8", "unknowns": unknowns},
+        "time_to_1e-8_ms": sec32 * 1e3, "refinement_steps": r32.iterations,
+        "fp64_mg_time_to_1e-8_ms": sec64 * 1e3, "fp64_mg_cycles": r64.iterations,
+        "speedup_mixed_vs_fp64": sec64 / sec32,
+        "err_vs_converged_fp64_mixed": err32, "err_vs_converged_fp64_fp64mg": err64,
+        "converged_reference_rel_residual": rref.rel_residual,
+        "t_multipole_ms": r32.t_multipole_ms,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "k_pass19<float> (fine-level four-colour GS pass)",
+                     "algorithmic_bytes_per_launch": bytes_per_pass, "pass_ms": pass_ms},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def c4(args):
+    """Log-spherical 256 x 128 x 256 grid (r in [1e-3, 1]), truncated SIS with a
+    10% m = 2 perturbation, lmax 8 outer + inner expansions and the excised
+    core as a central point mass; BiCGSTAB in FP64 from a cold start."""
+    import torch
+
+    import paper_2605_03563_amd as pg
+    import workloads as W
+
+    dev = "cuda:0"
+    wl = W.config_c4(device=dev)
+    rho = wl.rho.contiguous()
+    g = wl.grid
+    grid = pg.sph_grid(g.nr, g.nth, g.nph)
+    plan = pg.Plan(grid, pg.options("bicgstab", lmax=8, point_mass=4 * math.pi * g.r_min, max_iter=20000,
+                                    check_every=10), device=dev)
+    phi = torch.zeros_like(rho)
+    sec, res = _time_solves(plan, rho, phi, args.tol, max(1, args.steps // 2), 1)
+    unknowns = g.unknowns
+    it_ms = res.t_iter_ms / max(1, res.iterations)
+    bytes_per_it = 200.0 * unknowns   # preconditioned iteration: 7 streaming kernels
+    out = {
+        "metric": "Gcell-updates/s", "value": unknowns * res.iterations / sec / 1e9, "unit": "Gcell-updates/s",
+        "n_gpus": 1, "steps": max(1, args.steps // 2), "warmup": 1, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "c4_sis_m2_256x128x256_logsph_bicgstab_lmax8", "unknowns": unknowns},
+        "time_to_1e-8_ms": sec * 1e3, "iterations": res.iterations, "rel_residual": res.rel_residual,
+        "t_multipole_ms": res.t_multipole_ms, "ms_per_iteration": it_ms,
+        "iteration_GBps_algorithmic": bytes_per_it / (it_ms * 1e-3) / 1e9,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def serving(args):
@@ -232,8 +340,8 @@ def main():
     if args.kernels_only:
         kernels_only(args)
         return
-    if args.workload == "serving":
-        serving(args)
+    if args.workload != "c2":
+        {"serving": serving, "c3": c3, "c4": c4}[args.workload](args)
         return
 
     import torch

@@ -133,13 +133,18 @@ struct SphCoef { const double* cot; const double* isin2; const double* r2; };
 void sph_residual(const double* u, const double* rho, double* r, const SGeom& S, const SphCoef& c,
                   double four_pi_G, bool zero_unknowns_in, double* partial, hipStream_t st);
 void sph_apply(const double* u, double* out, const SGeom& S, const SphCoef& c, hipStream_t st);
-void bicg_p_v(const double* r, const double* p_old, const double* v_old, double* p, double* v,
-              const double* rhat, const SGeom& S, const SphCoef& c, const Scalars* scal, double* partial,
-              hipStream_t st);
-void bicg_s_t(const double* r, const double* v, double* s, double* t, const SGeom& S, const SphCoef& c,
-              const Scalars* scal, double* partial, hipStream_t st);
-void bicg_xr(double* x, double* r, const double* p, const double* s, const double* t, const double* rhat,
-             const SGeom& S, const Scalars* scal, double* partial, hipStream_t st);
+// right-preconditioned BiCGSTAB: p = r + beta (p - omega v), phat = B^-1 p;
+// s = r - alpha v, shat = B^-1 s (B: red-black block lower triangle);
+// out = A xhat with dots (mode 0: w.out; mode 1: w.out and out.out);
+// x += alpha phat + omega shat, r = s - omega t with dots rhat.r and r.r
+void pbicg_direction(const double* r, double* p, const double* v, double* phat, const SGeom& S,
+                     const SphCoef& c, const Scalars* scal, hipStream_t st);
+void pbicg_s(const double* r, const double* v, double* s, double* shat, const SGeom& S, const SphCoef& c,
+             const Scalars* scal, hipStream_t st);
+void pbicg_apply(const double* xhat, double* out, const double* w, int mode, const SGeom& S,
+                 const SphCoef& c, double* partial, hipStream_t st);
+void pbicg_xr(double* x, double* r, const double* phat, const double* shat, const double* s, const double* t,
+              const double* rhat, const SGeom& S, const Scalars* scal, double* partial, hipStream_t st);
 void bicg_scalars(const double* partial, int nb, Scalars* scal, int stage, hipStream_t st);
 int sph_blocks(const SGeom& S);
 void sph_fill_zero(double* x, const SGeom& S, hipStream_t st);

@@ -76,69 +76,106 @@ __global__ __launch_bounds__(256) void k_sph_apply(const double* __restrict__ U,
   out[S.at(i, j, k)] = sph_op(V, S, c, cot2, isin2, i, j, k);
 }
 
-// scal->v: 0 rho, 1 alpha, 2 omega, 3 beta, 4 rhat.v, 5 t.s, 6 t.t, 7 r.r
-// p = r + beta (p_old - omega v_old);  v = A p;  partial0 += rhat . v
-__global__ __launch_bounds__(256) void k_bicg_pv(const double* __restrict__ R, const double* __restrict__ Pold,
-                                                 const double* __restrict__ Vold, double* __restrict__ P,
-                                                 double* __restrict__ Vn, const double* __restrict__ Rhat, SGeom S,
-                                                 Coef c, const double* __restrict__ cot2,
-                                                 const double* __restrict__ isin2,
-                                                 const Scalars* __restrict__ scal, double* __restrict__ partial) {
-  const int i = 1 + blockIdx.x * BX + threadIdx.x;
-  const int j = blockIdx.y * BY + threadIdx.y;
-  const int k = blockIdx.z;
-  const double beta = scal->v[3], omega = scal->v[2];
-  double acc = 0.0;
-  if (active(S, i, j, k)) {
-    auto V = [&](int ii, int jj, int kk) -> double {
-      const long long q = S.at(ii, jj, kk);
-      return R[q] + beta * (Pold[q] - omega * Vold[q]);
-    };
-    const long long idx = S.at(i, j, k);
-    const double av = sph_op(V, S, c, cot2, isin2, i, j, k);
-    P[idx] = V(i, j, k);
-    Vn[idx] = av;
-    acc = Rhat[idx] * av;
-  }
-  const double s = block_sum(acc);
-  if (threadIdx.x == 0 && threadIdx.y == 0) partial[linear_block()] = s;
+// Right-preconditioned BiCGSTAB (Section 2.1.2: a multi-colour Gauss-Seidel
+// preconditioner B, the block lower triangle of A in red-black order, applied
+// by block substitution).  Red nodes (i + j + k even) solve with their
+// diagonal, black nodes subtract their red neighbours' values first;
+// couplings between nodes of one colour (only across a pole, when nphi/2 is
+// even) are left out of B.  scal->v: 0 rho, 1 alpha, 2 omega, 3 beta,
+// 4 rhat.v, 5 t.s, 6 t.t, 7 r.r.
+
+__device__ inline double sph_diag(const SGeom& S, const Coef& c, const double* __restrict__ isin2, int j) {
+  return -2.0 * c.ids2 - 2.0 * c.idt2 - 2.0 * isin2[j] * c.idp2;
 }
 
-// s = r - alpha v;  t = A s;  partial0 += t.s, partial1 += t.t
-__global__ __launch_bounds__(256) void k_bicg_st(const double* __restrict__ R, const double* __restrict__ Vv,
-                                                 double* __restrict__ Sv, double* __restrict__ T, SGeom S, Coef c,
-                                                 const double* __restrict__ cot2, const double* __restrict__ isin2,
-                                                 const Scalars* __restrict__ scal, double* __restrict__ partial) {
+__device__ inline bool is_red(int i, int j, int k) { return ((i + j + k) & 1) == 0; }
+
+// p = r + beta (p - omega v)   (in place);   phat = p / D on red nodes
+__global__ __launch_bounds__(256) void k_pbicg_p(const double* __restrict__ R, double* __restrict__ P,
+                                                 const double* __restrict__ Vv, double* __restrict__ Ph, SGeom S,
+                                                 Coef c, const double* __restrict__ isin2,
+                                                 const Scalars* __restrict__ scal) {
   const int i = 1 + blockIdx.x * BX + threadIdx.x;
   const int j = blockIdx.y * BY + threadIdx.y;
   const int k = blockIdx.z;
-  const double alpha = scal->v[1];
+  if (!active(S, i, j, k)) return;
+  const double beta = scal->v[3], omega = scal->v[2];
+  const long long idx = S.at(i, j, k);
+  const double pv = R[idx] + beta * (P[idx] - omega * Vv[idx]);
+  P[idx] = pv;
+  if (is_red(i, j, k)) Ph[idx] = pv / sph_diag(S, c, isin2, j);
+}
+
+// s = r - alpha v;   shat = s / D on red nodes
+__global__ __launch_bounds__(256) void k_pbicg_s(const double* __restrict__ R, const double* __restrict__ Vv,
+                                                 double* __restrict__ Sv, double* __restrict__ Sh, SGeom S, Coef c,
+                                                 const double* __restrict__ isin2,
+                                                 const Scalars* __restrict__ scal) {
+  const int i = 1 + blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  if (!active(S, i, j, k)) return;
+  const long long idx = S.at(i, j, k);
+  const double sv = R[idx] - scal->v[1] * Vv[idx];
+  Sv[idx] = sv;
+  if (is_red(i, j, k)) Sh[idx] = sv / sph_diag(S, c, isin2, j);
+}
+
+// black nodes of xhat = B^-1 y: (y - sum over red neighbours of a_n xhat_n) / D
+__global__ __launch_bounds__(256) void k_gs_black(const double* __restrict__ Y, double* __restrict__ Xh, SGeom S,
+                                                  Coef c, const double* __restrict__ cot2,
+                                                  const double* __restrict__ isin2) {
+  const int i = 1 + blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  if (!active(S, i, j, k) || is_red(i, j, k)) return;
+  const int half = S.nph >> 1;
+  // value of a neighbour if it is red, else 0 (radial ghosts of xhat are 0)
+  auto red = [&](int ii, int jj, int kk) -> double { return is_red(ii, jj, kk) ? Xh[S.at(ii, jj, kk)] : 0.0; };
+  const double cr = c.ids2 + c.i2ds, cl = c.ids2 - c.i2ds;
+  double s = cr * red(i + 1, j, k) + cl * red(i - 1, j, k);
+  const double cjp = c.idt2 + cot2[j], cjm = c.idt2 - cot2[j];
+  s += cjp * ((j + 1 < S.nth) ? red(i, j + 1, k) : red(i, S.nth - 1, (k + half) % S.nph));
+  s += cjm * ((j > 0) ? red(i, j - 1, k) : red(i, 0, (k + half) % S.nph));
+  const double cp = isin2[j] * c.idp2;
+  s += cp * (red(i, j, (k + 1) % S.nph) + red(i, j, (k + S.nph - 1) % S.nph));
+  const long long idx = S.at(i, j, k);
+  Xh[idx] = (Y[idx] - s) / sph_diag(S, c, isin2, j);
+}
+
+// out = A xhat with dots: mode 0: partial0 += a.out (a = rhat);
+// mode 1: partial0 += out.a, partial1 += out.out (a = s)
+template <int MODE>
+__global__ __launch_bounds__(256) void k_apply_dot(const double* __restrict__ Xh, double* __restrict__ Out,
+                                                   const double* __restrict__ Aw, SGeom S, Coef c,
+                                                   const double* __restrict__ cot2, const double* __restrict__ isin2,
+                                                   double* __restrict__ partial) {
+  const int i = 1 + blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
   double a0 = 0.0, a1 = 0.0;
   if (active(S, i, j, k)) {
-    auto V = [&](int ii, int jj, int kk) -> double {
-      const long long q = S.at(ii, jj, kk);
-      return R[q] - alpha * Vv[q];
-    };
+    auto V = [&](int ii, int jj, int kk) -> double { return Xh[S.at(ii, jj, kk)]; };
     const long long idx = S.at(i, j, k);
-    const double sv = V(i, j, k);
-    const double tv = sph_op(V, S, c, cot2, isin2, i, j, k);
-    Sv[idx] = sv;
-    T[idx] = tv;
-    a0 = tv * sv;
-    a1 = tv * tv;
+    const double o = sph_op(V, S, c, cot2, isin2, i, j, k);
+    Out[idx] = o;
+    a0 = Aw[idx] * o;
+    if (MODE == 1) a1 = o * o;
   }
   const double s0 = block_sum(a0);
   if (threadIdx.x == 0 && threadIdx.y == 0) partial[linear_block()] = s0;
-  const double s1 = block_sum(a1);
-  if (threadIdx.x == 0 && threadIdx.y == 0) partial[kPartialCap + linear_block()] = s1;
+  if (MODE == 1) {
+    const double s1 = block_sum(a1);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partial[kPartialCap + linear_block()] = s1;
+  }
 }
 
-// x += alpha p + omega s;  r = s - omega t;  partial0 += rhat.r, partial1 += r.r
-__global__ __launch_bounds__(256) void k_bicg_xr(double* __restrict__ X, double* __restrict__ R,
-                                                 const double* __restrict__ P, const double* __restrict__ Sv,
-                                                 const double* __restrict__ T, const double* __restrict__ Rhat,
-                                                 SGeom S, const Scalars* __restrict__ scal,
-                                                 double* __restrict__ partial) {
+// x += alpha phat + omega shat;  r = s - omega t;  partial0 += rhat.r, partial1 += r.r
+__global__ __launch_bounds__(256) void k_pbicg_xr(double* __restrict__ X, double* __restrict__ R,
+                                                  const double* __restrict__ Ph, const double* __restrict__ Sh,
+                                                  const double* __restrict__ Sv, const double* __restrict__ T,
+                                                  const double* __restrict__ Rhat, SGeom S,
+                                                  const Scalars* __restrict__ scal, double* __restrict__ partial) {
   const int i = 1 + blockIdx.x * BX + threadIdx.x;
   const int j = blockIdx.y * BY + threadIdx.y;
   const int k = blockIdx.z;
@@ -146,9 +183,8 @@ __global__ __launch_bounds__(256) void k_bicg_xr(double* __restrict__ X, double*
   double a0 = 0.0, a1 = 0.0;
   if (active(S, i, j, k)) {
     const long long idx = S.at(i, j, k);
-    const double sv = Sv[idx];
-    X[idx] += alpha * P[idx] + omega * sv;
-    const double rn = sv - omega * T[idx];
+    X[idx] += alpha * Ph[idx] + omega * Sh[idx];
+    const double rn = Sv[idx] - omega * T[idx];
     R[idx] = rn;
     a0 = Rhat[idx] * rn;
     a1 = rn * rn;
@@ -234,20 +270,32 @@ void sph_apply(const double* u, double* out, const SGeom& S, const SphCoef& c, h
   k_sph_apply<<<sgrid(S), dim3(BX, BY), 0, st>>>(u, out, S, make_coef(S), c.cot, c.isin2);
 }
 
-void bicg_p_v(const double* r, const double* p_old, const double* v_old, double* p, double* v, const double* rhat,
-              const SGeom& S, const SphCoef& c, const Scalars* scal, double* partial, hipStream_t st) {
-  k_bicg_pv<<<sgrid(S), dim3(BX, BY), 0, st>>>(r, p_old, v_old, p, v, rhat, S, make_coef(S), c.cot, c.isin2, scal,
-                                               partial);
+void pbicg_direction(const double* r, double* p, const double* v, double* phat, const SGeom& S, const SphCoef& c,
+                     const Scalars* scal, hipStream_t st) {
+  const Coef cf = make_coef(S);
+  k_pbicg_p<<<sgrid(S), dim3(BX, BY), 0, st>>>(r, p, v, phat, S, cf, c.isin2, scal);
+  k_gs_black<<<sgrid(S), dim3(BX, BY), 0, st>>>(p, phat, S, cf, c.cot, c.isin2);
 }
 
-void bicg_s_t(const double* r, const double* v, double* s, double* t, const SGeom& S, const SphCoef& c,
-              const Scalars* scal, double* partial, hipStream_t st) {
-  k_bicg_st<<<sgrid(S), dim3(BX, BY), 0, st>>>(r, v, s, t, S, make_coef(S), c.cot, c.isin2, scal, partial);
+void pbicg_s(const double* r, const double* v, double* s, double* shat, const SGeom& S, const SphCoef& c,
+             const Scalars* scal, hipStream_t st) {
+  const Coef cf = make_coef(S);
+  k_pbicg_s<<<sgrid(S), dim3(BX, BY), 0, st>>>(r, v, s, shat, S, cf, c.isin2, scal);
+  k_gs_black<<<sgrid(S), dim3(BX, BY), 0, st>>>(s, shat, S, cf, c.cot, c.isin2);
 }
 
-void bicg_xr(double* x, double* r, const double* p, const double* s, const double* t, const double* rhat,
-             const SGeom& S, const Scalars* scal, double* partial, hipStream_t st) {
-  k_bicg_xr<<<sgrid(S), dim3(BX, BY), 0, st>>>(x, r, p, s, t, rhat, S, scal, partial);
+void pbicg_apply(const double* xhat, double* out, const double* w, int mode, const SGeom& S, const SphCoef& c,
+                 double* partial, hipStream_t st) {
+  const Coef cf = make_coef(S);
+  if (mode == 0)
+    k_apply_dot<0><<<sgrid(S), dim3(BX, BY), 0, st>>>(xhat, out, w, S, cf, c.cot, c.isin2, partial);
+  else
+    k_apply_dot<1><<<sgrid(S), dim3(BX, BY), 0, st>>>(xhat, out, w, S, cf, c.cot, c.isin2, partial);
+}
+
+void pbicg_xr(double* x, double* r, const double* phat, const double* shat, const double* s, const double* t,
+              const double* rhat, const SGeom& S, const Scalars* scal, double* partial, hipStream_t st) {
+  k_pbicg_xr<<<sgrid(S), dim3(BX, BY), 0, st>>>(x, r, phat, shat, s, t, rhat, S, scal, partial);
 }
 
 void bicg_scalars(const double* partial, int nb, Scalars* scal, int stage, hipStream_t st) {

@@ -638,6 +638,8 @@ int solve_sph(poisson_plan_s* P, const double* rho, double* phi, double tol, poi
   auto restart = [&]() -> int {
     // rhat = r, rho = r.r, alpha = omega = 1, beta = 0, p = v = 0
     sph_copy(P->sr, P->srh, S, st);
+    sph_fill_zero(P->sp[0], S, st);
+    sph_fill_zero(P->sv[0], S, st);
     double init[4] = {P->host[0], 1.0, 1.0, 0.0};
     HIPCHK(hipMemcpyAsync(P->scal->v, init, sizeof init, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
@@ -647,16 +649,21 @@ int solve_sph(poisson_plan_s* P, const double* rho, double* phi, double tol, poi
     P->host[0] = P->host[1];
     CHK(restart());
   }
-  int cur = 0;
+  // right-preconditioned BiCGSTAB with the red-black Gauss-Seidel
+  // preconditioner: p, v, phat, shat, s, t
+  double* p = P->sp[0];
+  double* phat = P->sp[1];
+  double* v = P->sv[0];
+  double* shat = P->sv[1];
   while (!conv && it < o.max_iter) {
-    const int nxt = cur ^ 1;
-    bicg_p_v(P->sr, P->sp[cur], P->sv[cur], P->sp[nxt], P->sv[nxt], P->srh, S, P->sc, P->scal, P->partial, st);
+    pbicg_direction(P->sr, p, v, phat, S, P->sc, P->scal, st);
+    pbicg_apply(phat, v, P->srh, 0, S, P->sc, P->partial, st);
     bicg_scalars(P->partial, nb, P->scal, 0, st);
-    bicg_s_t(P->sr, P->sv[nxt], P->ss, P->stt, S, P->sc, P->scal, P->partial, st);
+    pbicg_s(P->sr, v, P->ss, shat, S, P->sc, P->scal, st);
+    pbicg_apply(shat, P->stt, P->ss, 1, S, P->sc, P->partial, st);
     bicg_scalars(P->partial, nb, P->scal, 1, st);
-    bicg_xr(phi, P->sr, P->sp[nxt], P->ss, P->stt, P->srh, S, P->scal, P->partial, st);
+    pbicg_xr(phi, P->sr, phat, shat, P->ss, P->stt, P->srh, S, P->scal, P->partial, st);
     bicg_scalars(P->partial, nb, P->scal, 2, st);
-    cur = nxt;
     ++it;
     if (it % o.check_every == 0 || it == o.max_iter) {
       CHK(launch_check("BiCGSTAB"));
@@ -676,8 +683,6 @@ int solve_sph(poisson_plan_s* P, const double* rho, double* phi, double tol, poi
           set_error("BiCGSTAB breakdown persisted after restarts");
           return POISSON_ENUMERIC;
         }
-        sph_fill_zero(P->sp[cur], S, st);
-        sph_fill_zero(P->sv[cur], S, st);
         P->host[0] = rr;
         CHK(restart());
       }
