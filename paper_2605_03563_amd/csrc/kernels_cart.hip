@@ -16,6 +16,7 @@ namespace {
 constexpr int BX = 64;   // threads along a compact row
 constexpr int BY = 4;    // rows per block
 constexpr int KZ = 8;    // planes marched per thread
+constexpr int TBY = 8;   // rows per block of the LDS-staged 19-point kernels
 
 // 19-point star weights (6th-order central second difference per axis)
 constexpr double kC0 = -49.0 / 18.0, kC1 = 1.5, kC2 = -3.0 / 20.0, kC3 = 1.0 / 90.0;
@@ -29,6 +30,14 @@ inline dim3 col_grid(const Geom& G) {
   const int E = G.n - 1;
   const int kz = kz_for(G);
   return dim3((mc + BX - 1) / BX, (E + BY - 1) / BY, (E + kz - 1) / kz);
+}
+
+// grid of the LDS-staged 19-point kernels (64 x 8 threads per block)
+inline dim3 staged_grid(const Geom& G) {
+  const int mc = G.mhi() - G.mlo() + 1;
+  const int E = G.n - 1;
+  const int kz = kz_for(G);
+  return dim3((mc + BX - 1) / BX, (E + TBY - 1) / TBY, (E + kz - 1) / kz);
 }
 
 __device__ inline int planes_per_block(const Geom& G) { return (G.n - 1 + (int)gridDim.z - 1) / (int)gridDim.z; }
@@ -116,43 +125,190 @@ __global__ __launch_bounds__(256) void k_pass7(T* __restrict__ X, const T* __res
   }
 }
 
-// four-colour pass of the 19-point star; colours whose bit is set in zmask
-// are taken as 0 (first forward sweep on a zeroed correction).
+// ---------------------------------------------------------------- 19-point star
+// Both kernels keep a register window along z: the values at the thread's own
+// compact column of rows b for planes k-3..k+3, so each plane costs one new
+// load per colour.  The residual kernel stages the window's centre plane, three
+// halo rows above and below and one halo column on each side in an LDS tile
+// (64 x TBY threads march planes in lock step) and reads x- and y-neighbours
+// from it; the pass kernel takes x-neighbours from the adjacent lanes instead
+// and needs no barrier.  The node at position q of a compact column in a row
+// with colour shift s has colour (q + s) mod 4.
+constexpr int TROWS = TBY + 6;
+constexpr int TCOLS = BX + 2;
+
+// Four-colour pass without LDS or barriers: the register window along z
+// holds the three other colours at the thread's compact column for planes
+// k-3..k+3; x-neighbours in the adjacent compact columns come from the
+// neighbouring lanes of the wavefront (one wavefront = 64 consecutive columns
+// of one row), the wavefront's edge lanes load theirs; y-neighbours are loaded.
 template <typename T>
-__global__ __launch_bounds__(256) void k_pass19(T* __restrict__ X, const T* __restrict__ F, Geom G, int c,
-                                                T h2, int zmask) {
+__global__ __launch_bounds__(256) void k_pass19w(T* __restrict__ X, const T* __restrict__ F, Geom G, int c, T h2,
+                                                 int zmask) {
   int bx, by, bz;
   xcd_block(bx, by, bz);
-  const int m = G.mlo() + bx * BX + (int)threadIdx.x;
+  const int tx = threadIdx.x;
+  const int m = G.mlo() + bx * BX + tx;
   const int b = G.g + by * BY + (int)threadIdx.y;
   const int last = G.g + G.n - 2;
-  if (m > G.mhi() || b > last) return;
   const int kz = planes_per_block(G);
   const int k0 = G.g + bz * kz;
   const int k1 = min(k0 + kz - 1, last);
-  const bool z1 = (zmask >> ((c + 1) & 3)) & 1, z2 = (zmask >> ((c + 2) & 3)) & 1,
-             z3 = (zmask >> ((c + 3) & 3)) & 1;
-  const T* __restrict__ X1 = X + (long long)((c + 1) & 3) * G.cs;  // colour c+1 (= c-3)
-  const T* __restrict__ X2 = X + (long long)((c + 2) & 3) * G.cs;  // colour c+2 (= c-2)
-  const T* __restrict__ X3 = X + (long long)((c + 3) & 3) * G.cs;  // colour c+3 (= c-1)
+  const bool rowok = b <= last;
+  const bool colok = m < G.W;
+  const T* P[3];
+  bool zero[3];
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int col = (c + e + 1) & 3;
+    P[e] = X + (long long)col * G.cs;
+    zero[e] = (zmask >> col) & 1;
+  }
+  const long long plane = (long long)G.M * G.W;
+  const long long cb = (long long)b * G.W + m;
+  const bool live = rowok && colok;
+  T win[7][3];
+#pragma unroll
+  for (int d = -3; d <= 2; ++d)
+#pragma unroll
+    for (int e = 0; e < 3; ++e) win[d + 3][e] = (live && !zero[e]) ? P[e][(k0 + d) * plane + cb] : (T)0;
   T* __restrict__ Xc = X + (long long)c * G.cs;
   const T* __restrict__ Fc = F + (long long)c * G.cs;
   const T inv = (T)(1.0 / (3.0 * kC0));
   for (int k = k0; k <= k1; ++k) {
-    const int a = 4 * m + ((c - b - k - G.off) & 3);
-    if (!G.inner(a)) continue;
-    const long long row = G.row(b, k);
-    // offset +d has colour c+d, offset -d colour c-d (mod 4)
-    T s1 = (T)0, s2 = (T)0, s3 = (T)0;
-    if (!z1) s1 += X1[row + ((a + 1) >> 2)] + X1[G.row(b + 1, k) + m] + X1[G.row(b, k + 1) + m];
-    if (!z3) s1 += X3[row + ((a - 1) >> 2)] + X3[G.row(b - 1, k) + m] + X3[G.row(b, k - 1) + m];
-    if (!z2)
-      s2 = X2[row + ((a + 2) >> 2)] + X2[row + ((a - 2) >> 2)] + X2[G.row(b + 2, k) + m] +
-           X2[G.row(b - 2, k) + m] + X2[G.row(b, k + 2) + m] + X2[G.row(b, k - 2) + m];
-    if (!z3) s3 += X3[row + ((a + 3) >> 2)] + X3[G.row(b + 3, k) + m] + X3[G.row(b, k + 3) + m];
-    if (!z1) s3 += X1[row + ((a - 3) >> 2)] + X1[G.row(b - 3, k) + m] + X1[G.row(b, k - 3) + m];
-    const T s = (T)kC1 * s1 + (T)kC2 * s2 + (T)kC3 * s3;
-    store_stream(Xc + row + m, (h2 * Fc[row + m] - s) * inv);
+#pragma unroll
+    for (int e = 0; e < 3; ++e) win[6][e] = (live && !zero[e]) ? P[e][(k + 3) * plane + cb] : (T)0;
+    // neighbouring compact columns from the adjacent lanes
+    T lft[3], rgt[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      lft[e] = __shfl_up(win[3][e], 1, 64);
+      rgt[e] = __shfl_down(win[3][e], 1, 64);
+    }
+    const long long row = k * plane + (long long)b * G.W;
+    if (tx == 0 && live && m >= 1) {
+#pragma unroll
+      for (int e = 0; e < 3; ++e) lft[e] = zero[e] ? (T)0 : P[e][row + m - 1];
+    }
+    if (tx == BX - 1 && live && m + 1 < G.W) {
+#pragma unroll
+      for (int e = 0; e < 3; ++e) rgt[e] = zero[e] ? (T)0 : P[e][row + m + 1];
+    }
+    if (live && m <= G.mhi()) {
+      const int q = (c - b - k - G.off) & 3;  // position of the colour-c node in the column
+      const int a = 4 * m + q;
+      if (G.inner(a)) {
+        // colour c+d (e = d-1 for d = 1..3, colour c-d = c+4-d: e = 3-d) at compact (a+-d)>>2
+        auto xval = [&](int d, int e) -> T {
+          const int mm = (a + d) >> 2;
+          return mm < m ? lft[e] : (mm > m ? rgt[e] : win[3][e]);
+        };
+        auto yv = [&](int d, int e) -> T { return zero[e] ? (T)0 : P[e][row + (long long)d * G.W + m]; };
+        const T s1 = xval(1, 0) + xval(-1, 2) + yv(1, 0) + yv(-1, 2) + win[4][0] + win[2][2];
+        const T s2 = xval(2, 1) + xval(-2, 1) + yv(2, 1) + yv(-2, 1) + win[5][1] + win[1][1];
+        const T s3 = xval(3, 2) + xval(-3, 0) + yv(3, 2) + yv(-3, 0) + win[6][2] + win[0][0];
+        const T sum = (T)kC1 * s1 + (T)kC2 * s2 + (T)kC3 * s3;
+        store_stream(Xc + row + m, (h2 * Fc[row + m] - sum) * inv);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d)
+#pragma unroll
+      for (int e = 0; e < 3; ++e) win[d][e] = win[d + 1][e];
+  }
+}
+
+// Residual of the 19-point star for all four nodes of a compact column.  The
+// register window and the LDS tile are indexed by the node's position q in
+// its compact column (colour (q + shift) mod 4 of that row), so every register
+// index is a compile-time constant; the colour rotation goes into the load
+// and store addresses.
+template <typename T, typename TO>
+__global__ __launch_bounds__(BX * TBY) void k_residual19s(const T* __restrict__ X, const T* __restrict__ F,
+                                                          TO* __restrict__ R, Geom G, T ih2,
+                                                          double* __restrict__ partial) {
+  __shared__ T tile[TROWS][4][TCOLS];
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int m0 = G.mlo() + bx * BX;
+  const int m = m0 + tx;
+  const int b0 = G.g + by * TBY;
+  const int b = b0 + ty;
+  const int last = G.g + G.n - 2;
+  const int kz = planes_per_block(G);
+  const int k0 = G.g + bz * kz;
+  const int k1 = min(k0 + kz - 1, last);
+  const bool colok = m < G.W;
+  const bool rowok = b < G.M;
+  const long long plane = (long long)G.M * G.W;
+  const long long cb = (long long)b * G.W + m;
+  // value at position q of compact column mm in row bb of plane kk
+  auto load = [&](int bb, int kk, int mm, int q) -> T {
+    const int col = (q + bb + kk + G.off) & 3;
+    return X[(long long)col * G.cs + kk * plane + (long long)bb * G.W + mm];
+  };
+  T win[7][4];  // win[d + 3][q] at (m, b, k + d)
+#pragma unroll
+  for (int d = -3; d <= 2; ++d)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) win[d + 3][q] = (colok && rowok) ? load(b, k0 + d, m, q) : (T)0;
+  double acc = 0.0;
+  for (int k = k0; k <= k1; ++k) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) win[6][q] = (colok && rowok) ? load(b, k + 3, m, q) : (T)0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tile[ty + 3][q][tx + 1] = win[3][q];
+    if (ty < 6) {
+      const int hb = ty < 3 ? b0 - 3 + ty : b0 + TBY + (ty - 3);
+      const int tr = ty < 3 ? ty : TBY + ty;
+      const bool ok = hb >= 0 && hb < G.M && colok;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tile[tr][q][tx + 1] = ok ? load(hb, k, m, q) : (T)0;
+    }
+    if (tx < 2) {
+      const int hm = tx == 0 ? m0 - 1 : m0 + BX;
+      const int tc = tx == 0 ? 0 : BX + 1;
+      for (int tr = ty; tr < TROWS; tr += TBY) {
+        const int hb = b0 - 3 + tr;
+        const bool ok = hb >= 0 && hb < G.M && hm >= 0 && hm < G.W;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) tile[tr][q][tc] = ok ? load(hb, k, hm, q) : (T)0;
+      }
+    }
+    __syncthreads();
+    if (m <= G.mhi() && b <= last) {
+      const int s = (b + k + G.off) & 3;
+      const int r0 = ty + 3;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int a = 4 * m + q;
+        if (!G.inner(a)) continue;
+        T sd[3];
+#pragma unroll
+        for (int d = 1; d <= 3; ++d) {
+          // x: positions q +- d, possibly in the neighbouring compact column
+          const int qp = q + d, qm = q - d;
+          const T xp = tile[r0][qp & 3][tx + 1 + (qp >> 2)];
+          const T xm = tile[r0][qm & 3][tx + 1 + (qm >> 2)];
+          sd[d - 1] = xp + xm + tile[r0 + d][q][tx + 1] + tile[r0 - d][q][tx + 1] + win[3 + d][q] + win[3 - d][q];
+        }
+        const T lap = ((T)(3.0 * kC0) * win[3][q] + (T)kC1 * sd[0] + (T)kC2 * sd[1] + (T)kC3 * sd[2]) * ih2;
+        const long long idx = (long long)((q + s) & 3) * G.cs + k * plane + cb;
+        const T res = F[idx] - lap;
+        if (R) R[idx] = (TO)res;
+        acc += (double)res * (double)res;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int d = 0; d < 6; ++d)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) win[d][q] = win[d + 1][q];
+  }
+  if (partial) {
+    const double sum = block_sum(acc);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partial[linear_block()] = sum;
   }
 }
 
@@ -165,14 +321,14 @@ __global__ __launch_bounds__(256) void k_pass19(T* __restrict__ X, const T* __re
 // positions.  Partial sums of r^2 (in FP64) per block when partial != nullptr;
 // ZU treats the unknowns of u as zero (norm of b).
 template <typename T, typename TO, int ORDER, bool ZU>
-__global__ __launch_bounds__(256) void k_residual(const T* __restrict__ X, const T* __restrict__ F,
+__global__ __launch_bounds__(512) void k_residual(const T* __restrict__ X, const T* __restrict__ F,
                                                   TO* __restrict__ R, Geom G, T ih2,
                                                   double* __restrict__ partial) {
   constexpr int C = ORDER == 2 ? 2 : 4;
   int bx, by, bz;
   xcd_block(bx, by, bz);
   const int m = G.mlo() + bx * BX + (int)threadIdx.x;
-  const int b = G.g + by * BY + (int)threadIdx.y;
+  const int b = G.g + by * (int)blockDim.y + (int)threadIdx.y;  // launched with 4 or 8 rows per block
   const int last = G.g + G.n - 2;
   double acc = 0.0;
   if (m <= G.mhi() && b <= last) {
@@ -767,9 +923,9 @@ void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, i
     }
   } else {
     if (f32)
-      k_pass19<float><<<grid, blk, 0, st>>>((float*)phi, (const float*)f, G, colour, (float)h2, zmask);
+      k_pass19w<float><<<grid, blk, 0, st>>>((float*)phi, (const float*)f, G, colour, (float)h2, zmask);
     else
-      k_pass19<double><<<grid, blk, 0, st>>>((double*)phi, (const double*)f, G, colour, h2, zmask);
+      k_pass19w<double><<<grid, blk, 0, st>>>((double*)phi, (const double*)f, G, colour, h2, zmask);
   }
 }
 
@@ -784,14 +940,16 @@ static void residual_t(const T* phi, const T* f, TO* r, const Geom& G, int order
     else
       k_residual7<T, TO><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
   } else {
+    // both variants launch on the staged grid so that partial-sum counts agree
+    const dim3 sg = staged_grid(G), sb(BX, TBY);
     if (zu)
-      k_residual<T, TO, 6, true><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
+      k_residual<T, TO, 6, true><<<sg, sb, 0, st>>>(phi, f, r, G, ih2, partial);
     else
-      k_residual<T, TO, 6, false><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
+      k_residual19s<T, TO><<<sg, sb, 0, st>>>(phi, f, r, G, ih2, partial);
   }
 }
 
-int residual_blocks(const Geom& G) { return (int)nblocks(col_grid(G)); }
+int residual_blocks(const Geom& G) { return (int)nblocks(G.C == 4 ? staged_grid(G) : col_grid(G)); }
 
 void residual(const void* phi, const void* f, bool in_f32, void* r_out, bool out_f32, const Geom& G, int order,
               bool zu, double* partial, hipStream_t st) {
