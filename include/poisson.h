@@ -60,10 +60,23 @@ extern "C" {
 
 #define POISSON_SOR            0  /* red-black SOR (Section 2.1.1) */
 #define POISSON_CG             1  /* conjugate gradients (Section 2.1.2) */
-#define POISSON_BICGSTAB       2  /* BiCGSTAB, spherical grids (Section 2.1.2) */
+#define POISSON_BICGSTAB       2  /* BiCGSTAB, spherical grids (Section 2.1.2), right-preconditioned
+                                     by one red-black Gauss-Seidel step (Section 2.1.1) */
 #define POISSON_MG             3  /* FP64 geometric multigrid V-cycles (Section 2.1.3) */
 #define POISSON_MG_IR32        4  /* FP32 V-cycles inside FP64 iterative refinement */
-#define POISSON_BICGSTAB_MG32  5  /* BiCGSTAB right-preconditioned by one FP32 V-cycle */
+#define POISSON_BICGSTAB_MG32  5  /* spherical grids: BiCGSTAB right-preconditioned by one FP32
+                                     V(nu1, nu2) cycle (four-colour Gauss-Seidel, cell-pair
+                                     coarsening); every axis must halve evenly down to a
+                                     level of <= 4096 unknowns, solved by a dense inverse */
+#define POISSON_MG_SPAI        6  /* Cartesian FP64 V(nu1, nu2) cycles with the SPAI Richardson
+                                     smoother of Table 1 (Eqs. richardson, Smoother), Galerkin
+                                     coarse operators R A P and compact radius-1 stencils:
+                                     order 2 (7-point) or 4 (19-point Mehrstellen, right-hand
+                                     side (6 f + face sum) / 12); coarsest level solved by a
+                                     dense inverse (Section 2.1.3) */
+#define POISSON_MG_SPAI32      7  /* POISSON_MG_SPAI with every level below the finest stored in
+                                     FP32 and all arithmetic in FP64 (the paper's mixed
+                                     precision, Section 2.1.3) */
 
 #define POISSON_OMEGA_OPT       0 /* 2/(1+sqrt(1-rJ^2)), rJ from Eq. rjac */
 #define POISSON_OMEGA_OPT_A     1 /* 2/(1+pi/N) */
@@ -84,8 +97,9 @@ typedef struct {
 } poisson_grid_t;
 
 typedef struct {
-    int32_t method;      /* POISSON_SOR .. POISSON_BICGSTAB_MG32 */
-    int32_t order;       /* Cartesian: 2 (7-point) or 6 (19-point star); spherical: 2 */
+    int32_t method;      /* POISSON_SOR .. POISSON_MG_SPAI32 */
+    int32_t order;       /* Cartesian: 2 (7-point) or 6 (19-point star); POISSON_MG_SPAI(32):
+                            2 or 4 (compact); spherical: 2 */
     int32_t lmax;        /* >= 0: multipole boundary of this order (<= 8);
                             -1: ghost values are read from Phi as given (Section 2.2 test mode) */
     int32_t nu1, nu2;    /* multigrid pre/post smoothing sweeps */
@@ -112,8 +126,9 @@ typedef struct {
     int32_t history_len;      /* entries written */
 } poisson_stats_t;
 
-/* Default options for a method (order 2, lmax 8, V(2,2) to 8 intervals,
-   max_iter 10000, check_every 1, four_pi_G 1). */
+/* Default options for a method (order 2, lmax 8, V(2,2) to 8 intervals --
+   V(3,3) for POISSON_MG_SPAI(32), the paper's choice --, max_iter 10000,
+   check_every 1, four_pi_G 1). */
 void poisson_default_opts(poisson_opts_t* opts, int32_t method);
 
 /* Bytes of device workspace a plan for (grid, opts) needs.  Returns 0 and
@@ -165,18 +180,23 @@ const char* poisson_last_error(void);
 
 /* d_out[unknowns] = (L_h Phi) on the unknown nodes (Cartesian: 7-point or
    19-point star by opts.order; spherical: the r^2-scaled operator).  Other
-   entries of d_out are left untouched. */
+   entries of d_out are left untouched.  POISSON_EINVAL for POISSON_MG_SPAI
+   plans, whose operator is exposed through poisson_op_residual. */
 int poisson_op_apply(poisson_plan_t plan, const double* d_phi, double* d_out);
 
-/* d_res[unknowns] = 4 pi G rho - L_h Phi (spherical: r^2-scaled), and
-   *h_norm2 = sum of squares over the unknowns (NULL to skip; synchronises). */
+/* d_res[unknowns] = 4 pi G rho - L_h Phi (spherical: r^2-scaled;
+   POISSON_MG_SPAI: 4 pi G B rho - L_h Phi with the compact stencil and its
+   right-hand side operator B), and *h_norm2 = sum of squares over the
+   unknowns (NULL to skip; synchronises). */
 int poisson_op_residual(poisson_plan_t plan, const double* d_rho, const double* d_phi,
                         double* d_res, double* h_norm2);
 
 /* `sweeps` full Gauss-Seidel/SOR sweeps in place on the unknowns of d_phi
    (Cartesian): colours in increasing order when forward != 0, reversed
    otherwise; red-black with relaxation omega for order 2 (Section 2.1.1),
-   four colours with omega = 1 for order 6 (Section 2.1.2). */
+   four colours with omega = 1 for order 6 (Section 2.1.2).  POISSON_MG_SPAI
+   plans: `sweeps` steps of the SPAI Richardson smoother (Eq. richardson;
+   forward and omega are ignored). */
 int poisson_op_smooth(poisson_plan_t plan, const double* d_rho, double* d_phi, int32_t sweeps,
                       int32_t forward, double omega);
 
@@ -187,17 +207,18 @@ int poisson_op_restrict(poisson_plan_t plan, const double* d_fine, double* d_coa
 /* d_fine += P d_coarse, P = 8 R^T (trilinear), dense interior arrays as above. */
 int poisson_op_prolong_add(poisson_plan_t plan, const double* d_coarse, double* d_fine);
 
-/* `cycles` V(nu1,nu2) cycles (MG or MG_IR32 plans use their own precision;
-   for MG_IR32 one cycle = one refinement step) on d_phi with the ghosts as
-   given, no convergence test. */
+/* `cycles` V(nu1,nu2) cycles (MG, MG_IR32 or MG_SPAI plans, each in its own
+   precision; for MG_IR32 one cycle = one refinement step) on d_phi with the
+   ghosts as given, no convergence test. */
 int poisson_op_vcycle(poisson_plan_t plan, const double* d_rho, double* d_phi, int32_t cycles);
 
 /* `sweeps` forward Gauss-Seidel sweeps (omega = 1) on the plan's resident
    fine-level arrays exactly as the last poisson_solve / poisson_op_* call
    left them, with no layout conversion: the smoother kernel alone, for
    timing it in its solver launch configuration.  MG / MG_IR32 plans sweep
-   their cycle's finest level (FP64 or FP32); other Cartesian plans the FP64
-   potential. */
+   their cycle's finest level (FP64 or FP32); MG_SPAI plans take SPAI steps
+   (residual kernel + smoother kernel) on theirs; other Cartesian plans sweep
+   the FP64 potential. */
 int poisson_op_sweep_resident(poisson_plan_t plan, int32_t sweeps);
 
 /* ---- serving loop: continuous batching of independent solves -----------

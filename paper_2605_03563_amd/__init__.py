@@ -15,11 +15,11 @@ from typing import Optional
 import torch
 
 from . import _lib as L
-from ._lib import (BICGSTAB, BICGSTAB_MG32, CARTESIAN, CG, MG, MG_IR32, OMEGA_CHEBYSHEV, OMEGA_FIXED,
+from ._lib import (BICGSTAB, BICGSTAB_MG32, CARTESIAN, CG, MG, MG_IR32, MG_SPAI, MG_SPAI32, OMEGA_CHEBYSHEV, OMEGA_FIXED,
                    OMEGA_OPT, OMEGA_OPT_A, SOR, SPHERICAL_LOG, WARN_MAXITER)
 
 METHODS = {"sor": SOR, "cg": CG, "bicgstab": BICGSTAB, "mg": MG, "mg_ir32": MG_IR32,
-           "bicgstab_mg32": BICGSTAB_MG32}
+           "bicgstab_mg32": BICGSTAB_MG32, "mg_spai": MG_SPAI, "mg_spai32": MG_SPAI32}
 
 
 class PoissonError(RuntimeError):
@@ -83,11 +83,17 @@ def array_shape(grid) -> tuple:
     return (grid.n[2], grid.n[1], grid.pitch[0])
 
 
-def options(method="mg", order=2, lmax=8, nu1=2, nu2=2, coarsest=8, omega_mode=OMEGA_OPT, omega=1.0,
+def options(method="mg", order=2, lmax=8, nu1=None, nu2=None, coarsest=8, omega_mode=OMEGA_OPT, omega=1.0,
             max_iter=10000, check_every=1, four_pi_G=1.0, point_mass=0.0):
+    """Solver options; nu1 / nu2 default to the library's per-method values
+    (V(2,2), V(3,3) for the SPAI multigrid)."""
     o = L.Opts()
     L.load().poisson_default_opts(C.byref(o), METHODS[method] if isinstance(method, str) else method)
-    o.order, o.lmax, o.nu1, o.nu2, o.coarsest = order, lmax, nu1, nu2, coarsest
+    o.order, o.lmax, o.coarsest = order, lmax, coarsest
+    if nu1 is not None:
+        o.nu1 = nu1
+    if nu2 is not None:
+        o.nu2 = nu2
     o.omega_mode, o.omega, o.max_iter, o.check_every = omega_mode, omega, max_iter, check_every
     o.four_pi_G, o.point_mass = four_pi_G, point_mass
     return o

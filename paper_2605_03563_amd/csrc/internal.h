@@ -65,6 +65,44 @@ struct SGeom {
   __host__ __device__ long long at(int i, int j, int k) const { return (long long)k * p1 + (long long)j * p0 + i; }
 };
 
+// One level of the FP32 multigrid preconditioner on the log-spherical grid:
+// nr x nth x nph unknowns in [phi][theta][r] layout with one zero radial
+// ghost on each side; level l pairs the nodes of level l-1 two by two along
+// each axis (spacings doubled, colatitudes (j + 1/2) pi / nth).
+struct SLev {
+  int nr, nth, nph, p0;  // unknowns, row pitch
+  long long p1;          // plane pitch
+  float ids2, i2ds, idt2, idp2;
+  float* u;
+  float* f;
+  float* r;
+  const float* cot2;   // cot(theta_j) / (2 dtheta)
+  const float* isin2;  // 1 / sin^2(theta_j)
+  // phi-line solver: each line splits into nseg segments of seg nodes; a
+  // block holds nl lines; per colatitude j the table at ltab + j * tstride
+  // holds the segment elimination factors m[seg], c'[seg], the responses
+  // v[seg], w[seg] to unit end loads and the 2nseg x 2nseg interface inverse
+  int seg, nseg, nl, tstride;
+  const float* ltab;
+  __host__ __device__ long long at(int i, int j, int k) const { return (long long)k * p1 + (long long)j * p0 + i; }
+  __host__ __device__ long long count() const { return p1 * nph; }
+};
+
+// Natural-layout level of the SPAI multigrid: nodes 0..n per axis (one
+// ghost layer), x pitch W (a multiple of 32), plane pitch P = (n + 1) W.
+struct NGeom {
+  int n, W;
+  long long P;
+  double h;
+  __host__ __device__ long long at(int i, int j, int k) const { return (long long)k * P + (long long)j * W + i; }
+  __host__ __device__ long long total() const { return (long long)(n + 1) * P; }
+};
+
+// Cubically symmetric 27-point stencil: centre, face, edge, corner weights.
+struct W4 {
+  double c, f, e, k;
+};
+
 // Per-plan device scalars used by the Krylov solvers and reductions.
 struct Scalars {
   double v[32];
@@ -141,11 +179,48 @@ void pbicg_direction(const double* r, double* p, const double* v, double* phat, 
                      const SphCoef& c, const Scalars* scal, hipStream_t st);
 void pbicg_s(const double* r, const double* v, double* s, double* shat, const SGeom& S, const SphCoef& c,
              const Scalars* scal, hipStream_t st);
+// the same vector updates without the Gauss-Seidel preconditioner
+void pbicg_update_p(const double* r, double* p, const double* v, const SGeom& S, const SphCoef& c,
+                    const Scalars* scal, hipStream_t st);
+void pbicg_update_s(const double* r, const double* v, double* s, const SGeom& S, const SphCoef& c,
+                    const Scalars* scal, hipStream_t st);
 void pbicg_apply(const double* xhat, double* out, const double* w, int mode, const SGeom& S,
                  const SphCoef& c, double* partial, hipStream_t st);
 void pbicg_xr(double* x, double* r, const double* phat, const double* shat, const double* s, const double* t,
               const double* rhat, const SGeom& S, const Scalars* scal, double* partial, hipStream_t st);
+// FP32 multigrid preconditioner on the spherical grid.  The smoother is
+// zebra phi-line Gauss-Seidel: the lines (i, j) with (i + j) & 1 == colour
+// are solved exactly along phi (a periodic tridiagonal system), with the
+// neighbours in r and theta -- the other colour -- held fixed; across a pole
+// a line meets itself half a turn away, and that coupling is taken from the
+// values before the pass.
+void sph_line_pass(const SLev& L, int colour, hipStream_t st);
+void sph_residual32(const SLev& L, hipStream_t st);
+void sph_restrict32(const SLev& Lf, const SLev& Lc, hipStream_t st);
+void sph_prolong_add32(const SLev& Lc, const SLev& Lf, hipStream_t st);
+void sph_coarse32(const double* inv, const SLev& L, hipStream_t st);
+void sph_cast_in(const double* x, const SGeom& S, const SLev& L0, hipStream_t st);
+void sph_cast_out(const SLev& L0, double* x, const SGeom& S, hipStream_t st);
 void bicg_scalars(const double* partial, int nb, Scalars* scal, int stage, hipStream_t st);
+// SPAI multigrid on natural-layout levels (27-point stencils).
+NGeom make_ngeom(int n, double h);
+long long n27_blocks(const NGeom& G);
+// r = f - A u at the unknowns (r may be nullptr with norm); norm: one partial
+// sum of r^2 per block.  f32: the level is stored in FP32 (arithmetic FP64).
+void n27_residual(const void* u, const void* f, void* r, bool f32, const NGeom& G, const W4& A, bool norm,
+                  double* partial, hipStream_t st);
+// u -= M r (M includes omega h^2)
+void n27_update(const void* r, void* u, bool f32, const NGeom& G, const W4& M, hipStream_t st);
+void n_restrict(const void* r, bool f32_fine, const NGeom& Gf, void* fc, bool f32_coarse, const NGeom& Gc,
+                hipStream_t st);
+void n_prolong_add(const void* uc, bool f32_coarse, const NGeom& Gc, void* uf, bool f32_fine, const NGeom& Gf,
+                   hipStream_t st);
+void n_coarse(const double* inv, const void* f, void* u, bool f32, const NGeom& G, hipStream_t st);
+void n_from_caller(const double* src, long long p0, long long p1, double* u, const NGeom& G, bool zero_inner,
+                   hipStream_t st);
+void n_rhs(const double* rho, long long p0, long long p1, double* f, const NGeom& G, int order, double scale,
+           hipStream_t st);
+void n_to_caller(const double* u, const NGeom& G, double* dst, long long p0, long long p1, hipStream_t st);
 int sph_blocks(const SGeom& S);
 void sph_fill_zero(double* x, const SGeom& S, hipStream_t st);
 void sph_copy(const double* src, double* dst, const SGeom& S, hipStream_t st);

@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_pbicg_p(const double* __restrict__ R, d
   const long long idx = S.at(i, j, k);
   const double pv = R[idx] + beta * (P[idx] - omega * Vv[idx]);
   P[idx] = pv;
-  if (is_red(i, j, k)) Ph[idx] = pv / sph_diag(S, c, isin2, j);
+  if (Ph && is_red(i, j, k)) Ph[idx] = pv / sph_diag(S, c, isin2, j);
 }
 
 // s = r - alpha v;   shat = s / D on red nodes
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_pbicg_s(const double* __restrict__ R, c
   const long long idx = S.at(i, j, k);
   const double sv = R[idx] - scal->v[1] * Vv[idx];
   Sv[idx] = sv;
-  if (is_red(i, j, k)) Sh[idx] = sv / sph_diag(S, c, isin2, j);
+  if (Sh && is_red(i, j, k)) Sh[idx] = sv / sph_diag(S, c, isin2, j);
 }
 
 // black nodes of xhat = B^-1 y: (y - sum over red neighbours of a_n xhat_n) / D
@@ -239,6 +239,154 @@ __global__ __launch_bounds__(256) void k_sph_copy(const double* __restrict__ a, 
   b[S.at(i, j, k)] = a[S.at(i, j, k)];
 }
 
+// ---------------------------------------------------------------- FP32 multigrid preconditioner
+// off-diagonal part of the level operator at unknown (i, j, k) (array index i+1)
+__device__ inline float slev_off(const SLev& L, int i, int j, int k) {
+  const int half = L.nph >> 1;
+  const int a = i + 1;
+  auto u = [&](int aa, int jj, int kk) -> float { return L.u[L.at(aa, jj, kk)]; };
+  const float jp = (j + 1 < L.nth) ? u(a, j + 1, k) : u(a, L.nth - 1, (k + half) % L.nph);
+  const float jm = (j > 0) ? u(a, j - 1, k) : u(a, 0, (k + half) % L.nph);
+  const float kp = u(a, j, (k + 1) % L.nph), km = u(a, j, (k + L.nph - 1) % L.nph);
+  return (L.ids2 + L.i2ds) * u(a + 1, j, k) + (L.ids2 - L.i2ds) * u(a - 1, j, k) + (L.idt2 + L.cot2[j]) * jp +
+         (L.idt2 - L.cot2[j]) * jm + L.isin2[j] * L.idp2 * (kp + km);
+}
+
+__device__ inline float slev_diag(const SLev& L, int j) {
+  return -2.0f * L.ids2 - 2.0f * L.idt2 - 2.0f * L.isin2[j] * L.idp2;
+}
+
+// One zebra colour of phi-line Gauss-Seidel.  Block (x, j) takes nl lines
+// i = 2 (x nl + line) + ((j + colour) & 1) at colatitude j; thread
+// (line, segment) eliminates its segment of seg nodes with the tabulated
+// factors (y = T^-1 d, T the segment's tridiagonal block), the segment ends
+// meet in the interface system X = G E (X: line values at segment ends,
+// E: the y values there), and each segment then adds the end loads:
+// x = y - a (x_left v + x_right w).  Y lives in LDS as [seg][thread].
+__global__ __launch_bounds__(1024) void k_sline(SLev L, int colour) {
+  extern __shared__ float lds[];
+  const int nt = blockDim.x;
+  const int t = threadIdx.x;
+  const int line = t % L.nl, sgi = t / L.nl;
+  const int j = blockIdx.y;
+  const int i = 2 * (blockIdx.x * L.nl + line) + ((j + colour) & 1);
+  const int SL = L.seg, P = L.nseg;
+  float* Y = lds;
+  float* E = lds + (size_t)SL * nt;
+  const float* tb = L.ltab + (size_t)j * L.tstride;
+  const float* m = tb;
+  const float* cp = tb + SL;
+  const float* v = tb + 2 * SL;
+  const float* w = tb + 3 * SL;
+  const float* G = tb + 4 * SL;
+  const bool act = i < L.nr;
+  const float aphi = L.isin2[j] * L.idp2;
+  const int k0 = sgi * SL;
+  if (act) {
+    const int a = i + 1, half = L.nph >> 1;
+    const float cr = L.ids2 + L.i2ds, cl = L.ids2 - L.i2ds;
+    const float cjp = L.idt2 + L.cot2[j], cjm = L.idt2 - L.cot2[j];
+    float d = 0.0f;
+#pragma unroll 8
+    for (int q = 0; q < SL; ++q) {
+      const int k = k0 + q;
+      const long long idx = L.at(a, j, k);
+      const float up = (j + 1 < L.nth) ? L.u[idx + L.p0] : L.u[L.at(a, j, (k + half) % L.nph)];
+      const float um = (j > 0) ? L.u[idx - L.p0] : L.u[L.at(a, j, (k + half) % L.nph)];
+      const float rhs = L.f[idx] - (cr * L.u[idx + 1] + cl * L.u[idx - 1] + cjp * up + cjm * um);
+      d = (rhs - aphi * d) * m[q];
+      Y[(size_t)q * nt + t] = d;
+    }
+    float y = d;
+    for (int q = SL - 2; q >= 0; --q) {
+      y = Y[(size_t)q * nt + t] - cp[q] * y;
+      Y[(size_t)q * nt + t] = y;
+    }
+    E[(size_t)(2 * sgi) * L.nl + line] = y;
+    E[(size_t)(2 * sgi + 1) * L.nl + line] = d;
+  }
+  __syncthreads();
+  if (!act) return;
+  const int rl = 2 * ((sgi + P - 1) % P) + 1, rr = 2 * ((sgi + 1) % P);
+  float xl = 0.0f, xr = 0.0f;
+  for (int q = 0; q < 2 * P; ++q) {
+    const float e = E[(size_t)q * L.nl + line];
+    xl += G[rl * 2 * P + q] * e;
+    xr += G[rr * 2 * P + q] * e;
+  }
+  xl *= aphi;
+  xr *= aphi;
+  const int a = i + 1;
+  for (int q = 0; q < SL; ++q)
+    L.u[L.at(a, j, k0 + q)] = Y[(size_t)q * nt + t] - (xl * v[q] + xr * w[q]);
+}
+
+__global__ __launch_bounds__(256) void k_sres32(SLev L) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= L.nr || j >= L.nth) return;
+  const long long idx = L.at(i + 1, j, k);
+  L.r[idx] = L.f[idx] - (slev_off(L, i, j, k) + slev_diag(L, j) * L.u[idx]);
+}
+
+// coarse f = mean of the 8 fine residuals it pairs
+__global__ __launch_bounds__(256) void k_srestrict(SLev Lf, SLev Lc) {
+  const int I = blockIdx.x * BX + threadIdx.x;
+  const int J = blockIdx.y * BY + threadIdx.y;
+  const int K = blockIdx.z;
+  if (I >= Lc.nr || J >= Lc.nth) return;
+  float s = 0.0f;
+  for (int c = 0; c < 2; ++c)
+    for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < 2; ++a) s += Lf.r[Lf.at(2 * I + a + 1, 2 * J + b, 2 * K + c)];
+  Lc.f[Lc.at(I + 1, J, K)] = 0.125f * s;
+}
+
+__global__ __launch_bounds__(256) void k_sprolong(SLev Lc, SLev Lf) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= Lf.nr || j >= Lf.nth) return;
+  Lf.u[Lf.at(i + 1, j, k)] += Lc.u[Lc.at((i >> 1) + 1, j >> 1, k >> 1)];
+}
+
+// coarsest level: u = A^-1 f with the dense FP64 inverse, one wavefront per row
+__global__ __launch_bounds__(256) void k_scoarse(const double* __restrict__ inv, SLev L) {
+  const int N = L.nr * L.nth * L.nph;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= N) return;
+  double acc = 0.0;
+  for (int col = lane; col < N; col += 64) {
+    const int i = col % L.nr, j = (col / L.nr) % L.nth, k = col / (L.nr * L.nth);
+    acc += inv[(long long)row * N + col] * (double)L.f[L.at(i + 1, j, k)];
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) {
+    const int i = row % L.nr, j = (row / L.nr) % L.nth, k = row / (L.nr * L.nth);
+    L.u[L.at(i + 1, j, k)] = (float)acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_scast_in(const double* __restrict__ x, SGeom S, SLev L) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= S.nr || j >= S.nth) return;
+  L.f[L.at(i + 1, j, k)] = (float)x[S.at(i + 1, j, k)];
+}
+
+__global__ __launch_bounds__(256) void k_scast_out(SLev L, double* __restrict__ x, SGeom S) {
+  const int i = blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= S.nr || j >= S.nth) return;
+  x[S.at(i + 1, j, k)] = (double)L.u[L.at(i + 1, j, k)];
+}
+
+inline dim3 lgrid(const SLev& L) { return dim3((L.nr + BX - 1) / BX, (L.nth + BY - 1) / BY, L.nph); }
+
 Coef make_coef(const SGeom& S) {
   Coef c;
   c.ids2 = 1.0 / (S.ds * S.ds);
@@ -277,6 +425,16 @@ void pbicg_direction(const double* r, double* p, const double* v, double* phat, 
   k_gs_black<<<sgrid(S), dim3(BX, BY), 0, st>>>(p, phat, S, cf, c.cot, c.isin2);
 }
 
+void pbicg_update_p(const double* r, double* p, const double* v, const SGeom& S, const SphCoef& c,
+                    const Scalars* scal, hipStream_t st) {
+  k_pbicg_p<<<sgrid(S), dim3(BX, BY), 0, st>>>(r, p, v, nullptr, S, make_coef(S), c.isin2, scal);
+}
+
+void pbicg_update_s(const double* r, const double* v, double* s, const SGeom& S, const SphCoef& c,
+                    const Scalars* scal, hipStream_t st) {
+  k_pbicg_s<<<sgrid(S), dim3(BX, BY), 0, st>>>(r, v, s, nullptr, S, make_coef(S), c.isin2, scal);
+}
+
 void pbicg_s(const double* r, const double* v, double* s, double* shat, const SGeom& S, const SphCoef& c,
              const Scalars* scal, hipStream_t st) {
   const Coef cf = make_coef(S);
@@ -300,6 +458,30 @@ void pbicg_xr(double* x, double* r, const double* phat, const double* shat, cons
 
 void bicg_scalars(const double* partial, int nb, Scalars* scal, int stage, hipStream_t st) {
   k_bicg_scalars<<<1, 256, 0, st>>>(partial, nb, scal, stage);
+}
+
+void sph_line_pass(const SLev& L, int colour, hipStream_t st) {
+  const int nt = L.nl * L.nseg;
+  const size_t lds = sizeof(float) * ((size_t)L.seg * nt + (size_t)2 * L.nseg * L.nl);
+  const int lines = (L.nr + 1) / 2;
+  k_sline<<<dim3((lines + L.nl - 1) / L.nl, L.nth), nt, lds, st>>>(L, colour);
+}
+void sph_residual32(const SLev& L, hipStream_t st) { k_sres32<<<lgrid(L), dim3(BX, BY), 0, st>>>(L); }
+void sph_restrict32(const SLev& Lf, const SLev& Lc, hipStream_t st) {
+  k_srestrict<<<lgrid(Lc), dim3(BX, BY), 0, st>>>(Lf, Lc);
+}
+void sph_prolong_add32(const SLev& Lc, const SLev& Lf, hipStream_t st) {
+  k_sprolong<<<lgrid(Lf), dim3(BX, BY), 0, st>>>(Lc, Lf);
+}
+void sph_coarse32(const double* inv, const SLev& L, hipStream_t st) {
+  const int N = L.nr * L.nth * L.nph;
+  k_scoarse<<<(N + 3) / 4, 256, 0, st>>>(inv, L);
+}
+void sph_cast_in(const double* x, const SGeom& S, const SLev& L0, hipStream_t st) {
+  k_scast_in<<<sgrid(S), dim3(BX, BY), 0, st>>>(x, S, L0);
+}
+void sph_cast_out(const SLev& L0, double* x, const SGeom& S, hipStream_t st) {
+  k_scast_out<<<sgrid(S), dim3(BX, BY), 0, st>>>(L0, x, S);
 }
 
 void sph_fill_zero(double* x, const SGeom& S, hipStream_t st) {

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -70,6 +71,40 @@ struct Carver {
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// Level sizes of the spherical FP32 multigrid preconditioner: halve every axis
+// while all three stay even (ntheta >= 4, nphi >= 8, nr >= 4) and the level
+// has more than 512 unknowns.
+std::vector<std::array<int, 3>> sph_levels(int nr, int nth, int nph) {
+  std::vector<std::array<int, 3>> out;
+  while (true) {
+    out.push_back({nr, nth, nph});
+    if ((long long)nr * nth * nph <= 512 || (nr & 1) || (nth & 1) || (nph & 1) || nth < 4 || nph < 8 || nr < 4) break;
+    nr /= 2;
+    nth /= 2;
+    nph /= 2;
+  }
+  return out;
+}
+
+// Split of a phi line of nph nodes for the line smoother: segments of seg
+// nodes (the largest divisor of nph up to 32), nseg = nph / seg of them, nl
+// lines per block (a power of two, <= 64 lines, <= 1024 threads and the LDS
+// of Y plus the interface values within 64 KiB).  False if no split fits.
+bool line_split(int nph, int* seg, int* nseg, int* nl) {
+  int L = 1;
+  for (int d = 2; d <= 32 && d <= nph; ++d)
+    if (nph % d == 0) L = d;
+  const int P = nph / L;
+  if (L < 2 || P > 64) return false;
+  int n = 64;
+  while (n > 1 && (n * P > 1024 || (long long)n * (nph + 2 * P) * 4 > 65536)) n >>= 1;
+  if ((long long)n * (nph + 2 * P) * 4 > 65536 || n * P > 1024) return false;
+  *seg = L;
+  *nseg = P;
+  *nl = n;
+  return true;
+}
+
 int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
   if (!g || !o) {
     set_error("null grid or options");
@@ -88,9 +123,27 @@ int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
     return POISSON_EINVAL;
   }
   if (g->coord == POISSON_SPHERICAL_LOG) {
-    if (o->method != POISSON_BICGSTAB) {
+    if (o->method != POISSON_BICGSTAB && o->method != POISSON_BICGSTAB_MG32) {
       set_error("the log-spherical grid is solved by BiCGSTAB");
       return POISSON_EINVAL;
+    }
+    if (o->method == POISSON_BICGSTAB_MG32) {
+      if (o->nu1 < 1 || o->nu2 < 1) {
+        set_error("the multigrid preconditioner needs nu1, nu2 >= 1");
+        return POISSON_EINVAL;
+      }
+      const auto lv = sph_levels(g->n[0], g->n[1], g->n[2]);
+      const auto& c = lv.back();
+      if ((long long)c[0] * c[1] * c[2] > 4096) {
+        set_error("spherical grid does not coarsen to <= 4096 unknowns (sizes must keep halving evenly)");
+        return POISSON_EGRID;
+      }
+      int sg, ns, nl;
+      for (size_t l = 0; l + 1 < lv.size(); ++l)
+        if (!line_split(lv[l][2], &sg, &ns, &nl)) {
+          set_error("nphi = %d has no segment split for the phi-line smoother", lv[l][2]);
+          return POISSON_EGRID;
+        }
     }
     if (g->n[0] < 3 || g->n[1] < 2 || g->n[2] < 2 || (g->n[1] & 1) || (g->n[2] & 1)) {
       set_error("spherical grid needs nr >= 3 and even ntheta, nphi");
@@ -139,17 +192,23 @@ int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
       return POISSON_EGRID;
     }
   }
-  if (o->order != 2 && o->order != 6) {
+  if (o->method == POISSON_MG_SPAI || o->method == POISSON_MG_SPAI32) {
+    if (o->order != 2 && o->order != 4) {
+      set_error("the SPAI multigrid takes the compact stencils of order 2 or 4");
+      return POISSON_EINVAL;
+    }
+  } else if (o->order != 2 && o->order != 6) {
     set_error("order must be 2 (7-point) or 6 (19-point star)");
     return POISSON_EINVAL;
   }
-  const int need_g = o->order == 2 ? 1 : 3;
+  const int need_g = o->order == 6 ? 3 : 1;
   if (g->ghost != need_g) {
     set_error("order %d needs ghost = %d", o->order, need_g);
     return POISSON_EGRID;
   }
   const int M = n + 1 + 2 * (g->ghost - 1);
-  if (residual_blocks(make_geom(n, g->ghost, o->order == 6 ? 4 : 2, 1.0)) > kPartialCap) {
+  if (residual_blocks(make_geom(n, g->ghost, o->order == 6 ? 4 : 2, 1.0)) > kPartialCap ||
+      n27_blocks(make_ngeom(n, 1.0)) > kPartialCap) {
     set_error("grid too large for the reduction buffers");
     return POISSON_EGRID;
   }
@@ -167,7 +226,9 @@ int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
     case POISSON_CG:
       break;
     case POISSON_MG:
-    case POISSON_MG_IR32: {
+    case POISSON_MG_IR32:
+    case POISSON_MG_SPAI:
+    case POISSON_MG_SPAI32: {
       if (o->coarsest < 2 || o->nu1 < 0 || o->nu2 < 0) {
         set_error("multigrid needs coarsest >= 2, nu >= 0");
         return POISSON_EINVAL;
@@ -211,10 +272,61 @@ void carve(poisson_plan_s* P, Carver& cv) {
     }
     P->ss = (double*)cv.take(vb);
     P->stt = (double*)cv.take(vb);
+    P->slv.clear();
+    if (o.method == POISSON_BICGSTAB_MG32) {
+      const double ds = log(g.hi[0] / g.lo[0]) / (g.n[0] - 1);
+      int lev = 0;
+      for (const auto& d : sph_levels(g.n[0], g.n[1], g.n[2])) {
+        SLev L{};
+        L.nr = d[0];
+        L.nth = d[1];
+        L.nph = d[2];
+        L.p0 = L.nr + 2;
+        L.p1 = (long long)L.nth * L.p0;
+        const double dsl = ds * (1 << lev), dth = M_PI / L.nth, dph = 2.0 * M_PI / L.nph;
+        L.ids2 = (float)(1.0 / (dsl * dsl));
+        L.i2ds = (float)(1.0 / (2.0 * dsl));
+        L.idt2 = (float)(1.0 / (dth * dth));
+        L.idp2 = (float)(1.0 / (dph * dph));
+        const size_t fb = sizeof(float) * (size_t)L.count();
+        L.u = (float*)cv.take(fb);
+        L.f = (float*)cv.take(fb);
+        L.r = (float*)cv.take(fb);
+        L.cot2 = (const float*)cv.take(sizeof(float) * L.nth);
+        L.isin2 = (const float*)cv.take(sizeof(float) * L.nth);
+        if (line_split(L.nph, &L.seg, &L.nseg, &L.nl)) {
+          L.tstride = 4 * L.seg + 4 * L.nseg * L.nseg;
+          L.ltab = (const float*)cv.take(sizeof(float) * (size_t)L.tstride * L.nth);
+        }
+        P->slv.push_back(L);
+        ++lev;
+      }
+      const SLev& C = P->slv.back();
+      P->sncoarse = C.nr * C.nth * C.nph;
+      P->scinv = (double*)cv.take(sizeof(double) * (size_t)P->sncoarse * P->sncoarse);
+    }
     return;
   }
   const int n = g.n[0];
   const double h = (g.hi[0] - g.lo[0]) / n;
+  if (o.method == POISSON_MG_SPAI || o.method == POISSON_MG_SPAI32) {
+    P->nlv.clear();
+    for (int nl = n;; nl /= 2) {
+      NLevel L;
+      L.G = make_ngeom(nl, h * (n / nl));
+      L.f32 = o.method == POISSON_MG_SPAI32 && nl != n;
+      const size_t b = (L.f32 ? sizeof(float) : sizeof(double)) * L.G.total();
+      L.u = cv.take(b);
+      L.f = cv.take(b);
+      L.r = (nl == o.coarsest) ? nullptr : cv.take(b);
+      P->nlv.push_back(L);
+      if (nl == o.coarsest) break;
+    }
+    const int E = o.coarsest - 1;
+    P->ncoarse = E * E * E;
+    P->cinv = (double*)cv.take(sizeof(double) * (size_t)P->ncoarse * P->ncoarse);
+    return;
+  }
   P->G0 = make_geom(n, g.ghost, P->C, h);
   const size_t b64 = sizeof(double) * P->G0.total();
   P->phi64 = (double*)cv.take(b64);
@@ -343,6 +455,163 @@ bool coarse_inverse(int nc, double h, int order, std::vector<double>& inv) {
   return true;
 }
 
+// Inverse of a general dense matrix by Gauss-Jordan elimination with partial
+// pivoting (the spherical operator is not symmetric).
+bool invert_general(int N, std::vector<double>& A, std::vector<double>& inv) {
+  inv.assign((size_t)N * N, 0.0);
+  for (int i = 0; i < N; ++i) inv[(size_t)i * N + i] = 1.0;
+  for (int c = 0; c < N; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < N; ++r)
+      if (fabs(A[(size_t)r * N + c]) > fabs(A[(size_t)piv * N + c])) piv = r;
+    if (!(fabs(A[(size_t)piv * N + c]) > 0.0)) return false;
+    if (piv != c)
+      for (int k = 0; k < N; ++k) {
+        std::swap(A[(size_t)c * N + k], A[(size_t)piv * N + k]);
+        std::swap(inv[(size_t)c * N + k], inv[(size_t)piv * N + k]);
+      }
+    const double d = 1.0 / A[(size_t)c * N + c];
+    for (int k = 0; k < N; ++k) {
+      A[(size_t)c * N + k] *= d;
+      inv[(size_t)c * N + k] *= d;
+    }
+    for (int r = 0; r < N; ++r) {
+      if (r == c) continue;
+      const double f = A[(size_t)r * N + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < N; ++k) {
+        A[(size_t)r * N + k] -= f * A[(size_t)c * N + k];
+        inv[(size_t)r * N + k] -= f * inv[(size_t)c * N + k];
+      }
+    }
+  }
+  return true;
+}
+
+// Dense operator of a spherical multigrid level (zero radial ghosts, pole
+// reflection, periodic phi), in the same coefficients as the level kernels.
+void sph_level_matrix(int nr, int nth, int nph, double ds, std::vector<double>& A) {
+  const int N = nr * nth * nph;
+  A.assign((size_t)N * N, 0.0);
+  const double dth = M_PI / nth, dph = 2.0 * M_PI / nph;
+  const int half = nph / 2;
+  auto id = [&](int i, int j, int k) { return (k * nth + j) * nr + i; };
+  for (int k = 0; k < nph; ++k)
+    for (int j = 0; j < nth; ++j) {
+      const double th = (j + 0.5) * dth;
+      const double cot2 = cos(th) / sin(th) / (2.0 * dth), is2 = 1.0 / (sin(th) * sin(th));
+      for (int i = 0; i < nr; ++i) {
+        double* row = &A[(size_t)id(i, j, k) * N];
+        row[id(i, j, k)] += -2.0 / (ds * ds) - 2.0 / (dth * dth) - 2.0 * is2 / (dph * dph);
+        if (i + 1 < nr) row[id(i + 1, j, k)] += 1.0 / (ds * ds) + 1.0 / (2.0 * ds);
+        if (i > 0) row[id(i - 1, j, k)] += 1.0 / (ds * ds) - 1.0 / (2.0 * ds);
+        row[(j + 1 < nth) ? id(i, j + 1, k) : id(i, nth - 1, (k + half) % nph)] += 1.0 / (dth * dth) + cot2;
+        row[(j > 0) ? id(i, j - 1, k) : id(i, 0, (k + half) % nph)] += 1.0 / (dth * dth) - cot2;
+        row[id(i, j, (k + 1) % nph)] += is2 / (dph * dph);
+        row[id(i, j, (k + nph - 1) % nph)] += is2 / (dph * dph);
+      }
+    }
+}
+
+// Tables of the phi-line smoother for one level (layout in SLev): per
+// colatitude j the line operator is the periodic tridiagonal system
+// a x[k-1] + b x[k] + a x[k+1] with a = 1 / (sin^2 theta_j dphi^2) and b the
+// level diagonal; computed in FP64, stored FP32.
+bool line_tables(const SLev& L, double ds, std::vector<float>& tab) {
+  const int SL = L.seg, Pn = L.nseg;
+  tab.assign((size_t)L.tstride * L.nth, 0.0f);
+  const double dth = M_PI / L.nth, dph = 2.0 * M_PI / L.nph;
+  std::vector<double> m(SL), cp(SL), v(SL), w(SL), K, G;
+  for (int j = 0; j < L.nth; ++j) {
+    const double th = (j + 0.5) * dth;
+    const double a = 1.0 / (sin(th) * sin(th) * dph * dph);
+    const double b = -2.0 / (ds * ds) - 2.0 / (dth * dth) - 2.0 * a;
+    m[0] = 1.0 / b;
+    cp[0] = a / b;
+    for (int q = 1; q < SL; ++q) {
+      const double den = b - a * cp[q - 1];
+      m[q] = 1.0 / den;
+      cp[q] = a / den;
+    }
+    auto tsolve = [&](int unit, std::vector<double>& y) {
+      double d = 0.0;
+      for (int q = 0; q < SL; ++q) {
+        d = ((q == unit ? 1.0 : 0.0) - a * d) * m[q];
+        y[q] = d;
+      }
+      for (int q = SL - 2; q >= 0; --q) y[q] -= cp[q] * y[q + 1];
+    };
+    tsolve(0, v);
+    tsolve(SL - 1, w);
+    // interface system: X[2s] = x at the first node of segment s, X[2s+1] at
+    // its last; X + a (v X_left + w X_right) = E
+    const int n2 = 2 * Pn;
+    K.assign((size_t)n2 * n2, 0.0);
+    for (int q = 0; q < n2; ++q) K[(size_t)q * n2 + q] = 1.0;
+    for (int sgi = 0; sgi < Pn; ++sgi) {
+      const int xl = 2 * ((sgi + Pn - 1) % Pn) + 1, xr = 2 * ((sgi + 1) % Pn);
+      K[(size_t)(2 * sgi) * n2 + xl] += a * v[0];
+      K[(size_t)(2 * sgi) * n2 + xr] += a * w[0];
+      K[(size_t)(2 * sgi + 1) * n2 + xl] += a * v[SL - 1];
+      K[(size_t)(2 * sgi + 1) * n2 + xr] += a * w[SL - 1];
+    }
+    if (!invert_general(n2, K, G)) return false;
+    float* t = &tab[(size_t)j * L.tstride];
+    for (int q = 0; q < SL; ++q) {
+      t[q] = (float)m[q];
+      t[SL + q] = (float)cp[q];
+      t[2 * SL + q] = (float)v[q];
+      t[3 * SL + q] = (float)w[q];
+    }
+    for (int q = 0; q < n2 * n2; ++q) t[4 * SL + q] = (float)G[q];
+  }
+  return true;
+}
+
+// Table 1: SPAI smoother coefficients (omega, alpha, beta, gamma, delta) of
+// the compact stencils of order 2 and 4.
+const double kSpai[2][5] = {{1.3699, 0.1432, 0.0284, 0.0081, 0.0025},
+                            {0.9363, 0.2807, 0.0329, 0.0166, 0.0044}};
+
+// Galerkin product R A P of a cubically symmetric radius-1 stencil with full
+// weighting and trilinear prolongation.  Per axis, R shift(d) P is the coarse
+// 1-D stencil s_d: s_0 = (1/8, 3/4, 1/8), s_+1 = (1/2, 1/2, 0),
+// s_-1 = (0, 1/2, 1/2) (entries for coarse offsets -1, 0, +1), and the 3-D
+// product factorises, so W(D) = sum_d w(d) s_dx(Dx) s_dy(Dy) s_dz(Dz).
+W4 galerkin_w4(const W4& w) {
+  const double s[3][3] = {{0.0, 0.5, 0.5}, {0.125, 0.75, 0.125}, {0.5, 0.5, 0.0}};  // [d+1][D+1]
+  const double cls[4] = {w.c, w.f, w.e, w.k};
+  double out[4] = {0, 0, 0, 0};
+  // read each class at one representative offset D: (0,0,0), (1,0,0), (1,1,0), (1,1,1)
+  const int rep[4][3] = {{0, 0, 0}, {1, 0, 0}, {1, 1, 0}, {1, 1, 1}};
+  for (int c = 0; c < 4; ++c)
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int nz = (dx != 0) + (dy != 0) + (dz != 0);
+          out[c] += cls[nz] * s[dx + 1][rep[c][0] + 1] * s[dy + 1][rep[c][1] + 1] * s[dz + 1][rep[c][2] + 1];
+        }
+  return W4{out[0], out[1], out[2], out[3]};
+}
+
+// dense matrix of a W4 stencil on the (n-1)^3 unknowns with zero ghosts
+void w4_matrix(const W4& w, int n, std::vector<double>& A) {
+  const int E = n - 1;
+  const int N = E * E * E;
+  A.assign((size_t)N * N, 0.0);
+  const double cls[4] = {w.c, w.f, w.e, w.k};
+  for (int k = 0; k < E; ++k)
+    for (int j = 0; j < E; ++j)
+      for (int i = 0; i < E; ++i)
+        for (int dz = -1; dz <= 1; ++dz)
+          for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+              const int a = i + dx, b = j + dy, c = k + dz;
+              if (a < 0 || a >= E || b < 0 || b >= E || c < 0 || c >= E) continue;
+              A[(size_t)((k * E + j) * E + i) * N + (c * E + b) * E + a] += cls[(dx != 0) + (dy != 0) + (dz != 0)];
+            }
+}
+
 // ------------------------------------------------------------ solver pieces
 // One V(nu1, nu2) cycle from level l down.  zero_guess: the level's
 // unknowns start at zero (every coarse correction, and the FP32 correction of
@@ -373,6 +642,108 @@ void vcycle(poisson_plan_s* P, int l, bool zero_guess, hipStream_t st) {
     for (int c = C - 1; c >= 0; --c) colour_pass(L.phi, L.f, f32, L.G, P->order, c, 1.0, st);
 }
 
+// One FP32 V(nu1, nu2) cycle of the spherical preconditioner from level l on a
+// zero initial guess (colours forward before, backward after the correction).
+void svcycle(poisson_plan_s* P, int l, hipStream_t st) {
+  const SLev& L = P->slv[l];
+  if (l + 1 == (int)P->slv.size()) {
+    sph_coarse32(P->scinv, L, st);
+    return;
+  }
+  fill_zero(L.u, true, L.count(), st);
+  for (int s = 0; s < P->opts.nu1; ++s)
+    for (int c = 0; c < 2; ++c) sph_line_pass(L, c, st);
+  sph_residual32(L, st);
+  sph_restrict32(L, P->slv[l + 1], st);
+  svcycle(P, l + 1, st);
+  sph_prolong_add32(P->slv[l + 1], L, st);
+  for (int s = 0; s < P->opts.nu2; ++s)
+    for (int c = 1; c >= 0; --c) sph_line_pass(L, c, st);
+}
+
+// yhat = M^-1 y with M^-1 one FP32 V-cycle (inputs / outputs FP64)
+void sph_precond(poisson_plan_s* P, const double* y, double* yhat, hipStream_t st) {
+  sph_cast_in(y, P->S, P->slv[0], st);
+  svcycle(P, 0, st);
+  sph_cast_out(P->slv[0], yhat, P->S, st);
+}
+
+// one right-preconditioned BiCGSTAB iteration with the multigrid preconditioner
+void sph_mg_iteration(poisson_plan_s* P, double* phi, hipStream_t st) {
+  const SGeom& S = P->S;
+  const int nb = sph_blocks(S);
+  double* p = P->sp[0];
+  double* phat = P->sp[1];
+  double* v = P->sv[0];
+  double* shat = P->sv[1];
+  pbicg_update_p(P->sr, p, v, S, P->sc, P->scal, st);
+  sph_precond(P, p, phat, st);
+  pbicg_apply(phat, v, P->srh, 0, S, P->sc, P->partial, st);
+  bicg_scalars(P->partial, nb, P->scal, 0, st);
+  pbicg_update_s(P->sr, v, P->ss, S, P->sc, P->scal, st);
+  sph_precond(P, P->ss, shat, st);
+  pbicg_apply(shat, P->stt, P->ss, 1, S, P->sc, P->partial, st);
+  bicg_scalars(P->partial, nb, P->scal, 1, st);
+  pbicg_xr(phi, P->sr, phat, shat, P->ss, P->stt, P->srh, S, P->scal, P->partial, st);
+  bicg_scalars(P->partial, nb, P->scal, 2, st);
+}
+
+int capture_sph_iteration(poisson_plan_s* P, double* phi) {
+  if (P->iter_exec && P->iter_phi == phi) return POISSON_OK;
+  if (P->iter_exec) {
+    hipGraphExecDestroy(P->iter_exec);
+    P->iter_exec = nullptr;
+  }
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
+  sph_mg_iteration(P, phi, P->cap);
+  hipError_t e = hipStreamEndCapture(P->cap, &graph);
+  if (e != hipSuccess) {
+    set_error("graph capture failed: %s", hipGetErrorString(e));
+    return POISSON_EHIP;
+  }
+  e = hipGraphInstantiate(&P->iter_exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    P->iter_exec = nullptr;
+    set_error("graph instantiation failed: %s", hipGetErrorString(e));
+    return POISSON_EHIP;
+  }
+  P->iter_phi = phi;
+  return POISSON_OK;
+}
+
+// One SPAI V(nu1, nu2) cycle from level l: Richardson steps u -= M (f - A u)
+// (Eq. richardson), Galerkin coarse problems on a zero initial guess.
+void spai_vcycle(poisson_plan_s* P, int l, hipStream_t st) {
+  NLevel& L = P->nlv[l];
+  if (l + 1 == (int)P->nlv.size()) {
+    n_coarse(P->cinv, L.f, L.u, L.f32, L.G, st);
+    return;
+  }
+  for (int s = 0; s < P->opts.nu1; ++s) {
+    n27_residual(L.u, L.f, L.r, L.f32, L.G, L.A, false, nullptr, st);
+    n27_update(L.r, L.u, L.f32, L.G, L.M, st);
+  }
+  n27_residual(L.u, L.f, L.r, L.f32, L.G, L.A, false, nullptr, st);
+  NLevel& C = P->nlv[l + 1];
+  n_restrict(L.r, L.f32, L.G, C.f, C.f32, C.G, st);
+  fill_zero(C.u, C.f32, C.G.total(), st);
+  spai_vcycle(P, l + 1, st);
+  n_prolong_add(C.u, C.f32, C.G, L.u, L.f32, L.G, st);
+  for (int s = 0; s < P->opts.nu2; ++s) {
+    n27_residual(L.u, L.f, L.r, L.f32, L.G, L.A, false, nullptr, st);
+    n27_update(L.r, L.u, L.f32, L.G, L.M, st);
+  }
+}
+
+void spai_step(poisson_plan_s* P, hipStream_t st) {
+  NLevel& L = P->nlv[0];
+  spai_vcycle(P, 0, st);
+  n27_residual(L.u, L.f, nullptr, false, L.G, L.A, true, P->partial, st);
+  finish_sum(P->partial, (int)n27_blocks(L.G), 1, P->scal, kRes2, st);
+}
+
 // One multigrid iteration followed by the fine residual norm into
 // scal->v[kRes2].  MG: a V-cycle on (phi64; f64).  MG_IR32: the FP32
 // V-cycle for the correction e of the current FP32 residual r32, phi64 += e,
@@ -395,7 +766,10 @@ int capture_step(poisson_plan_s* P) {
   if (P->step_exec) return POISSON_OK;
   hipGraph_t graph = nullptr;
   HIPCHK(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
-  mg_step(P, P->cap);
+  if (!P->nlv.empty())
+    spai_step(P, P->cap);
+  else
+    mg_step(P, P->cap);
   hipError_t e = hipStreamEndCapture(P->cap, &graph);
   if (e != hipSuccess) {
     set_error("graph capture failed: %s", hipGetErrorString(e));
@@ -502,6 +876,60 @@ int cart_setup_impl(poisson_plan_s* P, const double* rho, double* phi) {
   residual(P->phi64, P->f64, false, rout, rout32, G, P->order, false, P->partial, st);
   finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
   return launch_check("solve setup");
+}
+
+int solve_spai(poisson_plan_s* P, const double* rho, double* phi, double tol, poisson_stats_t* stats) {
+  const poisson_grid_t& g = P->grid;
+  const poisson_opts_t& o = P->opts;
+  hipStream_t st = P->st;
+  Tracker T{stats};
+  if (stats) stats->history_len = 0;
+  NLevel& L = P->nlv[0];
+  const int nb = (int)n27_blocks(L.G);
+  HIPCHK(hipEventRecord(P->ev[0], st));
+  if (o.lmax >= 0) CHK(do_multipole(P, rho, phi, o.lmax, nullptr));
+  HIPCHK(hipEventRecord(P->ev[1], st));
+  n_rhs(rho, g.pitch[0], g.pitch[1], (double*)L.f, L.G, o.order, o.four_pi_G, st);
+  n_from_caller(phi, g.pitch[0], g.pitch[1], (double*)L.u, L.G, true, st);
+  n27_residual(L.u, L.f, nullptr, false, L.G, L.A, true, P->partial, st);
+  finish_sum(P->partial, nb, 1, P->scal, kBnorm2, st);
+  n_from_caller(phi, g.pitch[0], g.pitch[1], (double*)L.u, L.G, false, st);
+  n27_residual(L.u, L.f, nullptr, false, L.G, L.A, true, P->partial, st);
+  finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
+  CHK(launch_check("SPAI setup"));
+  CHK(read_scalars(P, kBnorm2, 2));
+  T.bnorm = sqrt(P->host[0]);
+  double rel = rel_of(P->host[1], T.bnorm);
+  T.push(rel);
+  if (!isfinite(rel)) {
+    set_error("non-finite initial residual (NaN/Inf in rho or phi)");
+    return POISSON_ENUMERIC;
+  }
+  int it = 0;
+  bool conv = rel <= tol;
+  CHK(capture_step(P));
+  while (!conv && it < o.max_iter) {
+    HIPCHK(hipGraphLaunch(P->step_exec, st));
+    ++it;
+    if (it % o.check_every == 0 || it == o.max_iter) {
+      CHK(read_scalars(P, kRes2, 1));
+      rel = rel_of(P->host[0], T.bnorm);
+      T.push(rel);
+      if (!isfinite(rel)) {
+        set_error("multigrid diverged (non-finite residual)");
+        return POISSON_ENUMERIC;
+      }
+      conv = rel <= tol;
+    }
+  }
+  n_to_caller((const double*)L.u, L.G, phi, g.pitch[0], g.pitch[1], st);
+  HIPCHK(hipEventRecord(P->ev[2], st));
+  HIPCHK(hipEventSynchronize(P->ev[2]));
+  CHK(launch_check("SPAI multigrid"));
+  float t_mp = 0.f, t_it = 0.f;
+  HIPCHK(hipEventElapsedTime(&t_mp, P->ev[0], P->ev[1]));
+  HIPCHK(hipEventElapsedTime(&t_it, P->ev[1], P->ev[2]));
+  return finish_status(P, T, it, rel, conv, t_mp, t_it);
 }
 
 int solve_cart(poisson_plan_s* P, const double* rho, double* phi, double tol, poisson_stats_t* stats) {
@@ -649,23 +1077,31 @@ int solve_sph(poisson_plan_s* P, const double* rho, double* phi, double tol, poi
     P->host[0] = P->host[1];
     CHK(restart());
   }
-  // right-preconditioned BiCGSTAB with the red-black Gauss-Seidel
-  // preconditioner: p, v, phat, shat, s, t
+  // right-preconditioned BiCGSTAB (p, v, phat, shat, s, t) with either the
+  // red-black Gauss-Seidel preconditioner or one FP32 multigrid V-cycle; the
+  // latter runs as one captured graph per iteration
   double* p = P->sp[0];
   double* phat = P->sp[1];
   double* v = P->sv[0];
   double* shat = P->sv[1];
+  const bool mg = o.method == POISSON_BICGSTAB_MG32;
+  if (mg) CHK(capture_sph_iteration(P, phi));
   while (!conv && it < o.max_iter) {
-    pbicg_direction(P->sr, p, v, phat, S, P->sc, P->scal, st);
-    pbicg_apply(phat, v, P->srh, 0, S, P->sc, P->partial, st);
-    bicg_scalars(P->partial, nb, P->scal, 0, st);
-    pbicg_s(P->sr, v, P->ss, shat, S, P->sc, P->scal, st);
-    pbicg_apply(shat, P->stt, P->ss, 1, S, P->sc, P->partial, st);
-    bicg_scalars(P->partial, nb, P->scal, 1, st);
-    pbicg_xr(phi, P->sr, phat, shat, P->ss, P->stt, P->srh, S, P->scal, P->partial, st);
-    bicg_scalars(P->partial, nb, P->scal, 2, st);
+    if (mg) {
+      HIPCHK(hipGraphLaunch(P->iter_exec, st));
+    } else {
+      pbicg_direction(P->sr, p, v, phat, S, P->sc, P->scal, st);
+      pbicg_apply(phat, v, P->srh, 0, S, P->sc, P->partial, st);
+      bicg_scalars(P->partial, nb, P->scal, 0, st);
+      pbicg_s(P->sr, v, P->ss, shat, S, P->sc, P->scal, st);
+      pbicg_apply(shat, P->stt, P->ss, 1, S, P->sc, P->partial, st);
+      bicg_scalars(P->partial, nb, P->scal, 1, st);
+      pbicg_xr(phi, P->sr, phat, shat, P->ss, P->stt, P->srh, S, P->scal, P->partial, st);
+      bicg_scalars(P->partial, nb, P->scal, 2, st);
+    }
     ++it;
-    if (it % o.check_every == 0 || it == o.max_iter) {
+    if (!(it % o.check_every == 0 || it == o.max_iter)) continue;
+    {
       CHK(launch_check("BiCGSTAB"));
       CHK(read_scalars(P, 0, 8));
       const double rr = P->host[7];
@@ -744,8 +1180,8 @@ void poisson_default_opts(poisson_opts_t* o, int32_t method) {
   o->method = method;
   o->order = 2;
   o->lmax = 8;
-  o->nu1 = 2;
-  o->nu2 = 2;
+  o->nu1 = (method == POISSON_MG_SPAI || method == POISSON_MG_SPAI32) ? 3 : 2;
+  o->nu2 = o->nu1;
   o->coarsest = 8;
   o->omega_mode = POISSON_OMEGA_OPT;
   o->max_iter = 10000;
@@ -847,8 +1283,77 @@ int poisson_plan(poisson_plan_t* out, const poisson_grid_t* grid, const poisson_
       set_error("upload of spherical coefficients failed");
       return fail(POISSON_EHIP);
     }
+    for (size_t l = 0; l < P->slv.size(); ++l) {
+      const SLev& L = P->slv[l];
+      std::vector<float> c2(L.nth), is2(L.nth), tab;
+      if (L.ltab) {
+        if (!line_tables(L, S.ds * (1 << l), tab)) {
+          set_error("phi-line interface system is singular");
+          return fail(POISSON_ENUMERIC);
+        }
+        if (hipMemcpyAsync((void*)L.ltab, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice, st) !=
+            hipSuccess) {
+          set_error("upload of line-smoother tables failed");
+          return fail(POISSON_EHIP);
+        }
+      }
+      const double dth = M_PI / L.nth;
+      for (int j = 0; j < L.nth; ++j) {
+        const double th = (j + 0.5) * dth;
+        c2[j] = (float)(cos(th) / sin(th) / (2.0 * dth));
+        is2[j] = (float)(1.0 / (sin(th) * sin(th)));
+      }
+      if (hipMemcpyAsync((void*)L.cot2, c2.data(), sizeof(float) * L.nth, hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipMemcpyAsync((void*)L.isin2, is2.data(), sizeof(float) * L.nth, hipMemcpyHostToDevice, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) {
+        set_error("upload of preconditioner coefficients failed");
+        return fail(POISSON_EHIP);
+      }
+    }
+    if (!P->slv.empty()) {
+      const SLev& C = P->slv.back();
+      const double dsc = S.ds * (1 << (P->slv.size() - 1));
+      std::vector<double> A, inv;
+      sph_level_matrix(C.nr, C.nth, C.nph, dsc, A);
+      if (!invert_general(P->sncoarse, A, inv)) {
+        set_error("coarsest preconditioner level is singular");
+        return fail(POISSON_ENUMERIC);
+      }
+      if (hipMemcpyAsync(P->scinv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) {
+        set_error("upload of the coarsest inverse failed");
+        return fail(POISSON_EHIP);
+      }
+    }
     if (hipStreamSynchronize(st) != hipSuccess) {
       set_error("stream synchronisation failed");
+      return fail(POISSON_EHIP);
+    }
+  } else if (!P->nlv.empty()) {
+    const double* sp = kSpai[P->order == 4 ? 1 : 0];
+    for (size_t l = 0; l < P->nlv.size(); ++l) {
+      NLevel& L = P->nlv[l];
+      const double h2 = L.G.h * L.G.h;
+      if (l == 0) {
+        L.A = P->order == 4 ? W4{-4.0 / h2, 1.0 / (3.0 * h2), 1.0 / (6.0 * h2), 0.0} : W4{-6.0 / h2, 1.0 / h2, 0.0, 0.0};
+      } else {
+        L.A = galerkin_w4(P->nlv[l - 1].A);
+      }
+      const double s = sp[0] * h2;
+      L.M = W4{s * sp[1], s * sp[2], s * sp[3], s * sp[4]};
+    }
+    const NLevel& Lc = P->nlv.back();
+    std::vector<double> A, inv;
+    w4_matrix(Lc.A, Lc.G.n, A);
+    if (!invert_general(P->ncoarse, A, inv)) {
+      set_error("coarsest Galerkin operator is singular");
+      return fail(POISSON_ENUMERIC);
+    }
+    if (hipMemcpyAsync(P->cinv, inv.data(), sizeof(double) * inv.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      set_error("upload of the coarsest inverse failed");
       return fail(POISSON_EHIP);
     }
   } else if (!P->lv.empty()) {
@@ -877,6 +1382,7 @@ int poisson_plan(poisson_plan_t* out, const poisson_grid_t* grid, const poisson_
 void poisson_plan_destroy(poisson_plan_t P) {
   if (!P) return;
   if (P->step_exec) hipGraphExecDestroy(P->step_exec);
+  if (P->iter_exec) hipGraphExecDestroy(P->iter_exec);
   for (int i = 0; i < 3; ++i)
     if (P->ev[i]) hipEventDestroy(P->ev[i]);
   if (P->cap) hipStreamDestroy(P->cap);
@@ -910,7 +1416,9 @@ int poisson_solve(poisson_plan_t P, const double* d_rho, double* d_phi, const po
     set_error("grid differs from the plan's grid");
     return POISSON_EGRID;
   }
-  int s = P->sph ? solve_sph(P, d_rho, d_phi, tol, stats) : solve_cart(P, d_rho, d_phi, tol, stats);
+  int s = P->sph                               ? solve_sph(P, d_rho, d_phi, tol, stats)
+          : !P->nlv.empty()                   ? solve_spai(P, d_rho, d_phi, tol, stats)
+                                               : solve_cart(P, d_rho, d_phi, tol, stats);
   if (stats && s < 0) stats->status = s;
   return s;
 }
@@ -954,6 +1462,10 @@ int poisson_op_apply(poisson_plan_t P, const double* d_phi, double* d_out) {
     sph_apply(d_phi, d_out, P->S, P->sc, st);
     return launch_check("poisson_op_apply");
   }
+  if (!P->nlv.empty()) {
+    set_error("poisson_op_apply is not defined for SPAI plans (use poisson_op_residual)");
+    return POISSON_EINVAL;
+  }
   const poisson_grid_t& g = P->grid;
   split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);
   fill_zero(P->f64, false, P->G0.total(), st);
@@ -972,6 +1484,14 @@ int poisson_op_residual(poisson_plan_t P, const double* d_rho, const double* d_p
   if (P->sph) {
     sph_residual(d_phi, d_rho, d_res, P->S, P->sc, P->opts.four_pi_G, false, P->partial, st);
     finish_sum(P->partial, sph_blocks(P->S), 1, P->scal, kRes2, st);
+  } else if (!P->nlv.empty()) {
+    const poisson_grid_t& g = P->grid;
+    NLevel& L = P->nlv[0];
+    n_rhs(d_rho, g.pitch[0], g.pitch[1], (double*)L.f, L.G, P->order, P->opts.four_pi_G, st);
+    n_from_caller(d_phi, g.pitch[0], g.pitch[1], (double*)L.u, L.G, false, st);
+    n27_residual(L.u, L.f, L.r, false, L.G, L.A, true, P->partial, st);
+    finish_sum(P->partial, (int)n27_blocks(L.G), 1, P->scal, kRes2, st);
+    n_to_caller((const double*)L.r, L.G, d_res, g.pitch[0], g.pitch[1], st);
   } else {
     const poisson_grid_t& g = P->grid;
     split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);
@@ -1001,6 +1521,19 @@ int poisson_op_smooth(poisson_plan_t P, const double* d_rho, double* d_phi, int3
   }
   hipStream_t st = P->st;
   const poisson_grid_t& g = P->grid;
+  if (!P->nlv.empty()) {
+    // SPAI plans: `sweeps` Richardson steps with the plan's smoother
+    // (the sweep direction and omega do not apply)
+    NLevel& L = P->nlv[0];
+    n_rhs(d_rho, g.pitch[0], g.pitch[1], (double*)L.f, L.G, P->order, P->opts.four_pi_G, st);
+    n_from_caller(d_phi, g.pitch[0], g.pitch[1], (double*)L.u, L.G, false, st);
+    for (int s = 0; s < sweeps; ++s) {
+      n27_residual(L.u, L.f, L.r, false, L.G, L.A, false, nullptr, st);
+      n27_update(L.r, L.u, false, L.G, L.M, st);
+    }
+    n_to_caller((const double*)L.u, L.G, d_phi, g.pitch[0], g.pitch[1], st);
+    return launch_check("poisson_op_smooth");
+  }
   split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);
   split_from_natural(d_rho, g.pitch[0], g.pitch[1], P->f64, false, P->G0, P->opts.four_pi_G, st);
   for (int s = 0; s < sweeps; ++s)
@@ -1043,12 +1576,20 @@ int poisson_op_prolong_add(poisson_plan_t P, const double* d_coarse, double* d_f
 
 int poisson_op_vcycle(poisson_plan_t P, const double* d_rho, double* d_phi, int32_t cycles) {
   CHK(need_cart(P));
-  if (P->lv.empty() || !d_rho || !d_phi || cycles < 0) {
+  if ((P->lv.empty() && P->nlv.empty()) || !d_rho || !d_phi || cycles < 0) {
     set_error("V-cycles need a multigrid plan");
     return POISSON_EINVAL;
   }
   hipStream_t st = P->st;
   const poisson_grid_t& g = P->grid;
+  if (!P->nlv.empty()) {
+    NLevel& L = P->nlv[0];
+    n_rhs(d_rho, g.pitch[0], g.pitch[1], (double*)L.f, L.G, P->order, P->opts.four_pi_G, st);
+    n_from_caller(d_phi, g.pitch[0], g.pitch[1], (double*)L.u, L.G, false, st);
+    for (int c = 0; c < cycles; ++c) spai_step(P, st);
+    n_to_caller((const double*)L.u, L.G, d_phi, g.pitch[0], g.pitch[1], st);
+    return launch_check("poisson_op_vcycle");
+  }
   split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);
   split_from_natural(d_rho, g.pitch[0], g.pitch[1], P->f64, false, P->G0, P->opts.four_pi_G, st);
   if (P->mg32) residual(P->phi64, P->f64, false, P->lv[0].f, true, P->G0, P->order, false, nullptr, st);
@@ -1062,6 +1603,14 @@ int poisson_op_sweep_resident(poisson_plan_t P, int32_t sweeps) {
   if (sweeps < 0) {
     set_error("sweeps must be >= 0");
     return POISSON_EINVAL;
+  }
+  if (!P->nlv.empty()) {
+    NLevel& L = P->nlv[0];
+    for (int s = 0; s < sweeps; ++s) {
+      n27_residual(L.u, L.f, L.r, false, L.G, L.A, false, nullptr, P->st);
+      n27_update(L.r, L.u, false, L.G, L.M, P->st);
+    }
+    return launch_check("poisson_op_sweep_resident");
   }
   void* phi = P->phi64;
   const void* f = P->f64;

@@ -17,6 +17,17 @@ struct Level {
   void* f = nullptr;
   void* tmp = nullptr;
 };
+// level of the SPAI multigrid: natural layout, operator A (Galerkin on coarse
+// levels) and smoother M = omega h^2 (alpha, beta, gamma, delta)
+struct NLevel {
+  NGeom G{};
+  void* u = nullptr;
+  void* f = nullptr;
+  void* r = nullptr;
+  bool f32 = false;  // stored in FP32 (coarse levels of MG_SPAI32); arithmetic FP64
+  W4 A{};
+  W4 M{};
+};
 
 }  // namespace psn
 
@@ -38,6 +49,8 @@ struct poisson_plan_s {
   bool mg32 = false;
   double* cinv = nullptr;
   int ncoarse = 0;
+  // SPAI multigrid (natural layout)
+  std::vector<psn::NLevel> nlv;
   // CG
   double *cr = nullptr, *cp0 = nullptr, *cp1 = nullptr, *cq = nullptr;
   // spherical
@@ -45,6 +58,11 @@ struct poisson_plan_s {
   psn::SphCoef sc{};
   double *sr = nullptr, *srh = nullptr, *sp[2] = {nullptr, nullptr}, *sv[2] = {nullptr, nullptr};
   double *ss = nullptr, *stt = nullptr;
+  std::vector<psn::SLev> slv;          // FP32 multigrid preconditioner levels (BICGSTAB_MG32)
+  double* scinv = nullptr;             // dense inverse of its coarsest level
+  int sncoarse = 0;
+  hipGraphExec_t iter_exec = nullptr;  // captured preconditioned BiCGSTAB iteration
+  const double* iter_phi = nullptr;    // caller array the captured iteration updates
   // reductions and moments
   double* partial = nullptr;
   psn::Scalars* scal = nullptr;

@@ -101,6 +101,26 @@ def test_pitch_and_spherical_checks():
     assert L.load().poisson_workspace_bytes(C.byref(s_odd), C.byref(pg.options("bicgstab"))) == 0
 
 
+def test_spherical_multigrid_preconditioner_sizes():
+    lib = L.load()
+    s = pg.sph_grid(64, 32, 32)
+    gs = lib.poisson_workspace_bytes(C.byref(s), C.byref(pg.options("bicgstab")))
+    mg = lib.poisson_workspace_bytes(C.byref(s), C.byref(pg.options("bicgstab_mg32")))
+    # FP32 u, f, r on the fine level (with radial ghosts) and the coarser levels
+    assert mg > gs + 3 * 4 * 66 * 32 * 32
+    # 96 x 48 x 48 halves three times, to 12 x 6 x 6 (432 unknowns)
+    assert lib.poisson_workspace_bytes(C.byref(pg.sph_grid(96, 48, 48)),
+                                       C.byref(pg.options("bicgstab_mg32"))) > 0
+    # odd radial count: no coarsening, 33 x 32 x 32 unknowns is too many for the dense level
+    assert lib.poisson_workspace_bytes(C.byref(pg.sph_grid(33, 32, 32)),
+                                       C.byref(pg.options("bicgstab_mg32"))) == 0
+    assert b"coarsen" in lib.poisson_last_error()
+    # a small odd grid is its own coarsest level
+    assert lib.poisson_workspace_bytes(C.byref(pg.sph_grid(9, 8, 8)),
+                                       C.byref(pg.options("bicgstab_mg32"))) > 0
+    assert lib.poisson_workspace_bytes(C.byref(s), C.byref(pg.options("bicgstab_mg32", nu1=0))) == 0
+
+
 def test_plan_rejects_small_or_misaligned_workspace_before_any_device_call():
     lib = L.load()
     grid = pg.cart_grid(32)

@@ -97,14 +97,15 @@ def test_c3_star19_multigrid_reduced(method):
     assert rel_l2(phi[s, s, s], ref[s, s, s]) < CONV_TOL
 
 
-def test_c4_spherical_bicgstab_reduced():
-    say("C4 reduced 32x16x16 BiCGSTAB")
+@pytest.mark.parametrize("method", ["bicgstab", "bicgstab_mg32"])
+def test_c4_spherical_bicgstab_reduced(method):
+    say(f"C4 reduced 32x16x16 {method}")
     nr, nth, nph = 32, 16, 16
     wl = W.config_c4(nr=nr, nth=nth, nph=nph)
     rho = wl.rho.numpy()
     r, th, ph, ds = OM.sph_axes(nr, nth, nph)
     mc = 4 * math.pi * 1e-3
-    plan = pg.Plan(pg.sph_grid(nr, nth, nph), pg.options("bicgstab", lmax=8, point_mass=mc, max_iter=4000))
+    plan = pg.Plan(pg.sph_grid(nr, nth, nph), pg.options(method, lmax=8, point_mass=mc, max_iter=4000))
     phi = torch.zeros(rho.shape, dtype=torch.float64, device="cuda:0")
     res = plan.solve(dev(rho), phi, tol=1e-12)
     assert res.converged, res
@@ -113,6 +114,35 @@ def test_c4_spherical_bicgstab_reduced():
     got = host(phi)
     assert rel_l2(got[:, :, 1:nr + 1], ref[:, :, 1:nr + 1]) < CONV_TOL
     assert np.max(np.abs(got[:, :, [0, -1]] - ref[:, :, [0, -1]])) < 1e-12 * np.max(np.abs(ref[:, :, [0, -1]]))
+
+
+def test_c4_multigrid_preconditioner_cuts_iterations():
+    """64 x 32 x 64: one FP32 V(2,2) cycle as the right preconditioner needs
+    well under half the BiCGSTAB iterations of the red-black Gauss-Seidel
+    step, and both reach the same solution; solving twice into the same
+    array (graph reuse) and into another array (re-capture) gives the same
+    bits."""
+    say("C4 64x32x64 preconditioners")
+    nr, nth, nph = 64, 32, 64
+    wl = W.config_c4(nr=nr, nth=nth, nph=nph)
+    rho = dev(wl.rho.numpy())
+    mc = 4 * math.pi * 1e-3
+    out = {}
+    for m in ("bicgstab", "bicgstab_mg32"):
+        plan = pg.Plan(pg.sph_grid(nr, nth, nph), pg.options(m, lmax=8, point_mass=mc, max_iter=4000))
+        phi = torch.zeros_like(rho)
+        out[m] = (plan.solve(rho, phi, tol=1e-11), host(phi))
+        if m == "bicgstab_mg32":
+            again = torch.zeros_like(rho)
+            res2 = plan.solve(rho, again, tol=1e-11)
+            phi.zero_()
+            res3 = plan.solve(rho, phi, tol=1e-11)
+            assert torch.equal(again, phi) and res2.iterations == res3.iterations == out[m][0].iterations
+    (gs, a), (mg, b) = out["bicgstab"], out["bicgstab_mg32"]
+    say(f"  iterations: GS {gs.iterations}, MG {mg.iterations}")
+    assert gs.converged and mg.converged
+    assert mg.iterations * 2 < gs.iterations
+    assert rel_l2(a[:, :, 1:-1], b[:, :, 1:-1]) < 1e-9
 
 
 def test_c2_full_size_multigrid():
@@ -165,25 +195,30 @@ def test_error_paths():
 
 
 def test_c4_full_size_bicgstab():
-    """256 x 128 x 256 log-spherical grid, BiCGSTAB driven to 1e-12 against the
-    per-azimuthal-mode sparse-LU oracle (about 1.5 minutes of CPU)."""
+    """256 x 128 x 256 log-spherical grid, BiCGSTAB with both preconditioners
+    driven to 1e-12 against the per-azimuthal-mode sparse-LU oracle (about 1.5
+    minutes of CPU)."""
     say("C4 full size 256x128x256 BiCGSTAB")
     wl = W.config_c4()
     rho = wl.rho.numpy()
     g = wl.grid
     mc = 4 * math.pi * g.r_min
-    plan = pg.Plan(pg.sph_grid(g.nr, g.nth, g.nph),
-                   pg.options("bicgstab", lmax=8, point_mass=mc, max_iter=20000, check_every=10))
-    phi = torch.zeros(rho.shape, dtype=torch.float64, device="cuda:0")
-    res = plan.solve(dev(rho), phi, tol=1e-12)
-    say(f"  BiCGSTAB {res.iterations} iterations, rel residual {res.rel_residual:.2e}")
-    assert res.converged, res
+    got = {}
+    for m in ("bicgstab", "bicgstab_mg32"):
+        plan = pg.Plan(pg.sph_grid(g.nr, g.nth, g.nph),
+                       pg.options(m, lmax=8, point_mass=mc, max_iter=20000, check_every=10))
+        phi = torch.zeros(rho.shape, dtype=torch.float64, device="cuda:0")
+        res = plan.solve(dev(rho), phi, tol=1e-12)
+        say(f"  {m}: {res.iterations} iterations, rel residual {res.rel_residual:.2e}")
+        assert res.converged, res
+        got[m] = host(phi)
+        del plan, phi
     r, th, ph, ds = OM.sph_axes(g.nr, g.nth, g.nph)
     ghost, _, _ = OM.sph_boundary(rho, g.nr, g.nth, g.nph, 8, point_mass=mc)
     say("  oracle multipole done")
     ref = OD.solve_sph(ghost, rho, r, ds, th)
-    got = host(phi)
-    assert rel_l2(got[:, :, 1:-1], ref[:, :, 1:-1]) < CONV_TOL
+    for m, x in got.items():
+        assert rel_l2(x[:, :, 1:-1], ref[:, :, 1:-1]) < CONV_TOL, m
 
 
 def test_c3_full_size_properties():
