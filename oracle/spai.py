@@ -23,7 +23,9 @@ that, see the Table 1 reading in the tests).
 
 M(alpha, beta, gamma, delta) = h^2 * stencil (alpha, beta, gamma, delta)
 (Eq. Smoother); every level uses its own spacing h_l and the same
-coefficients.  Coarse operators are Galerkin products R A_l P with full
+coefficients.  With store32 the levels below the finest keep their data in
+FP32 and compute in FP64 (the paper's mixed precision): every stored value
+is rounded to FP32 where it is written.  Coarse operators are Galerkin products R A_l P with full
 weighting R and P = 8 R^T (trilinear), which for the stencils here stay
 radius 1 and cubically symmetric.
 """
@@ -153,12 +155,19 @@ def level_operators(order: int, n: int, coarsest: int = 8):
     return ops
 
 
-def spai_step(u: np.ndarray, f_int: np.ndarray, n: int, w_abs, coef, h: float) -> np.ndarray:
+def _stored(x, store32: bool):
+    """Value as stored: rounded to FP32 when the level keeps FP32 data."""
+    return x.astype(np.float32).astype(np.float64) if store32 else x
+
+
+def spai_step(u: np.ndarray, f_int: np.ndarray, n: int, w_abs, coef, h: float, store32: bool = False) -> np.ndarray:
     """One Richardson step u <- u - omega M r, r = f - A_L u, in place on the
-    unknowns of the node array u (ghosts fixed); M acts on r extended by zero."""
+    unknowns of the node array u (ghosts fixed); M acts on r extended by zero.
+    store32: the level stores r and u in FP32 (arithmetic stays FP64)."""
     omega, alpha, beta, gamma, delta = coef[:5]
-    r = f_int - apply27(u, n, w_abs)
-    u[1:n, 1:n, 1:n] -= omega * apply27(embed(r), n, (alpha, beta, gamma, delta), h * h)
+    r = _stored(f_int - apply27(u, n, w_abs), store32)
+    u[1:n, 1:n, 1:n] = _stored(u[1:n, 1:n, 1:n] - omega * apply27(embed(r), n, (alpha, beta, gamma, delta), h * h),
+                               store32)
     return u
 
 
@@ -173,15 +182,18 @@ def coarse_dense(w_abs, n: int) -> np.ndarray:
     return A
 
 
-def vcycle(u, f_int, n, ops, coef, nu1=3, nu2=3, level=0, _cache=None):
+def vcycle(u, f_int, n, ops, coef, nu1=3, nu2=3, level=0, _cache=None, store32=False):
     """One V(nu1, nu2) cycle with SPAI smoothing and Galerkin coarse
     operators on the node array u (one ghost layer, ghosts fixed); f_int is
     the right-hand side at the unknowns.  The coarsest level is solved
-    exactly (dense)."""
+    exactly (dense).  store32: every level below the finest stores its data
+    (u, f, r) in FP32 while all arithmetic stays FP64 (Section 2.1.3's mixed
+    precision)."""
     if _cache is None:
         _cache = {}
     h = 1.0 / n
     w = ops[level]
+    s32 = store32 and level > 0
     if level == len(ops) - 1:
         key = (n, w)
         if key not in _cache:
@@ -189,18 +201,18 @@ def vcycle(u, f_int, n, ops, coef, nu1=3, nu2=3, level=0, _cache=None):
         z = u.copy()
         z[1:n, 1:n, 1:n] = 0.0
         rhs = f_int - apply27(z, n, w)
-        u[1:n, 1:n, 1:n] = (_cache[key] @ rhs.ravel()).reshape(rhs.shape)
+        u[1:n, 1:n, 1:n] = _stored((_cache[key] @ rhs.ravel()).reshape(rhs.shape), s32)
         return u
     for _ in range(nu1):
-        spai_step(u, f_int, n, w, coef, h)
-    r = f_int - apply27(u, n, w)
-    rc = S.restrict(r)
+        spai_step(u, f_int, n, w, coef, h, s32)
+    r = _stored(f_int - apply27(u, n, w), s32)
     nc = n // 2
+    rc = _stored(S.restrict(r), store32)
     ec = np.zeros((nc + 1,) * 3)
-    vcycle(ec, rc, nc, ops, coef, nu1, nu2, level + 1, _cache)
-    u[1:n, 1:n, 1:n] += S.prolong(ec[1:nc, 1:nc, 1:nc])
+    vcycle(ec, rc, nc, ops, coef, nu1, nu2, level + 1, _cache, store32)
+    u[1:n, 1:n, 1:n] = _stored(u[1:n, 1:n, 1:n] + S.prolong(ec[1:nc, 1:nc, 1:nc]), s32)
     for _ in range(nu2):
-        spai_step(u, f_int, n, w, coef, h)
+        spai_step(u, f_int, n, w, coef, h, s32)
     return u
 
 

@@ -217,3 +217,24 @@ def test_vcycle_contraction_in_table2_regime(order, nu):
     rate = rs[-1] / rs[-2]
     ref = TABLE2_RHO[(order, nu)]
     assert ref / 3 < rate < ref * 3, rate
+
+
+def test_fp32_coarse_storage_keeps_the_fixed_point_and_rate():
+    """Rounding the coarse-level data to FP32 leaves the exact solution a
+    fixed point (the finest level is FP64) and changes one cycle's result by
+    no more than FP32 rounding of the correction."""
+    n = 32
+    ops = SP.level_operators(2, n)
+    rng = np.random.default_rng(9)
+    f = rng.standard_normal((n - 1,) * 3)
+    x = SP.embed(SP.dst_solve(ops[0], f, n))
+    y = x.copy()
+    SP.vcycle(y, f, n, ops, SP.TABLE1[2], 3, 3, store32=True)
+    assert np.max(np.abs(y - x)) < 1e-12 * np.max(np.abs(x))
+    u0 = SP.embed(rng.standard_normal((n - 1,) * 3))
+    a, b = u0.copy(), u0.copy()
+    SP.vcycle(a, f, n, ops, SP.TABLE1[2], 3, 3)
+    SP.vcycle(b, f, n, ops, SP.TABLE1[2], 3, 3, store32=True)
+    corr = np.max(np.abs(a - u0))
+    d = np.max(np.abs(a - b))
+    assert 0.0 < d < 1e-6 * corr
