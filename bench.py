@@ -48,7 +48,7 @@ def parse():
                          "--sweeps resident smoother sweeps and one 1 GiB reference copy; "
                          "prints no bench line")
     ap.add_argument("--sweeps", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "serving"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "serving", "spai"],
                     help="c2: the 255^3 FP64 multigrid solve (default bench line); serving: the "
                          "continuous-batching request stream (its own JSON line)")
     ap.add_argument("--requests", type=int, default=2000)
@@ -135,7 +135,7 @@ def c3(args):
         "t_multipole_ms": r32.t_multipole_ms,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "k_pass19<float> (fine-level four-colour GS pass)",
+                     "kernel": "k_pass19w<float> (fine-level four-colour GS pass)",
                      "algorithmic_bytes_per_launch": bytes_per_pass, "pass_ms": pass_ms},
     }
     print(json.dumps(out), flush=True)
@@ -144,7 +144,9 @@ def c3(args):
 def c4(args):
     """Log-spherical 256 x 128 x 256 grid (r in [1e-3, 1]), truncated SIS with a
     10% m = 2 perturbation, lmax 8 outer + inner expansions and the excised
-    core as a central point mass; BiCGSTAB in FP64 from a cold start."""
+    core as a central point mass; FP64 BiCGSTAB from a cold start, right-
+    preconditioned by one FP32 multigrid V(2,2) cycle, beside the red-black
+    Gauss-Seidel preconditioner."""
     import torch
 
     import paper_2605_03563_amd as pg
@@ -155,21 +157,100 @@ def c4(args):
     rho = wl.rho.contiguous()
     g = wl.grid
     grid = pg.sph_grid(g.nr, g.nth, g.nph)
-    plan = pg.Plan(grid, pg.options("bicgstab", lmax=8, point_mass=4 * math.pi * g.r_min, max_iter=20000,
-                                    check_every=10), device=dev)
-    phi = torch.zeros_like(rho)
-    sec, res = _time_solves(plan, rho, phi, args.tol, max(1, args.steps // 2), 1)
     unknowns = g.unknowns
-    it_ms = res.t_iter_ms / max(1, res.iterations)
-    bytes_per_it = 200.0 * unknowns   # preconditioned iteration: 7 streaming kernels
+    runs = {}
+    for m in ("bicgstab_mg32", "bicgstab"):
+        plan = pg.Plan(grid, pg.options(m, lmax=8, point_mass=4 * math.pi * g.r_min, max_iter=20000,
+                                        check_every=10 if m == "bicgstab" else 2), device=dev)
+        phi = torch.zeros_like(rho)
+        steps = max(1, args.steps // 2) if m == "bicgstab" else args.steps
+        sec, res = _time_solves(plan, rho, phi, args.tol, steps, 1)
+        runs[m] = (sec, res, steps)
+        del plan, phi
+    sec, res, steps = runs["bicgstab_mg32"]
+    sgs, rgs, _ = runs["bicgstab"]
+    gs_it_ms = rgs.t_iter_ms / max(1, rgs.iterations)
+    bytes_per_it = 200.0 * unknowns   # Gauss-Seidel-preconditioned iteration: 7 streaming kernels
     out = {
         "metric": "Gcell-updates/s", "value": unknowns * res.iterations / sec / 1e9, "unit": "Gcell-updates/s",
-        "n_gpus": 1, "steps": max(1, args.steps // 2), "warmup": 1, "ms_per_step": sec * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "c4_sis_m2_256x128x256_logsph_bicgstab_lmax8", "unknowns": unknowns},
+        "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32", "data": "synthetic",
+        "config": {"workload": "c4_sis_m2_256x128x256_logsph_bicgstab_fp32mg_lmax8", "unknowns": unknowns},
         "time_to_1e-8_ms": sec * 1e3, "iterations": res.iterations, "rel_residual": res.rel_residual,
-        "t_multipole_ms": res.t_multipole_ms, "ms_per_iteration": it_ms,
-        "iteration_GBps_algorithmic": bytes_per_it / (it_ms * 1e-3) / 1e9,
+        "t_multipole_ms": res.t_multipole_ms, "ms_per_iteration": res.t_iter_ms / max(1, res.iterations),
+        "gs_preconditioned": {"time_to_1e-8_ms": sgs * 1e3, "iterations": rgs.iterations,
+                              "ms_per_iteration": gs_it_ms,
+                              "iteration_GBps_algorithmic": bytes_per_it / (gs_it_ms * 1e-3) / 1e9},
+        "speedup_mg_vs_gs": sgs / sec,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def spai(args):
+    """The paper's own multigrid (Table 2 shape): 512^3 intervals (511^3
+    unknowns), seven coarse levels (coarsest 4 intervals), SPAI Richardson
+    smoothing with the Table 1 coefficients, Galerkin coarse operators,
+    compact stencils of order 2 and 4, V(nu, nu) for nu = 1, 2, 3, FP64 and
+    FP32 coarse-level storage; density of 64 clumps and the turbulent floor
+    (the 512^3 workload), multipole boundary lmax 8, cold start, tol 1e-8.
+    Reports the time per V-cycle s and the mean rate rho of Eq. rho beside
+    the paper's Table 2 values (other hardware: context only)."""
+    import torch
+
+    import paper_2605_03563_amd as pg
+    import workloads as W
+
+    dev = "cuda:0"
+    n = 512
+    wl = W.config_c3(n=n, device=dev, g=1)
+    rho = wl.rho.contiguous()
+    del wl
+    unknowns = (n - 1) ** 3
+    grid = pg.cart_grid(n, ghost=1)
+    paper = {(2, 1): (3.48e-2, 0.102), (2, 2): (5.29e-2, 0.028), (2, 3): (7.27e-2, 0.013),
+             (4, 1): (3.49e-2, 0.065), (4, 2): (5.33e-2, 0.017), (4, 3): (7.37e-2, 0.011)}
+    rows = []
+    best = None
+    for method in ("mg_spai", "mg_spai32"):
+        for order in (2, 4):
+            for nu in (1, 2, 3):
+                plan = pg.Plan(grid, pg.options(method, order=order, lmax=8, nu1=nu, nu2=nu, coarsest=4), device=dev)
+                phi = torch.zeros_like(rho)
+                sec, res = _time_solves(plan, rho, phi, args.tol, max(1, args.steps // 2), 1)
+                s_cycle = res.t_iter_ms / max(1, res.iterations) * 1e-3
+                row = {"method": method, "order": order, "nu": nu, "cycles": res.iterations,
+                       "time_to_1e-8_ms": sec * 1e3, "s_per_cycle": s_cycle, "rho": res.rate,
+                       "s_times_rho": s_cycle * res.rate, "t_multipole_ms": res.t_multipole_ms,
+                       "paper_s": paper[(order, nu)][0], "paper_rho": paper[(order, nu)][1]}
+                rows.append(row)
+                print(json.dumps({"spai_row": row}), flush=True)
+                if method == "mg_spai32" and order == 2 and nu == 3:
+                    best = (plan, row, sec)
+                else:
+                    del plan
+    plan, row, sec = best
+    # dominant kernels: the fine-level residual and smoother stencils (one SPAI
+    # step = both), timed resident on the plan's stream
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pg.sweep_resident(plan, 1)
+    ev0.record(plan.stream)
+    pg.sweep_resident(plan, 10)
+    ev1.record(plan.stream)
+    torch.cuda.synchronize()
+    step_ms = ev0.elapsed_time(ev1) / 10
+    bytes_per_step = 48.0 * unknowns   # residual (read u, f; write r) + smoother (read r, u; write u), FP64
+    achieved = bytes_per_step / (step_ms * 1e-3) / 1e9
+    out = {
+        "metric": "Gcell-updates/s", "value": unknowns * row["cycles"] / sec / 1e9, "unit": "Gcell-updates/s",
+        "n_gpus": 1, "steps": max(1, args.steps // 2), "warmup": 1, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32storage",
+        "data": "synthetic",
+        "config": {"workload": "spai_mg_512^3_order2_V33_fp32coarse_lmax8", "unknowns": unknowns},
+        "time_to_1e-8_ms": sec * 1e3, "cycles": row["cycles"], "rows": rows,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "k_n27 residual + k_n27 smoother (one fine-level SPAI step)",
+                     "algorithmic_bytes_per_launch": bytes_per_step / 2, "step_ms": step_ms},
     }
     print(json.dumps(out), flush=True)
 
@@ -341,7 +422,7 @@ def main():
         kernels_only(args)
         return
     if args.workload != "c2":
-        {"serving": serving, "c3": c3, "c4": c4}[args.workload](args)
+        {"serving": serving, "c3": c3, "c4": c4, "spai": spai}[args.workload](args)
         return
 
     import torch

@@ -1,0 +1,162 @@
+"""SPAI multigrid on compact stencils (Section 2.1.3, Table 1) against the
+oracle: residual with the compact right-hand side, Richardson steps, one
+V-cycle with Galerkin coarse operators, converged solves, full size."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2605_03563_amd as pg
+from oracle import multipole as OM
+from oracle import spai as SP
+from tests.gpu_util import dev, host, rel_l2, rel_max, say
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+KERNEL_TOL = 1e-13
+CYCLE_TOL = 1e-12
+CONV_TOL = 1e-10
+
+
+def _random(n, seed):
+    rng = np.random.default_rng(seed)
+    phi = rng.normal(size=(n + 1,) * 3)
+    rho = rng.normal(size=(n + 1,) * 3)
+    return phi, rho
+
+
+def _plan(n, order, coarsest=8, **kw):
+    return pg.Plan(pg.cart_grid(n, ghost=1), pg.options("mg_spai", order=order, lmax=-1, coarsest=coarsest, **kw))
+
+
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("n", [16, 48])
+def test_residual_with_compact_rhs(order, n):
+    say(f"SPAI residual order {order} n {n}")
+    phi, rho = _random(n, 100 + n + order)
+    plan = _plan(n, order, coarsest=n // 2 if n == 16 else 6)
+    res = torch.zeros(rho.shape, dtype=torch.float64, device="cuda:0")
+    n2 = plan.residual(dev(rho), dev(phi), res)
+    h = 1.0 / n
+    ref = SP.rhs_compact(rho, n, order) - SP.apply27(phi, n, SP.WEIGHTS[order], 1.0 / (h * h))
+    got = host(res)[1:n, 1:n, 1:n]
+    assert rel_max(got, ref) < KERNEL_TOL
+    assert n2 == pytest.approx(float(np.sum(ref * ref)), rel=1e-12)
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_richardson_steps(order):
+    n = 48
+    say(f"SPAI Richardson steps order {order}")
+    phi, rho = _random(n, 7 + order)
+    plan = _plan(n, order, coarsest=6)
+    x = dev(phi)
+    plan.smooth(dev(rho), x, sweeps=3)
+    h = 1.0 / n
+    w = tuple(c / (h * h) for c in SP.WEIGHTS[order])
+    f = SP.rhs_compact(rho, n, order)
+    ref = phi.copy()
+    for _ in range(3):
+        SP.spai_step(ref, f, n, w, SP.TABLE1[order], h)
+    assert rel_max(host(x), ref) < KERNEL_TOL
+
+
+@pytest.mark.parametrize("order,n,coarsest", [(2, 32, 8), (4, 32, 8), (2, 48, 6), (4, 128, 8)])
+def test_one_vcycle_matches_oracle(order, n, coarsest):
+    """One V(3,3) cycle with Galerkin coarse operators from a random guess
+    (n = 48: 47 unknowns per row, a ragged tile; n = 128: four levels)."""
+    say(f"SPAI one V-cycle order {order} n {n}")
+    phi, rho = _random(n, 11 * n + order)
+    plan = _plan(n, order, coarsest=coarsest)
+    x = dev(phi)
+    plan.vcycle(dev(rho), x, 1)
+    ops = SP.level_operators(order, n, coarsest)
+    f = SP.rhs_compact(rho, n, order)
+    ref = phi.copy()
+    SP.vcycle(ref, f, n, ops, SP.TABLE1[order], 3, 3)
+    assert rel_max(host(x), ref) < CYCLE_TOL
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_converged_solve_matches_exact_discrete_solution(order):
+    """Clumps at 64^3 with the multipole boundary (lmax 8) from the oracle:
+    the converged SPAI multigrid equals the DST solution of the same
+    compact discretisation."""
+    n = 64
+    say(f"SPAI converged order {order}")
+    wl = W.config_c2(n=n)
+    rho = wl.rho.numpy()
+    ghost, _ = OM.cart_boundary(rho, n, 1, 8)
+    plan = _plan(n, order)
+    phi = dev(ghost)
+    res = plan.solve(dev(rho), phi, tol=1e-13)
+    assert res.converged, res
+    ref = SP.solve_cart(ghost, rho, n, order)
+    s = slice(1, n)
+    assert rel_l2(host(phi)[s, s, s], ref[s, s, s]) < CONV_TOL
+
+
+def test_multipole_ghosts_and_rate_full_size():
+    """255^3 unknowns, order 4, GPU multipole boundary: converged against the
+    DST oracle on the ghosts the GPU wrote, at a V(3,3) contraction well
+    inside the Table 2 regime."""
+    n = 256
+    say("SPAI full size 256^3 order 4")
+    wl = W.config_c2(n=n, device="cuda:0")
+    rho_d = wl.rho.contiguous()
+    plan = pg.Plan(pg.cart_grid(n, ghost=1), pg.options("mg_spai", order=4, lmax=8))
+    phi = torch.zeros_like(rho_d)
+    res = plan.solve(rho_d, phi, tol=1e-12, history=64)
+    assert res.converged, res
+    say(f"  {res.iterations} cycles, rate {res.rate:.3g}")
+    assert res.rate < 0.05
+    got = host(phi)
+    ref = SP.solve_cart(got, host(rho_d), n, 4)
+    s = slice(1, n)
+    assert rel_l2(got[s, s, s], ref[s, s, s]) < CONV_TOL
+
+
+def test_spai_plans_reject_split_layout_operators():
+    plan = _plan(16, 2)
+    t = torch.zeros(17 ** 3, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(pg.PoissonError):
+        plan.apply(t, t)
+    with pytest.raises(pg.PoissonError):
+        plan.restrict(torch.zeros(15 ** 3, dtype=torch.float64, device="cuda:0"),
+                      torch.zeros(7 ** 3, dtype=torch.float64, device="cuda:0"))
+
+
+@pytest.mark.parametrize("order", [2, 4])
+def test_fp32_coarse_storage_vcycle(order):
+    """MG_SPAI32: one V(3,3) cycle against the oracle that rounds every value
+    stored on the coarse levels to FP32 (arithmetic FP64 on both sides), and
+    within FP32 rounding of the all-FP64 cycle."""
+    n = 64
+    say(f"SPAI32 one V-cycle order {order}")
+    phi, rho = _random(n, 300 + order)
+    plan = pg.Plan(pg.cart_grid(n, ghost=1), pg.options("mg_spai32", order=order, lmax=-1))
+    x = dev(phi)
+    plan.vcycle(dev(rho), x, 1)
+    ops = SP.level_operators(order, n)
+    f = SP.rhs_compact(rho, n, order)
+    ref32, ref64 = phi.copy(), phi.copy()
+    SP.vcycle(ref32, f, n, ops, SP.TABLE1[order], 3, 3, store32=True)
+    SP.vcycle(ref64, f, n, ops, SP.TABLE1[order], 3, 3)
+    got = host(x)
+    assert rel_max(got, ref32) < 1e-9
+    corr = np.max(np.abs(ref64 - phi))
+    assert np.max(np.abs(got - ref64)) < 1e-6 * corr
+
+
+def test_fp32_coarse_storage_converges_to_the_fp64_solution():
+    n = 64
+    say("SPAI32 converged")
+    wl = W.config_c2(n=n)
+    rho = wl.rho.numpy()
+    ghost, _ = OM.cart_boundary(rho, n, 1, 8)
+    plan = pg.Plan(pg.cart_grid(n, ghost=1), pg.options("mg_spai32", order=2, lmax=-1))
+    phi = dev(ghost)
+    res = plan.solve(dev(rho), phi, tol=1e-13)
+    assert res.converged, res
+    ref = SP.solve_cart(ghost, rho, n, 2)
+    s = slice(1, n)
+    assert rel_l2(host(phi)[s, s, s], ref[s, s, s]) < CONV_TOL
