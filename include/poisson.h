@@ -216,9 +216,9 @@ int poisson_op_vcycle(poisson_plan_t plan, const double* d_rho, double* d_phi, i
    fine-level arrays exactly as the last poisson_solve / poisson_op_* call
    left them, with no layout conversion: the smoother kernel alone, for
    timing it in its solver launch configuration.  MG / MG_IR32 plans sweep
-   their cycle's finest level (FP64 or FP32); MG_SPAI plans take SPAI steps
-   (residual kernel + smoother kernel) on theirs; other Cartesian plans sweep
-   the FP64 potential. */
+   their cycle's finest level (FP64 or FP32); MG_SPAI plans take 2 * sweeps
+   fused SPAI steps (out of place, so the result returns to where it
+   started) on theirs; other Cartesian plans sweep the FP64 potential. */
 int poisson_op_sweep_resident(poisson_plan_t plan, int32_t sweeps);
 
 /* ---- serving loop: continuous batching of independent solves -----------

@@ -211,6 +211,11 @@ void n27_residual(const void* u, const void* f, void* r, bool f32, const NGeom& 
                   double* partial, hipStream_t st);
 // u -= M r (M includes omega h^2)
 void n27_update(const void* r, void* u, bool f32, const NGeom& G, const W4& M, hipStream_t st);
+// fused Richardson step out of place: out = u - M (f - A u) at the unknowns
+// (ghost entries of out are not written)
+void n_spai_step(const void* u, const void* f, void* out, bool f32, const NGeom& G, const W4& A, const W4& M,
+                 hipStream_t st);
+void n_copy(const void* a, void* b, bool f32, const NGeom& G, hipStream_t st);
 void n_restrict(const void* r, bool f32_fine, const NGeom& Gf, void* fc, bool f32_coarse, const NGeom& Gc,
                 hipStream_t st);
 void n_prolong_add(const void* uc, bool f32_coarse, const NGeom& Gc, void* uf, bool f32_fine, const NGeom& Gf,

@@ -723,12 +723,10 @@ __global__ __launch_bounds__(256) void k_dense_split(const double* __restrict__ 
 }
 
 // ---------------------------------------------------------------- reductions
-__global__ __launch_bounds__(256) void k_finish(const double* __restrict__ partial, int nb, int nslots,
-                                                Scalars* __restrict__ scal, int dst) {
+__global__ __launch_bounds__(kFinishThreads) void k_finish(const double* __restrict__ partial, int nb, int nslots,
+                                                           Scalars* __restrict__ scal, int dst) {
   for (int slot = 0; slot < nslots; ++slot) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partial[slot * kPartialCap + i];
-    s = block_sum(s);
+    const double s = sum_partials(partial + slot * kPartialCap, nb);
     if (threadIdx.x == 0) scal->v[dst + slot] = s;
     __syncthreads();
   }
@@ -817,11 +815,9 @@ __global__ __launch_bounds__(256) void k_cg_upd(double* __restrict__ X, double* 
 
 // stage 0: v[4] = p.q (summed) -> alpha = rr / pq
 // stage 1: v[5] = new rr (summed) -> beta = rr_new / rr; rr = rr_new
-__global__ void k_cg_scalars(const double* __restrict__ partial, int nb, Scalars* __restrict__ scal,
-                             int stage) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) s += partial[i];
-  s = block_sum(s);
+__global__ __launch_bounds__(kFinishThreads) void k_cg_scalars(const double* __restrict__ partial, int nb,
+                                                               Scalars* __restrict__ scal, int stage) {
+  const double s = sum_partials(partial, nb);
   if (threadIdx.x == 0) {
     if (stage == 0) {
       scal->v[4] = s;
@@ -1023,7 +1019,7 @@ void split_to_dense(const void* split, bool f32, double* dense, const Geom& G, h
 }
 
 void finish_sum(const double* partial, int nb, int nslots, Scalars* scal, int dst, hipStream_t st) {
-  k_finish<<<1, 256, 0, st>>>(partial, nb, nslots, scal, dst);
+  k_finish<<<1, kFinishThreads, 0, st>>>(partial, nb, nslots, scal, dst);
 }
 
 int cg_blocks(const Geom& G) { return (int)nblocks(col_grid(G)); }
@@ -1043,7 +1039,7 @@ void cg_update(double* x, double* r, const double* p, const double* q, const Geo
 }
 
 void cg_scalars(const double* partial, int nb, Scalars* scal, int stage, hipStream_t st) {
-  k_cg_scalars<<<1, 256, 0, st>>>(partial, nb, scal, stage);
+  k_cg_scalars<<<1, kFinishThreads, 0, st>>>(partial, nb, scal, stage);
 }
 
 }  // namespace psn

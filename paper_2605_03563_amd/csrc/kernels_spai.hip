@@ -10,6 +10,8 @@
 // them for planes k-1, k, k+1 in registers, so
 //   (S u)(i,j,k) = w_c c_k + w_f (f4_k + c_{k-1} + c_{k+1})
 //                + w_e (e4_k + f4_{k-1} + f4_{k+1}) + w_k (e4_{k-1} + e4_{k+1}).
+#include <algorithm>
+
 #include "internal.h"
 #include "reduce.h"
 
@@ -84,6 +86,134 @@ __global__ __launch_bounds__(BX* BY) void k_n27(const T* __restrict__ src, const
   }
 }
 
+// One fused Richardson step out of place: out = u - M (f - A u) at the
+// unknowns (Eq. richardson), reading u and f once and writing out once.
+// A block owns a 64 x 8 output tile and a run of planes.  Per plane q it
+// loads u on the tile plus a 2-node halo into LDS, every thread forms the
+// in-plane sums (c, f4, e4) of u for its points of the 66 x 10 residual tile
+// (tile plus a 1-node halo) and keeps the last three planes of them in
+// registers, which gives r at plane q-1 (zero off the unknowns, so M acts on
+// r extended by zero); r goes to LDS, and the in-plane sums of r at the
+// thread's own column, again kept for three planes, give the output at plane
+// q-2.  Out of place because neighbouring tiles read the old u in their halos.
+constexpr int FX = 64, FY = 8;
+template <typename T>
+__global__ __launch_bounds__(FX* FY) void k_nspai(const T* __restrict__ u, const T* __restrict__ f,
+                                                  T* __restrict__ out, NGeom G, W4 A, W4 M) {
+  constexpr int UX = FX + 4, UY = FY + 4, RX = FX + 2, RY = FY + 2, NT = FX * FY;
+  __shared__ double Us[UY][UX];
+  __shared__ double Rs[RY][RX];
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int n = G.n;
+  const int tid = (int)threadIdx.x + FX * (int)threadIdx.y;
+  const int i0 = 1 + bx * FX, j0 = 1 + by * FY;
+  const int kz = (n - 1 + (int)gridDim.z - 1) / (int)gridDim.z;
+  const int kb = 1 + bz * kz;
+  const int ke = min(kb + kz - 1, n - 1);
+  if (kb > ke) return;  // uniform over the block
+  // residual-tile points of this thread: tid and tid + NT
+  int rx[2], ry[2];
+  bool rin[2];
+  const int np = (tid + NT < RX * RY) ? 2 : 1;
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int idx = tid + p * NT;
+    rx[p] = idx % RX;
+    ry[p] = idx / RX;
+    const int gi = i0 - 1 + rx[p], gj = j0 - 1 + ry[p];
+    rin[p] = p < np && gi >= 1 && gi <= n - 1 && gj >= 1 && gj <= n - 1;
+  }
+  const int oi = (int)threadIdx.x, oj = (int)threadIdx.y;
+  const int gi = i0 + oi, gj = j0 + oj;
+  const bool oin = gi <= n - 1 && gj <= n - 1;
+  auto lds_sums = [](const double* b, int pitch) {
+    Plane s;
+    s.c = b[0];
+    s.f = (b[-1] + b[1]) + (b[-pitch] + b[pitch]);
+    s.e = (b[-pitch - 1] + b[-pitch + 1]) + (b[pitch - 1] + b[pitch + 1]);
+    return s;
+  };
+  Plane us[2][3] = {};
+  Plane rs[3] = {};
+  double uown[3] = {0.0, 0.0, 0.0};
+  // software pipeline: the u plane for the next iteration and the f values
+  // of the next residual plane are loaded while this plane is computed
+  constexpr int NL = (UX * UY + NT - 1) / NT;  // u-tile entries per thread (2)
+  // per-thread tile offsets, fixed over the planes
+  long long uoff[NL];
+  bool uok[NL];
+#pragma unroll
+  for (int l = 0; l < NL; ++l) {
+    const int idx = tid + l * NT;
+    const int x = idx % UX, y = idx / UX;
+    const int gx = i0 - 2 + x, gy = j0 - 2 + y;
+    uok[l] = idx < UX * UY && gx >= 0 && gx <= n && gy >= 0 && gy <= n;
+    uoff[l] = uok[l] ? (long long)gy * G.W + gx : 0;
+  }
+  long long foff[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) foff[p] = rin[p] ? (long long)(j0 - 1 + ry[p]) * G.W + (i0 - 1 + rx[p]) : 0;
+  double ureg[NL];
+  auto load_u = [&](int q) {
+    const bool qok = q >= 0 && q <= n;
+    const long long base = (long long)q * G.P;
+#pragma unroll
+    for (int l = 0; l < NL; ++l) ureg[l] = (qok && uok[l]) ? (double)u[base + uoff[l]] : 0.0;
+  };
+  double freg[2] = {0.0, 0.0};
+  auto load_f = [&](int pr) {
+    const bool pok = pr >= 1 && pr <= n - 1;
+    const long long base = (long long)pr * G.P;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) freg[p] = (pok && rin[p]) ? (double)f[base + foff[p]] : 0.0;
+  };
+  load_u(kb - 2);
+  load_f(kb - 1);
+  for (int q = kb - 2; q <= ke + 2; ++q) {
+#pragma unroll
+    for (int l = 0; l < NL; ++l) {
+      const int idx = tid + l * NT;
+      if (idx < UX * UY) (&Us[0][0])[idx] = ureg[l];
+    }
+    __syncthreads();
+    if (q + 1 <= ke + 2) load_u(q + 1);
+    const double fcur0 = freg[0], fcur1 = freg[1];
+    if (q >= kb && q <= ke + 1) load_f(q);
+    uown[0] = uown[1];
+    uown[1] = uown[2];
+    uown[2] = Us[oj + 2][oi + 2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (p < np) {
+        us[p][0] = us[p][1];
+        us[p][1] = us[p][2];
+        us[p][2] = lds_sums(&Us[ry[p] + 1][rx[p] + 1], UX);
+        if (q >= kb) {
+          const int pr = q - 1;
+          double r = 0.0;
+          if (rin[p] && pr >= 1 && pr <= n - 1)
+            r = (p == 0 ? fcur0 : fcur1) - apply_sums(A, us[p][0], us[p][1], us[p][2]);
+          Rs[ry[p]][rx[p]] = r;
+        }
+      }
+    }
+    __syncthreads();
+    if (q >= kb) {
+      rs[0] = rs[1];
+      rs[1] = rs[2];
+      rs[2] = lds_sums(&Rs[oj + 1][oi + 1], RX);
+      if (q >= kb + 2 && oin)
+        __builtin_nontemporal_store((T)(uown[0] - apply_sums(M, rs[0], rs[1], rs[2])), out + G.at(gi, gj, q - 2));
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ncopy(const T* __restrict__ a, T* __restrict__ b, long long count) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < count; i += (long long)gridDim.x * 256) b[i] = a[i];
+}
+
 // coarse f(I,J,K) = full weighting of the fine residual around (2I,2J,2K)
 template <typename TF, typename TC>
 __global__ __launch_bounds__(BX* BY) void k_nrestrict(const TF* __restrict__ r, NGeom Gf, TC* __restrict__ fc,
@@ -105,7 +235,11 @@ __global__ __launch_bounds__(BX* BY) void k_nrestrict(const TF* __restrict__ r, 
   fc[Gc.at(I, J, K)] = (TC)((plane(c - Gf.P) + 2.0 * plane(c) + plane(c + Gf.P)) * (1.0 / 64.0));
 }
 
-// fine u += trilinear interpolation of the coarse correction (P = 8 R^T)
+// fine u += trilinear interpolation of the coarse correction (P = 8 R^T).
+// A thread owns a fine (i, j) column and marches k: b_K, the sum of the four
+// coarse values around (i, j) on coarse plane K (each counted twice when i or
+// j is even), is formed once per coarse plane; fine plane 2K takes 2 b_K,
+// plane 2K+1 takes b_K + b_{K+1}, both times 1/8.
 template <typename TC, typename TF>
 __global__ __launch_bounds__(BX* BY) void k_nprolong(const TC* __restrict__ uc, NGeom Gc, TF* __restrict__ uf,
                                                      NGeom Gf) {
@@ -113,14 +247,28 @@ __global__ __launch_bounds__(BX* BY) void k_nprolong(const TC* __restrict__ uc, 
   xcd_block(bx, by, bz);
   const int i = 1 + bx * BX + (int)threadIdx.x;
   const int j = 1 + by * BY + (int)threadIdx.y;
-  const int k = 1 + bz;
-  if (i >= Gf.n || j >= Gf.n || k >= Gf.n) return;
-  const int i0 = i >> 1, j0 = j >> 1, k0 = k >> 1;
-  const int i1 = i0 + (i & 1), j1 = j0 + (j & 1), k1 = k0 + (k & 1);
-  auto line = [&](int jj, int kk) { return (double)uc[Gc.at(i0, jj, kk)] + (double)uc[Gc.at(i1, jj, kk)]; };
-  const double s = (line(j0, k0) + line(j1, k0)) + (line(j0, k1) + line(j1, k1));
-  const long long q = Gf.at(i, j, k);
-  uf[q] = (TF)((double)uf[q] + 0.125 * s);
+  const int kz = (Gf.n - 1 + (int)gridDim.z - 1) / (int)gridDim.z;
+  const int k0 = 1 + bz * kz;
+  const int k1 = min(k0 + kz - 1, Gf.n - 1);
+  if (i >= Gf.n || j >= Gf.n || k0 > k1) return;
+  const int i0 = i >> 1, j0 = j >> 1;
+  const int i1 = i0 + (i & 1), j1 = j0 + (j & 1);
+  auto bsum = [&](int K) {
+    return ((double)uc[Gc.at(i0, j0, K)] + (double)uc[Gc.at(i1, j0, K)]) +
+           ((double)uc[Gc.at(i0, j1, K)] + (double)uc[Gc.at(i1, j1, K)]);
+  };
+  int Kc = k0 >> 1;
+  double bc = bsum(Kc), bn = bsum(Kc + 1);
+  for (int k = k0; k <= k1; ++k) {
+    if ((k >> 1) != Kc) {
+      Kc = k >> 1;
+      bc = bn;
+      bn = bsum(Kc + 1);
+    }
+    const double s = (k & 1) ? (bc + bn) : 2.0 * bc;
+    const long long q = Gf.at(i, j, k);
+    uf[q] = (TF)((double)uf[q] + 0.125 * s);
+  }
 }
 
 // coarsest level: u = A^-1 f with the dense inverse, one wavefront per row
@@ -223,6 +371,29 @@ void n27_update(const void* r, void* u, bool f32, const NGeom& G, const W4& M, h
                                                                 nullptr);
 }
 
+inline dim3 fgrid(const NGeom& G) {
+  const int e = G.n - 1;
+  const int kz = G.n >= 256 ? 32 : G.n >= 128 ? 16 : 4;
+  return dim3((e + FX - 1) / FX, (e + FY - 1) / FY, (e + kz - 1) / kz);
+}
+
+void n_spai_step(const void* u, const void* f, void* out, bool f32, const NGeom& G, const W4& A, const W4& M,
+                 hipStream_t st) {
+  if (f32)
+    k_nspai<float><<<fgrid(G), dim3(FX, FY), 0, st>>>((const float*)u, (const float*)f, (float*)out, G, A, M);
+  else
+    k_nspai<double><<<fgrid(G), dim3(FX, FY), 0, st>>>((const double*)u, (const double*)f, (double*)out, G, A, M);
+}
+
+void n_copy(const void* a, void* b, bool f32, const NGeom& G, hipStream_t st) {
+  const long long count = G.total();
+  const long long blocks = std::min<long long>((count + 255) / 256, 65536);
+  if (f32)
+    k_ncopy<float><<<(unsigned)blocks, 256, 0, st>>>((const float*)a, (float*)b, count);
+  else
+    k_ncopy<double><<<(unsigned)blocks, 256, 0, st>>>((const double*)a, (double*)b, count);
+}
+
 void n_restrict(const void* r, bool f32_fine, const NGeom& Gf, void* fc, bool f32_coarse, const NGeom& Gc,
                 hipStream_t st) {
   const dim3 gr = inner_grid(Gc), bl(BX, BY);
@@ -238,7 +409,7 @@ void n_restrict(const void* r, bool f32_fine, const NGeom& Gf, void* fc, bool f3
 
 void n_prolong_add(const void* uc, bool f32_coarse, const NGeom& Gc, void* uf, bool f32_fine, const NGeom& Gf,
                    hipStream_t st) {
-  const dim3 gr = inner_grid(Gf), bl(BX, BY);
+  const dim3 gr = ngrid(Gf), bl(BX, BY);
   if (f32_coarse && f32_fine)
     k_nprolong<float, float><<<gr, bl, 0, st>>>((const float*)uc, Gc, (float*)uf, Gf);
   else if (f32_coarse && !f32_fine)

@@ -197,15 +197,11 @@ __global__ __launch_bounds__(256) void k_pbicg_xr(double* __restrict__ X, double
 
 // stage 0: alpha = rho / (rhat.v); stage 1: omega = (t.s)/(t.t);
 // stage 2: beta = (rho_new/rho)(alpha/omega), rho = rho_new, v[7] = r.r
-__global__ void k_bicg_scalars(const double* __restrict__ partial, int nb, Scalars* __restrict__ scal, int stage) {
-  double s0 = 0.0, s1 = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-    s0 += partial[b];
-    if (stage > 0) s1 += partial[kPartialCap + b];
-  }
-  s0 = block_sum(s0);
+__global__ __launch_bounds__(kFinishThreads) void k_bicg_scalars(const double* __restrict__ partial, int nb,
+                                                                 Scalars* __restrict__ scal, int stage) {
+  const double s0 = sum_partials(partial, nb);
   __syncthreads();
-  s1 = block_sum(s1);
+  const double s1 = stage > 0 ? sum_partials(partial + kPartialCap, nb) : 0.0;
   if (threadIdx.x == 0) {
     double* v = scal->v;
     if (stage == 0) {
@@ -457,7 +453,7 @@ void pbicg_xr(double* x, double* r, const double* phat, const double* shat, cons
 }
 
 void bicg_scalars(const double* partial, int nb, Scalars* scal, int stage, hipStream_t st) {
-  k_bicg_scalars<<<1, 256, 0, st>>>(partial, nb, scal, stage);
+  k_bicg_scalars<<<1, kFinishThreads, 0, st>>>(partial, nb, scal, stage);
 }
 
 void sph_line_pass(const SLev& L, int colour, hipStream_t st) {

@@ -86,14 +86,20 @@ std::vector<std::array<int, 3>> sph_levels(int nr, int nth, int nph) {
   return out;
 }
 
-// Split of a phi line of nph nodes for the line smoother: segments of seg
-// nodes (the largest divisor of nph up to 32), nseg = nph / seg of them, nl
-// lines per block (a power of two, <= 64 lines, <= 1024 threads and the LDS
-// of Y plus the interface values within 64 KiB).  False if no split fits.
+// Split of a phi line of nph nodes for the line smoother: eight segments
+// when nph is a multiple of 16 and at most 256 (short sequential
+// recurrences on the coarse levels, where the pass is latency bound), else
+// segments of the largest divisor of nph up to 32; nseg = nph / seg of them,
+// nl lines per block (a power of two, <= 64 lines, <= 1024 threads and the
+// LDS of Y plus the interface values within 64 KiB).  False if no split fits.
 bool line_split(int nph, int* seg, int* nseg, int* nl) {
   int L = 1;
-  for (int d = 2; d <= 32 && d <= nph; ++d)
-    if (nph % d == 0) L = d;
+  if (nph % 16 == 0 && nph <= 256) {
+    L = nph / 8;
+  } else {
+    for (int d = 2; d <= 32 && d <= nph; ++d)
+      if (nph % d == 0) L = d;
+  }
   const int P = nph / L;
   if (L < 2 || P > 64) return false;
   int n = 64;
@@ -316,9 +322,11 @@ void carve(poisson_plan_s* P, Carver& cv) {
       L.G = make_ngeom(nl, h * (n / nl));
       L.f32 = o.method == POISSON_MG_SPAI32 && nl != n;
       const size_t b = (L.f32 ? sizeof(float) : sizeof(double)) * L.G.total();
+      const bool dense_only = nl == o.coarsest && nl != n;  // coarsest below the finest: solved densely
       L.u = cv.take(b);
+      L.u2 = dense_only ? nullptr : cv.take(b);
       L.f = cv.take(b);
-      L.r = (nl == o.coarsest) ? nullptr : cv.take(b);
+      L.r = dense_only ? nullptr : cv.take(b);
       P->nlv.push_back(L);
       if (nl == o.coarsest) break;
     }
@@ -713,28 +721,35 @@ int capture_sph_iteration(poisson_plan_s* P, double* phi) {
   return POISSON_OK;
 }
 
-// One SPAI V(nu1, nu2) cycle from level l: Richardson steps u -= M (f - A u)
-// (Eq. richardson), Galerkin coarse problems on a zero initial guess.
+// `steps` fused Richardson steps on level L, alternating between u and u2;
+// returns the array holding the result.
+void* spai_smooth(NLevel& L, void* cur, int steps, hipStream_t st) {
+  for (int s = 0; s < steps; ++s) {
+    void* nxt = (cur == L.u) ? L.u2 : L.u;
+    n_spai_step(cur, L.f, nxt, L.f32, L.G, L.A, L.M, st);
+    cur = nxt;
+  }
+  return cur;
+}
+
+// One SPAI V(nu1, nu2) cycle from level l: Richardson steps u <- u - M (f - A u)
+// (Eq. richardson), Galerkin coarse problems on a zero initial guess.  The
+// result is left in L.u (copied back when the step count is odd).
 void spai_vcycle(poisson_plan_s* P, int l, hipStream_t st) {
   NLevel& L = P->nlv[l];
   if (l + 1 == (int)P->nlv.size()) {
     n_coarse(P->cinv, L.f, L.u, L.f32, L.G, st);
     return;
   }
-  for (int s = 0; s < P->opts.nu1; ++s) {
-    n27_residual(L.u, L.f, L.r, L.f32, L.G, L.A, false, nullptr, st);
-    n27_update(L.r, L.u, L.f32, L.G, L.M, st);
-  }
-  n27_residual(L.u, L.f, L.r, L.f32, L.G, L.A, false, nullptr, st);
+  void* cur = spai_smooth(L, L.u, P->opts.nu1, st);
+  n27_residual(cur, L.f, L.r, L.f32, L.G, L.A, false, nullptr, st);
   NLevel& C = P->nlv[l + 1];
   n_restrict(L.r, L.f32, L.G, C.f, C.f32, C.G, st);
   fill_zero(C.u, C.f32, C.G.total(), st);
   spai_vcycle(P, l + 1, st);
-  n_prolong_add(C.u, C.f32, C.G, L.u, L.f32, L.G, st);
-  for (int s = 0; s < P->opts.nu2; ++s) {
-    n27_residual(L.u, L.f, L.r, L.f32, L.G, L.A, false, nullptr, st);
-    n27_update(L.r, L.u, L.f32, L.G, L.M, st);
-  }
+  n_prolong_add(C.u, C.f32, C.G, cur, L.f32, L.G, st);
+  cur = spai_smooth(L, cur, P->opts.nu2, st);
+  if (cur != L.u) n_copy(cur, L.u, L.f32, L.G, st);
 }
 
 void spai_step(poisson_plan_s* P, hipStream_t st) {
@@ -894,6 +909,7 @@ int solve_spai(poisson_plan_s* P, const double* rho, double* phi, double tol, po
   n27_residual(L.u, L.f, nullptr, false, L.G, L.A, true, P->partial, st);
   finish_sum(P->partial, nb, 1, P->scal, kBnorm2, st);
   n_from_caller(phi, g.pitch[0], g.pitch[1], (double*)L.u, L.G, false, st);
+  if (L.u2) n_from_caller(phi, g.pitch[0], g.pitch[1], (double*)L.u2, L.G, false, st);
   n27_residual(L.u, L.f, nullptr, false, L.G, L.A, true, P->partial, st);
   finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
   CHK(launch_check("SPAI setup"));
@@ -1527,11 +1543,9 @@ int poisson_op_smooth(poisson_plan_t P, const double* d_rho, double* d_phi, int3
     NLevel& L = P->nlv[0];
     n_rhs(d_rho, g.pitch[0], g.pitch[1], (double*)L.f, L.G, P->order, P->opts.four_pi_G, st);
     n_from_caller(d_phi, g.pitch[0], g.pitch[1], (double*)L.u, L.G, false, st);
-    for (int s = 0; s < sweeps; ++s) {
-      n27_residual(L.u, L.f, L.r, false, L.G, L.A, false, nullptr, st);
-      n27_update(L.r, L.u, false, L.G, L.M, st);
-    }
-    n_to_caller((const double*)L.u, L.G, d_phi, g.pitch[0], g.pitch[1], st);
+    if (L.u2) n_from_caller(d_phi, g.pitch[0], g.pitch[1], (double*)L.u2, L.G, false, st);
+    const void* cur = spai_smooth(L, L.u, sweeps, st);
+    n_to_caller((const double*)cur, L.G, d_phi, g.pitch[0], g.pitch[1], st);
     return launch_check("poisson_op_smooth");
   }
   split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);
@@ -1586,6 +1600,7 @@ int poisson_op_vcycle(poisson_plan_t P, const double* d_rho, double* d_phi, int3
     NLevel& L = P->nlv[0];
     n_rhs(d_rho, g.pitch[0], g.pitch[1], (double*)L.f, L.G, P->order, P->opts.four_pi_G, st);
     n_from_caller(d_phi, g.pitch[0], g.pitch[1], (double*)L.u, L.G, false, st);
+    if (L.u2) n_from_caller(d_phi, g.pitch[0], g.pitch[1], (double*)L.u2, L.G, false, st);
     for (int c = 0; c < cycles; ++c) spai_step(P, st);
     n_to_caller((const double*)L.u, L.G, d_phi, g.pitch[0], g.pitch[1], st);
     return launch_check("poisson_op_vcycle");
@@ -1605,11 +1620,9 @@ int poisson_op_sweep_resident(poisson_plan_t P, int32_t sweeps) {
     return POISSON_EINVAL;
   }
   if (!P->nlv.empty()) {
+    // an even number of out-of-place steps leaves the result where it started
     NLevel& L = P->nlv[0];
-    for (int s = 0; s < sweeps; ++s) {
-      n27_residual(L.u, L.f, L.r, false, L.G, L.A, false, nullptr, P->st);
-      n27_update(L.r, L.u, false, L.G, L.M, P->st);
-    }
+    if (L.u2) spai_smooth(L, L.u, 2 * sweeps, P->st);
     return launch_check("poisson_op_sweep_resident");
   }
   void* phi = P->phi64;

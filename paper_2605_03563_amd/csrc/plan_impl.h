@@ -22,6 +22,7 @@ struct Level {
 struct NLevel {
   NGeom G{};
   void* u = nullptr;
+  void* u2 = nullptr;  // partner of u for the out-of-place smoothing steps (same ghosts)
   void* f = nullptr;
   void* r = nullptr;
   bool f32 = false;  // stored in FP32 (coarse levels of MG_SPAI32); arithmetic FP64

@@ -53,4 +53,26 @@ __device__ inline double block_sum(double v) {
   return s;
 }
 
+// Sum of p[0 .. nb) by one block in a fixed order: thread t takes the
+// entries t, t + T, t + 2T, ... into four interleaved accumulators (four
+// independent loads in flight per round), then the block reduces.  Result
+// valid in thread 0.  Call from every thread of the block.
+__device__ inline double sum_partials(const double* __restrict__ p, int nb) {
+  const int T = blockDim.x * blockDim.y * blockDim.z;
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = tid;
+  for (; i + 3 * T < nb; i += 4 * T) {
+    a0 += p[i];
+    a1 += p[i + T];
+    a2 += p[i + 2 * T];
+    a3 += p[i + 3 * T];
+  }
+  for (; i < nb; i += T) a0 += p[i];
+  return block_sum((a0 + a1) + (a2 + a3));
+}
+
+// threads of the one-block kernels that finish a reduction
+constexpr int kFinishThreads = 1024;
+
 }  // namespace psn
