@@ -182,11 +182,34 @@ def coarse_dense(w_abs, n: int) -> np.ndarray:
     return A
 
 
-def vcycle(u, f_int, n, ops, coef, nu1=3, nu2=3, level=0, _cache=None, store32=False):
+def cg_coarse(w_abs, b: np.ndarray, n: int, rtol: float, maxit: int = 10000):
+    """Conjugate gradients on A = -stencil (SPD) from a zero guess, stopped
+    once ||b - L x|| <= rtol ||b|| (Section 2.1.2's CG, used as the coarsest
+    solve of Section 2.1.3).  Returns (x, iterations)."""
+    x = np.zeros_like(b)
+    r = b.copy()            # residual of L x = b with x = 0
+    p = r.copy()
+    rr = float(np.sum(r * r))
+    stop = rtol * rtol * rr
+    it = 0
+    while rr > stop and it < maxit:
+        q = -apply27(embed(p), n, w_abs)      # A p with A = -L
+        alpha = rr / float(np.sum(p * q))
+        x = x - alpha * p                     # L x = b  <=>  A x = -b
+        r = r - alpha * q
+        rr_new = float(np.sum(r * r))
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        it += 1
+    return x, it
+
+
+def vcycle(u, f_int, n, ops, coef, nu1=3, nu2=3, level=0, _cache=None, store32=False, coarse_rtol=0.0):
     """One V(nu1, nu2) cycle with SPAI smoothing and Galerkin coarse
     operators on the node array u (one ghost layer, ghosts fixed); f_int is
     the right-hand side at the unknowns.  The coarsest level is solved
-    exactly (dense).  store32: every level below the finest stores its data
+    exactly (dense), or by CG to relative accuracy coarse_rtol when that is
+    positive.  store32: every level below the finest stores its data
     (u, f, r) in FP32 while all arithmetic stays FP64 (Section 2.1.3's mixed
     precision)."""
     if _cache is None:
@@ -195,12 +218,16 @@ def vcycle(u, f_int, n, ops, coef, nu1=3, nu2=3, level=0, _cache=None, store32=F
     w = ops[level]
     s32 = store32 and level > 0
     if level == len(ops) - 1:
-        key = (n, w)
-        if key not in _cache:
-            _cache[key] = np.linalg.inv(coarse_dense(w, n))
         z = u.copy()
         z[1:n, 1:n, 1:n] = 0.0
         rhs = f_int - apply27(z, n, w)
+        if coarse_rtol > 0.0:
+            x, _ = cg_coarse(w, rhs, n, coarse_rtol)
+            u[1:n, 1:n, 1:n] = _stored(x, s32)
+            return u
+        key = (n, w)
+        if key not in _cache:
+            _cache[key] = np.linalg.inv(coarse_dense(w, n))
         u[1:n, 1:n, 1:n] = _stored((_cache[key] @ rhs.ravel()).reshape(rhs.shape), s32)
         return u
     for _ in range(nu1):
@@ -209,7 +236,7 @@ def vcycle(u, f_int, n, ops, coef, nu1=3, nu2=3, level=0, _cache=None, store32=F
     nc = n // 2
     rc = _stored(S.restrict(r), store32)
     ec = np.zeros((nc + 1,) * 3)
-    vcycle(ec, rc, nc, ops, coef, nu1, nu2, level + 1, _cache, store32)
+    vcycle(ec, rc, nc, ops, coef, nu1, nu2, level + 1, _cache, store32, coarse_rtol)
     u[1:n, 1:n, 1:n] = _stored(u[1:n, 1:n, 1:n] + S.prolong(ec[1:nc, 1:nc, 1:nc]), s32)
     for _ in range(nu2):
         spai_step(u, f_int, n, w, coef, h, s32)

@@ -238,3 +238,40 @@ def test_fp32_coarse_storage_keeps_the_fixed_point_and_rate():
     corr = np.max(np.abs(a - u0))
     d = np.max(np.abs(a - b))
     assert 0.0 < d < 1e-6 * corr
+
+
+def test_cg_coarse_solve_reaches_its_tolerance_and_the_dense_solution():
+    """The CG coarsest solve stops at the requested relative residual and,
+    driven to round-off, equals the dense inverse (and needs at most as many
+    steps as the operator has distinct eigenvalues, 7 per axis here)."""
+    n = 8
+    ops = SP.level_operators(4, 32)
+    w = ops[-1]
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal((n - 1,) * 3)
+    x, it = SP.cg_coarse(w, b, n, 0.013)
+    r = b - SP.apply27(SP.embed(x), n, w)
+    assert np.linalg.norm(r) <= 0.013 * np.linalg.norm(b) and it >= 1
+    x_full, it_full = SP.cg_coarse(w, b, n, 1e-14)
+    ref = np.linalg.solve(SP.coarse_dense(w, n), b.ravel()).reshape(b.shape)
+    assert np.allclose(x_full, ref, rtol=0, atol=1e-11 * np.max(np.abs(ref)))
+    assert it_full <= 7 * 7 * 7
+
+
+def test_vcycle_with_cg_coarsest_keeps_the_rate():
+    """Section 2.1.3: solving the coarsest problem only to relative accuracy
+    rho keeps the cycle's contraction (here within 20% of the exact coarsest
+    solve at 31^3, V(3,3), order 2, rho = 0.013)."""
+    n = 32
+    ops = SP.level_operators(2, n)
+    rng = np.random.default_rng(1)
+    f = np.zeros((n - 1,) * 3)
+    rates = []
+    for rtol in (0.0, 0.013):
+        u = SP.embed(rng.standard_normal((n - 1,) * 3))
+        rs = [np.linalg.norm(SP.apply27(u, n, ops[0]))]
+        for _ in range(5):
+            SP.vcycle(u, f, n, ops, SP.TABLE1[2], 3, 3, coarse_rtol=rtol)
+            rs.append(np.linalg.norm(SP.apply27(u, n, ops[0])))
+        rates.append(rs[-1] / rs[-2])
+    assert rates[1] < 1.2 * rates[0], rates
