@@ -111,6 +111,9 @@ typedef struct {
     double  omega;       /* SOR with POISSON_OMEGA_FIXED */
     double  four_pi_G;   /* 4 pi G */
     double  point_mass;  /* mass of a point at the expansion origin (central sink), 0 for none */
+    double  coarse_tol;  /* POISSON_MG_SPAI(32): 0 = coarsest level by its dense inverse; in (0, 1):
+                            by CG from a zero guess to this relative residual (Section 2.1.3
+                            takes the cycle's rate), coarsest <= 12 intervals */
 } poisson_opts_t;
 
 typedef struct {

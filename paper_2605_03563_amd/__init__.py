@@ -84,7 +84,7 @@ def array_shape(grid) -> tuple:
 
 
 def options(method="mg", order=2, lmax=8, nu1=None, nu2=None, coarsest=8, omega_mode=OMEGA_OPT, omega=1.0,
-            max_iter=10000, check_every=1, four_pi_G=1.0, point_mass=0.0):
+            max_iter=10000, check_every=1, four_pi_G=1.0, point_mass=0.0, coarse_tol=0.0):
     """Solver options; nu1 / nu2 default to the library's per-method values
     (V(2,2), V(3,3) for the SPAI multigrid)."""
     o = L.Opts()
@@ -95,7 +95,7 @@ def options(method="mg", order=2, lmax=8, nu1=None, nu2=None, coarsest=8, omega_
     if nu2 is not None:
         o.nu2 = nu2
     o.omega_mode, o.omega, o.max_iter, o.check_every = omega_mode, omega, max_iter, check_every
-    o.four_pi_G, o.point_mass = four_pi_G, point_mass
+    o.four_pi_G, o.point_mass, o.coarse_tol = four_pi_G, point_mass, coarse_tol
     return o
 
 

@@ -26,7 +26,7 @@ class Opts(C.Structure):
                 ("nu1", C.c_int32), ("nu2", C.c_int32), ("coarsest", C.c_int32),
                 ("omega_mode", C.c_int32), ("max_iter", C.c_int32), ("check_every", C.c_int32),
                 ("pad_", C.c_int32), ("omega", C.c_double), ("four_pi_G", C.c_double),
-                ("point_mass", C.c_double)]
+                ("point_mass", C.c_double), ("coarse_tol", C.c_double)]
 
 
 class Stats(C.Structure):

@@ -221,6 +221,9 @@ void n_restrict(const void* r, bool f32_fine, const NGeom& Gf, void* fc, bool f3
 void n_prolong_add(const void* uc, bool f32_coarse, const NGeom& Gc, void* uf, bool f32_fine, const NGeom& Gf,
                    hipStream_t st);
 void n_coarse(const double* inv, const void* f, void* u, bool f32, const NGeom& G, hipStream_t st);
+// coarsest level by CG to relative residual rtol (one block, LDS resident)
+size_t n_cg_lds_bytes(const NGeom& G);
+void n_coarse_cg(const void* f, void* u, bool f32, const NGeom& G, const W4& A, double rtol, hipStream_t st);
 void n_from_caller(const double* src, long long p0, long long p1, double* u, const NGeom& G, bool zero_inner,
                    hipStream_t st);
 void n_rhs(const double* rho, long long p0, long long p1, double* f, const NGeom& G, int order, double scale,

@@ -292,6 +292,85 @@ __global__ __launch_bounds__(256) void k_ncoarse(const double* __restrict__ inv,
   }
 }
 
+// coarsest level by conjugate gradients on A = -L (SPD) from a zero guess,
+// one block, everything in LDS: p with a zero ghost layer, x, r, q.  Stops
+// once ||r|| <= rtol ||f|| or after maxit steps (Section 2.1.2's CG as the
+// coarsest solve of Section 2.1.3).  Sums are block reductions in a fixed
+// order.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_ncg(const T* __restrict__ f, T* __restrict__ u, NGeom G, W4 A,
+                                              double rtol, int maxit) {
+  extern __shared__ double sh[];
+  __shared__ double bc;
+  const int E = G.n - 1, EP = E + 2, N = E * E * E;
+  double* pp = sh;
+  double* x = pp + EP * EP * EP;
+  double* r = x + N;
+  double* q = r + N;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  auto pad = [&](int c) {
+    const int i = c % E, j = (c / E) % E, k = c / (E * E);
+    return ((k + 1) * EP + (j + 1)) * EP + (i + 1);
+  };
+  auto at = [&](int c) {
+    const int i = c % E, j = (c / E) % E, k = c / (E * E);
+    return G.at(i + 1, j + 1, k + 1);
+  };
+  for (int c = tid; c < EP * EP * EP; c += nt) pp[c] = 0.0;
+  __syncthreads();
+  double part = 0.0;
+  for (int c = tid; c < N; c += nt) {
+    const double v = (double)f[at(c)];
+    x[c] = 0.0;
+    r[c] = v;
+    pp[pad(c)] = v;
+    part += v * v;
+  }
+  auto allsum = [&](double v) {
+    const double s = block_sum(v);
+    if (tid == 0) bc = s;
+    __syncthreads();
+    const double out = bc;
+    __syncthreads();
+    return out;
+  };
+  double rr = allsum(part);
+  const double stop = rtol * rtol * rr;
+  for (int it = 0; it < maxit && rr > stop; ++it) {
+    part = 0.0;
+    for (int c = tid; c < N; c += nt) {
+      const int o = pad(c);
+      const double* b = pp + o;
+      double fc = 0.0, ec = 0.0, kc = 0.0;
+      for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int nz = (dx != 0) + (dy != 0) + (dz != 0);
+            const double v = b[(dz * EP + dy) * EP + dx];
+            if (nz == 1) fc += v;
+            else if (nz == 2) ec += v;
+            else if (nz == 3) kc += v;
+          }
+      const double qv = -(A.c * b[0] + A.f * fc + A.e * ec + A.k * kc);
+      q[c] = qv;
+      part += b[0] * qv;
+    }
+    const double alpha = rr / allsum(part);
+    part = 0.0;
+    for (int c = tid; c < N; c += nt) {
+      x[c] -= alpha * pp[pad(c)];
+      r[c] -= alpha * q[c];
+      part += r[c] * r[c];
+    }
+    const double rr_new = allsum(part);
+    const double beta = rr_new / rr;
+    for (int c = tid; c < N; c += nt) pp[pad(c)] = r[c] + beta * pp[pad(c)];
+    __syncthreads();
+    rr = rr_new;
+  }
+  for (int c = tid; c < N; c += nt) u[at(c)] = (T)x[c];
+}
+
 // caller node array (one ghost layer, pitches p0, p1) -> level array;
 // interior zeroed when zero_inner
 __global__ __launch_bounds__(BX* BY) void k_nin(const double* __restrict__ src, long long p0, long long p1,
@@ -427,6 +506,21 @@ void n_coarse(const double* inv, const void* f, void* u, bool f32, const NGeom& 
     k_ncoarse<float><<<(N + 3) / 4, 256, 0, st>>>(inv, (const float*)f, (float*)u, G);
   else
     k_ncoarse<double><<<(N + 3) / 4, 256, 0, st>>>(inv, (const double*)f, (double*)u, G);
+}
+
+size_t n_cg_lds_bytes(const NGeom& G) {
+  const size_t E = G.n - 1, EP = E + 2;
+  return sizeof(double) * (EP * EP * EP + 3 * E * E * E);
+}
+
+void n_coarse_cg(const void* f, void* u, bool f32, const NGeom& G, const W4& A, double rtol, hipStream_t st) {
+  const int E = G.n - 1;
+  const int maxit = 2 * E * E * E;
+  const size_t lds = n_cg_lds_bytes(G);
+  if (f32)
+    k_ncg<float><<<1, 1024, lds, st>>>((const float*)f, (float*)u, G, A, rtol, maxit);
+  else
+    k_ncg<double><<<1, 1024, lds, st>>>((const double*)f, (double*)u, G, A, rtol, maxit);
 }
 
 void n_from_caller(const double* src, long long p0, long long p1, double* u, const NGeom& G, bool zero_inner,

@@ -124,6 +124,14 @@ int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
     set_error("max_iter and check_every must be >= 1");
     return POISSON_EINVAL;
   }
+  if (!(o->coarse_tol >= 0.0 && o->coarse_tol < 1.0)) {
+    set_error("coarse_tol must lie in [0, 1)");
+    return POISSON_EINVAL;
+  }
+  if (o->coarse_tol != 0.0 && o->method != POISSON_MG_SPAI && o->method != POISSON_MG_SPAI32) {
+    set_error("coarse_tol applies to the SPAI multigrid only");
+    return POISSON_EINVAL;
+  }
   if (!(o->four_pi_G > 0.0)) {
     set_error("four_pi_G must be positive");
     return POISSON_EINVAL;
@@ -201,6 +209,10 @@ int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
   if (o->method == POISSON_MG_SPAI || o->method == POISSON_MG_SPAI32) {
     if (o->order != 2 && o->order != 4) {
       set_error("the SPAI multigrid takes the compact stencils of order 2 or 4");
+      return POISSON_EINVAL;
+    }
+    if (o->coarse_tol > 0.0 && o->coarsest > 12) {
+      set_error("the CG coarsest solve keeps its level in LDS: coarsest <= 12 intervals");
       return POISSON_EINVAL;
     }
   } else if (o->order != 2 && o->order != 6) {
@@ -738,7 +750,10 @@ void* spai_smooth(NLevel& L, void* cur, int steps, hipStream_t st) {
 void spai_vcycle(poisson_plan_s* P, int l, hipStream_t st) {
   NLevel& L = P->nlv[l];
   if (l + 1 == (int)P->nlv.size()) {
-    n_coarse(P->cinv, L.f, L.u, L.f32, L.G, st);
+    if (P->opts.coarse_tol > 0.0)
+      n_coarse_cg(L.f, L.u, L.f32, L.G, L.A, P->opts.coarse_tol, st);
+    else
+      n_coarse(P->cinv, L.f, L.u, L.f32, L.G, st);
     return;
   }
   void* cur = spai_smooth(L, L.u, P->opts.nu1, st);

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_function():
 
 def test_struct_layouts_match_header_sizes():
     assert C.sizeof(L.Grid) == 4 + 12 + 24 + 24 + 4 + 4 + 16
-    assert C.sizeof(L.Opts) == 10 * 4 + 3 * 8
+    assert C.sizeof(L.Opts) == 10 * 4 + 4 * 8
     assert C.sizeof(L.Stats) == 8 + 5 * 8 + 8 + 8
 
 
@@ -134,3 +134,15 @@ def test_plan_rejects_small_or_misaligned_workspace_before_any_device_call():
     st = lib.poisson_plan(C.byref(h), C.byref(grid), C.byref(opts), None, need, None)
     assert st == L.EWORKSPACE
     assert h.value is None
+
+
+def test_coarse_tol_validation():
+    lib = L.load()
+    g = pg.cart_grid(32)
+    assert lib.poisson_workspace_bytes(C.byref(g), C.byref(pg.options("mg_spai", coarse_tol=0.013))) > 0
+    assert lib.poisson_workspace_bytes(C.byref(g), C.byref(pg.options("mg", coarse_tol=0.013))) == 0
+    assert lib.poisson_workspace_bytes(C.byref(g), C.byref(pg.options("mg_spai", coarse_tol=1.5))) == 0
+    assert lib.poisson_workspace_bytes(C.byref(pg.cart_grid(64)),
+                                       C.byref(pg.options("mg_spai", coarse_tol=0.1, coarsest=16))) == 0
+    s = pg.sph_grid(32, 16, 16)
+    assert lib.poisson_workspace_bytes(C.byref(s), C.byref(pg.options("bicgstab", coarse_tol=0.1))) == 0

@@ -160,3 +160,31 @@ def test_fp32_coarse_storage_converges_to_the_fp64_solution():
     ref = SP.solve_cart(ghost, rho, n, 2)
     s = slice(1, n)
     assert rel_l2(host(phi)[s, s, s], ref[s, s, s]) < CONV_TOL
+
+
+@pytest.mark.parametrize("order,coarsest", [(2, 8), (4, 4)])
+def test_cg_coarsest_vcycle_and_solve(order, coarsest):
+    """Coarsest level by CG to relative accuracy 0.013 (Section 2.1.3): one
+    V-cycle against the oracle's cycle with the same CG coarsest solve, and a
+    converged solve against the exact discrete solution."""
+    n = 64
+    say(f"SPAI CG coarsest order {order} coarsest {coarsest}")
+    phi, rho = _random(n, 500 + order)
+    plan = pg.Plan(pg.cart_grid(n, ghost=1),
+                   pg.options("mg_spai", order=order, lmax=-1, coarsest=coarsest, coarse_tol=0.013))
+    x = dev(phi)
+    plan.vcycle(dev(rho), x, 1)
+    ops = SP.level_operators(order, n, coarsest)
+    f = SP.rhs_compact(rho, n, order)
+    ref = phi.copy()
+    SP.vcycle(ref, f, n, ops, SP.TABLE1[order], 3, 3, coarse_rtol=0.013)
+    assert rel_max(host(x), ref) < 1e-10
+    wl = W.config_c2(n=n)
+    rho2 = wl.rho.numpy()
+    ghost, _ = OM.cart_boundary(rho2, n, 1, 8)
+    phi2 = dev(ghost)
+    res = plan.solve(dev(rho2), phi2, tol=1e-13)
+    assert res.converged, res
+    ref2 = SP.solve_cart(ghost, rho2, n, order)
+    s = slice(1, n)
+    assert rel_l2(host(phi2)[s, s, s], ref2[s, s, s]) < CONV_TOL
