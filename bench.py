@@ -167,6 +167,16 @@ def c4(args):
         sec, res = _time_solves(plan, rho, phi, args.tol, steps, 1)
         runs[m] = (sec, res, steps)
         del plan, phi
+    # SOR with the local Chebyshev relaxation sequence (Eq. local_rjac), one solve
+    plan = pg.Plan(grid, pg.options("sor", lmax=8, point_mass=4 * math.pi * g.r_min, max_iter=40000,
+                                    check_every=50, omega_mode=pg.OMEGA_CHEBYSHEV), device=dev)
+    phi = torch.zeros_like(rho)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rsor = plan.solve(rho, phi, tol=args.tol)
+    torch.cuda.synchronize()
+    ssor = time.perf_counter() - t0
+    del plan, phi
     sec, res, steps = runs["bicgstab_mg32"]
     sgs, rgs, _ = runs["bicgstab"]
     gs_it_ms = rgs.t_iter_ms / max(1, rgs.iterations)
@@ -182,6 +192,9 @@ def c4(args):
                               "ms_per_iteration": gs_it_ms,
                               "iteration_GBps_algorithmic": bytes_per_it / (gs_it_ms * 1e-3) / 1e9},
         "speedup_mg_vs_gs": sgs / sec,
+        "sor_local_chebyshev": {"time_ms": ssor * 1e3, "converged": rsor.converged, "sweeps": rsor.iterations,
+                                "rel_residual": rsor.rel_residual,
+                                "ms_per_sweep": rsor.t_iter_ms / max(1, rsor.iterations)},
     }
     print(json.dumps(out), flush=True)
 

@@ -58,7 +58,11 @@ extern "C" {
 #define POISSON_CARTESIAN      0
 #define POISSON_SPHERICAL_LOG  1
 
-#define POISSON_SOR            0  /* red-black SOR (Section 2.1.1) */
+#define POISSON_SOR            0  /* red-black SOR (Section 2.1.1); on spherical grids four
+                                     colours (parity, half turn) and relaxation factors per
+                                     colatitude from Eq. local_rjac: omega_mode OPT (local
+                                     omega_opt), CHEBYSHEV (local Eq. omega_n from n = 1) or
+                                     FIXED */
 #define POISSON_CG             1  /* conjugate gradients (Section 2.1.2) */
 #define POISSON_BICGSTAB       2  /* BiCGSTAB, spherical grids (Section 2.1.2), right-preconditioned
                                      by one red-black Gauss-Seidel step (Section 2.1.1) */
@@ -199,7 +203,10 @@ int poisson_op_residual(poisson_plan_t plan, const double* d_rho, const double* 
    otherwise; red-black with relaxation omega for order 2 (Section 2.1.1),
    four colours with omega = 1 for order 6 (Section 2.1.2).  POISSON_MG_SPAI
    plans: `sweeps` steps of the SPAI Richardson smoother (Eq. richardson;
-   forward and omega are ignored). */
+   forward and omega are ignored).  Spherical POISSON_SOR plans: `sweeps`
+   SOR sweeps (colours 0, 2 then 1, 3) with the plan's per-colatitude
+   relaxation factors from the start of their sequence (forward and omega are
+   ignored). */
 int poisson_op_smooth(poisson_plan_t plan, const double* d_rho, double* d_phi, int32_t sweeps,
                       int32_t forward, double omega);
 

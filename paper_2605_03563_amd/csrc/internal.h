@@ -171,6 +171,12 @@ struct SphCoef { const double* cot; const double* isin2; const double* r2; };
 void sph_residual(const double* u, const double* rho, double* r, const SGeom& S, const SphCoef& c,
                   double four_pi_G, bool zero_unknowns_in, double* partial, hipStream_t st);
 void sph_apply(const double* u, double* out, const SGeom& S, const SphCoef& c, hipStream_t st);
+// one SOR colour pass (colours 0..3: parity + 2 in the second half turn) with
+// relaxation factor omega[j] per colatitude, and one step of the Chebyshev
+// sequence omega <- 1 / (1 - rj^2 omega / 4)
+void sph_sor_pass(double* u, const double* rho, const SGeom& S, const SphCoef& c, double four_pi_G,
+                  const double* omega, int colour, hipStream_t st);
+void sph_omega_next(double* omega, const double* rj, int nth, hipStream_t st);
 // right-preconditioned BiCGSTAB: p = r + beta (p - omega v), phat = B^-1 p;
 // s = r - alpha v, shat = B^-1 s (B: red-black block lower triangle);
 // out = A xhat with dots (mode 0: w.out; mode 1: w.out and out.out);

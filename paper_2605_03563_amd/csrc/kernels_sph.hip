@@ -76,6 +76,32 @@ __global__ __launch_bounds__(256) void k_sph_apply(const double* __restrict__ U,
   out[S.at(i, j, k)] = sph_op(V, S, c, cot2, isin2, i, j, k);
 }
 
+// One colour of SOR (Section 2.1.1) on the log-spherical grid.  Colour =
+// parity of (i + j + k) plus 2 for phi in the second half turn, so no two
+// neighbours -- across a pole included -- share a colour; the grid covers the
+// colour's half turn only.  u += omega_j (u_GS - u), u_GS solving the node's
+// own row: u_GS - u = residual / diagonal.
+__global__ __launch_bounds__(256) void k_sph_sor(double* __restrict__ U, const double* __restrict__ rho, SGeom S,
+                                                 Coef c, const double* __restrict__ cot2,
+                                                 const double* __restrict__ isin2, const double* __restrict__ r2,
+                                                 double fpg, const double* __restrict__ omega, int colour) {
+  const int i = 1 + blockIdx.x * BX + threadIdx.x;
+  const int j = blockIdx.y * BY + threadIdx.y;
+  const int k = blockIdx.z + ((colour >> 1) ? (S.nph >> 1) : 0);
+  if (!active(S, i, j, k) || ((i + j + k) & 1) != (colour & 1)) return;
+  auto V = [&](int ii, int jj, int kk) -> double { return U[S.at(ii, jj, kk)]; };
+  const long long idx = S.at(i, j, k);
+  const double res = fpg * r2[i] * rho[idx] - sph_op(V, S, c, cot2, isin2, i, j, k);
+  const double d = -2.0 * c.ids2 - 2.0 * c.idt2 - 2.0 * isin2[j] * c.idp2;
+  U[idx] += omega[j] * res / d;
+}
+
+// next term of the relaxation sequence at every colatitude (Eq. omega_n)
+__global__ void k_sph_omega(double* __restrict__ omega, const double* __restrict__ rj, int nth) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < nth) omega[j] = 1.0 / (1.0 - rj[j] * rj[j] * omega[j] / 4.0);
+}
+
 // Right-preconditioned BiCGSTAB (Section 2.1.2: a multi-colour Gauss-Seidel
 // preconditioner B, the block lower triangle of A in red-black order, applied
 // by block substitution).  Red nodes (i + j + k even) solve with their
@@ -478,6 +504,16 @@ void sph_cast_in(const double* x, const SGeom& S, const SLev& L0, hipStream_t st
 }
 void sph_cast_out(const SLev& L0, double* x, const SGeom& S, hipStream_t st) {
   k_scast_out<<<sgrid(S), dim3(BX, BY), 0, st>>>(L0, x, S);
+}
+
+void sph_sor_pass(double* u, const double* rho, const SGeom& S, const SphCoef& c, double four_pi_G,
+                  const double* omega, int colour, hipStream_t st) {
+  const dim3 g((S.nr + BX - 1) / BX, (S.nth + BY - 1) / BY, S.nph / 2);
+  k_sph_sor<<<g, dim3(BX, BY), 0, st>>>(u, rho, S, make_coef(S), c.cot, c.isin2, c.r2, four_pi_G, omega, colour);
+}
+
+void sph_omega_next(double* omega, const double* rj, int nth, hipStream_t st) {
+  k_sph_omega<<<(nth + 255) / 256, 256, 0, st>>>(omega, rj, nth);
 }
 
 void sph_fill_zero(double* x, const SGeom& S, hipStream_t st) {

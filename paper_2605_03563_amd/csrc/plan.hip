@@ -137,8 +137,17 @@ int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
     return POISSON_EINVAL;
   }
   if (g->coord == POISSON_SPHERICAL_LOG) {
-    if (o->method != POISSON_BICGSTAB && o->method != POISSON_BICGSTAB_MG32) {
-      set_error("the log-spherical grid is solved by BiCGSTAB");
+    if (o->method != POISSON_BICGSTAB && o->method != POISSON_BICGSTAB_MG32 && o->method != POISSON_SOR) {
+      set_error("the log-spherical grid is solved by BiCGSTAB or SOR");
+      return POISSON_EINVAL;
+    }
+    if (o->method == POISSON_SOR && o->omega_mode != POISSON_OMEGA_OPT && o->omega_mode != POISSON_OMEGA_CHEBYSHEV &&
+        o->omega_mode != POISSON_OMEGA_FIXED) {
+      set_error("spherical SOR takes the local omega_opt, the local Chebyshev sequence or a fixed omega");
+      return POISSON_EINVAL;
+    }
+    if (o->method == POISSON_SOR && o->omega_mode == POISSON_OMEGA_FIXED && !(o->omega > 0.0 && o->omega < 2.0)) {
+      set_error("SOR needs 0 < omega < 2");
       return POISSON_EINVAL;
     }
     if (o->method == POISSON_BICGSTAB_MG32) {
@@ -290,6 +299,10 @@ void carve(poisson_plan_s* P, Carver& cv) {
     }
     P->ss = (double*)cv.take(vb);
     P->stt = (double*)cv.take(vb);
+    if (o.method == POISSON_SOR) {
+      P->somega = (double*)cv.take(sizeof(double) * g.n[1]);
+      P->srj = (double*)cv.take(sizeof(double) * g.n[1]);
+    }
     P->slv.clear();
     if (o.method == POISSON_BICGSTAB_MG32) {
       const double ds = log(g.hi[0] / g.lo[0]) / (g.n[0] - 1);
@@ -1068,6 +1081,72 @@ int solve_cart(poisson_plan_s* P, const double* rho, double* phi, double tol, po
 }
 
 // ------------------------------------------------------------ spherical solve
+// SOR on the log-spherical grid (Section 2.1.1): red half-sweep (colours 0,
+// 2), then black (1, 3); the relaxation factors are per colatitude -- the
+// local omega_opt of Eqs. omega_final and local_rjac, the local Chebyshev
+// sequence of Eq. omega_n from n = 1 advanced after every half-sweep, or a
+// fixed omega.
+// relaxation factors at the start of a solve
+int sph_sor_init(poisson_plan_s* P) {
+  const poisson_opts_t& o = P->opts;
+  const std::vector<double>& rj = P->srj_host;
+  std::vector<double> w(rj.size());
+  for (size_t j = 0; j < rj.size(); ++j) {
+    if (o.omega_mode == POISSON_OMEGA_FIXED)
+      w[j] = o.omega;
+    else if (o.omega_mode == POISSON_OMEGA_OPT)
+      w[j] = 2.0 / (1.0 + sqrt(1.0 - rj[j] * rj[j]));
+    else
+      w[j] = 1.0 / (1.0 - rj[j] * rj[j] / 2.0);
+  }
+  HIPCHK(hipMemcpyAsync(P->somega, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice, P->st));
+  HIPCHK(hipStreamSynchronize(P->st));
+  return POISSON_OK;
+}
+
+// one SOR sweep: red half (colours 0, 2), then black (1, 3)
+void sph_sor_sweep(poisson_plan_s* P, const double* rho, double* phi, hipStream_t st) {
+  const bool cheb = P->opts.omega_mode == POISSON_OMEGA_CHEBYSHEV;
+  for (int half = 0; half < 2; ++half) {
+    sph_sor_pass(phi, rho, P->S, P->sc, P->opts.four_pi_G, P->somega, half, st);
+    sph_sor_pass(phi, rho, P->S, P->sc, P->opts.four_pi_G, P->somega, half + 2, st);
+    if (cheb) sph_omega_next(P->somega, P->srj, P->S.nth, st);
+  }
+}
+
+int solve_sph_sor(poisson_plan_s* P, const double* rho, double* phi, double tol, Tracker& T, double rel) {
+  const poisson_opts_t& o = P->opts;
+  hipStream_t st = P->st;
+  const SGeom& S = P->S;
+  const int nb = sph_blocks(S);
+  CHK(sph_sor_init(P));
+  int it = 0;
+  bool conv = rel <= tol;
+  while (!conv && it < o.max_iter) {
+    sph_sor_sweep(P, rho, phi, st);
+    ++it;
+    if (it % o.check_every == 0 || it == o.max_iter) {
+      sph_residual(phi, rho, nullptr, S, P->sc, o.four_pi_G, false, P->partial, st);
+      finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
+      CHK(launch_check("spherical SOR"));
+      CHK(read_scalars(P, kRes2, 1));
+      rel = rel_of(P->host[0], T.bnorm);
+      T.push(rel);
+      if (!isfinite(rel)) {
+        set_error("SOR diverged (non-finite residual)");
+        return POISSON_ENUMERIC;
+      }
+      conv = rel <= tol;
+    }
+  }
+  HIPCHK(hipEventRecord(P->ev[2], st));
+  HIPCHK(hipEventSynchronize(P->ev[2]));
+  float t_mp = 0.f, t_it = 0.f;
+  HIPCHK(hipEventElapsedTime(&t_mp, P->ev[0], P->ev[1]));
+  HIPCHK(hipEventElapsedTime(&t_it, P->ev[1], P->ev[2]));
+  return finish_status(P, T, it, rel, conv, t_mp, t_it);
+}
+
 int solve_sph(poisson_plan_s* P, const double* rho, double* phi, double tol, poisson_stats_t* stats) {
   const poisson_opts_t& o = P->opts;
   hipStream_t st = P->st;
@@ -1104,6 +1183,7 @@ int solve_sph(poisson_plan_s* P, const double* rho, double* phi, double tol, poi
     HIPCHK(hipStreamSynchronize(st));
     return POISSON_OK;
   };
+  if (o.method == POISSON_SOR) return solve_sph_sor(P, rho, phi, tol, T, rel);
   if (!conv) {
     P->host[0] = P->host[1];
     CHK(restart());
@@ -1313,6 +1393,23 @@ int poisson_plan(poisson_plan_t* out, const poisson_grid_t* grid, const poisson_
             hipSuccess) {
       set_error("upload of spherical coefficients failed");
       return fail(POISSON_EHIP);
+    }
+    if (P->srj) {
+      // Eq. local_rjac in s = ln r: the weights ds^-2, dtheta^-2,
+      // (sin(theta) dphi)^-2 are the metric ones times r^2, so r cancels
+      std::vector<double> rj(S.nth);
+      for (int j = 0; j < S.nth; ++j) {
+        const double th = (j + 0.5) * S.dth;
+        const double wr = 1.0 / (S.ds * S.ds), wt = 1.0 / (S.dth * S.dth);
+        const double wp = 1.0 / (sin(th) * sin(th) * S.dph * S.dph);
+        rj[j] = (cos(M_PI / S.nr) * wr + cos(M_PI / S.nth) * wt + cos(M_PI / S.nph) * wp) / (wr + wt + wp);
+      }
+      if (hipMemcpyAsync(P->srj, rj.data(), sizeof(double) * S.nth, hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) {
+        set_error("upload of the local spectral radii failed");
+        return fail(POISSON_EHIP);
+      }
+      P->srj_host = rj;
     }
     for (size_t l = 0; l < P->slv.size(); ++l) {
       const SLev& L = P->slv[l];
@@ -1541,6 +1638,17 @@ int poisson_op_residual(poisson_plan_t P, const double* d_rho, const double* d_p
 
 int poisson_op_smooth(poisson_plan_t P, const double* d_rho, double* d_phi, int32_t sweeps, int32_t forward,
                       double omega) {
+  if (P && P->sph && P->opts.method == POISSON_SOR) {
+    // spherical SOR plans: `sweeps` sweeps with the plan's relaxation factors
+    // from the start of their sequence (forward and omega do not apply)
+    if (!d_rho || !d_phi || sweeps < 0) {
+      set_error("bad argument");
+      return POISSON_EINVAL;
+    }
+    CHK(sph_sor_init(P));
+    for (int s = 0; s < sweeps; ++s) sph_sor_sweep(P, d_rho, d_phi, P->st);
+    return launch_check("poisson_op_smooth");
+  }
   CHK(need_cart(P));
   if (!d_rho || !d_phi || sweeps < 0) {
     set_error("bad argument");

@@ -59,6 +59,9 @@ struct poisson_plan_s {
   psn::SphCoef sc{};
   double *sr = nullptr, *srh = nullptr, *sp[2] = {nullptr, nullptr}, *sv[2] = {nullptr, nullptr};
   double *ss = nullptr, *stt = nullptr;
+  double* somega = nullptr;            // SOR: relaxation factor per colatitude
+  double* srj = nullptr;               // SOR: local Jacobi spectral radius per colatitude
+  std::vector<double> srj_host;        // the same on the host
   std::vector<psn::SLev> slv;          // FP32 multigrid preconditioner levels (BICGSTAB_MG32)
   double* scinv = nullptr;             // dense inverse of its coarsest level
   int sncoarse = 0;

@@ -146,3 +146,14 @@ def test_coarse_tol_validation():
                                        C.byref(pg.options("mg_spai", coarse_tol=0.1, coarsest=16))) == 0
     s = pg.sph_grid(32, 16, 16)
     assert lib.poisson_workspace_bytes(C.byref(s), C.byref(pg.options("bicgstab", coarse_tol=0.1))) == 0
+
+
+def test_spherical_sor_options():
+    lib = L.load()
+    s = pg.sph_grid(32, 16, 16)
+    assert lib.poisson_workspace_bytes(C.byref(s), C.byref(pg.options("sor", omega_mode=pg.OMEGA_CHEBYSHEV))) > 0
+    assert lib.poisson_workspace_bytes(C.byref(s), C.byref(pg.options("sor", omega_mode=pg.OMEGA_OPT))) > 0
+    assert lib.poisson_workspace_bytes(C.byref(s), C.byref(pg.options("sor", omega_mode=pg.OMEGA_OPT_A))) == 0
+    assert lib.poisson_workspace_bytes(C.byref(s), C.byref(pg.options("sor", omega_mode=pg.OMEGA_FIXED,
+                                                                      omega=2.5))) == 0
+    assert lib.poisson_workspace_bytes(C.byref(s), C.byref(pg.options("cg"))) == 0

@@ -258,3 +258,55 @@ def test_c3_full_size_properties():
     assert q[2] == pytest.approx((inner.sum(axis=(1, 2)) * x).sum() * w, rel=1e-9, abs=1e-12 * mass)  # z dipole
     assert q[3] == pytest.approx((inner.sum(axis=(0, 1)) * x).sum() * w, rel=1e-9, abs=1e-12 * mass)  # x dipole
     del OS
+
+
+@pytest.mark.parametrize("mode", ["chebyshev", "opt"])
+def test_spherical_sor_sweeps_match_oracle(mode):
+    """Three SOR sweeps on a random 12 x 8 x 16 state with the local
+    relaxation factors (Eq. local_rjac; Eq. omega_n advanced per half-sweep,
+    or the local omega_opt) against the oracle's colour passes."""
+    from oracle import sph_sor as SS
+    say(f"spherical SOR sweeps ({mode})")
+    nr, nth, nph = 12, 8, 16
+    r, th, ph, ds = OM.sph_axes(nr, nth, nph)
+    rng = np.random.default_rng(21)
+    u = rng.standard_normal((nph, nth, nr + 2))
+    rho = rng.standard_normal((nph, nth, nr + 2))
+    om = pg.OMEGA_CHEBYSHEV if mode == "chebyshev" else pg.OMEGA_OPT
+    plan = pg.Plan(pg.sph_grid(nr, nth, nph), pg.options("sor", lmax=-1, omega_mode=om))
+    x = dev(u)
+    plan.smooth(dev(rho), x, sweeps=3)
+    rj = SS.local_rjac(nr, nth, nph, ds, th)
+    ref = u.copy()
+    w = SS.omega_first(rj) if mode == "chebyshev" else SS.omega_opt(rj)
+    for _ in range(3):
+        wr = w
+        if mode == "chebyshev":
+            w = SS.omega_next(w, rj)
+        wb = w
+        if mode == "chebyshev":
+            w = SS.omega_next(w, rj)
+        SS.sweep(ref, rho, r, ds, th, wr, wb)
+    got = host(x)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_spherical_sor_converges_to_the_oracle_solution():
+    """C4's SIS density on 32 x 16 x 16 with the multipole boundary: SOR with
+    the local Chebyshev sequence driven to 1e-12 equals the per-mode sparse
+    LU solution."""
+    say("spherical SOR converged")
+    nr, nth, nph = 32, 16, 16
+    wl = W.config_c4(nr=nr, nth=nth, nph=nph)
+    rho = wl.rho.numpy()
+    r, th, ph, ds = OM.sph_axes(nr, nth, nph)
+    mc = 4 * math.pi * 1e-3
+    plan = pg.Plan(pg.sph_grid(nr, nth, nph), pg.options("sor", lmax=8, point_mass=mc, max_iter=50000,
+                                                         omega_mode=pg.OMEGA_CHEBYSHEV, check_every=10))
+    phi = torch.zeros(rho.shape, dtype=torch.float64, device="cuda:0")
+    res = plan.solve(dev(rho), phi, tol=1e-12)
+    say(f"  {res.iterations} sweeps")
+    assert res.converged, res
+    ghost, _, _ = OM.sph_boundary(rho, nr, nth, nph, 8, point_mass=mc)
+    ref = OD.solve_sph(ghost, rho, r, ds, th)
+    assert rel_l2(host(phi)[:, :, 1:nr + 1], ref[:, :, 1:nr + 1]) < CONV_TOL
