@@ -24,6 +24,8 @@ import statistics
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -133,6 +135,7 @@ def c3(args):
         "err_vs_converged_fp64_mixed": err32, "err_vs_converged_fp64_fp64mg": err64,
         "converged_reference_rel_residual": rref.rel_residual,
         "t_multipole_ms": r32.t_multipole_ms,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_c3(args.cpu_budget_s),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
                      "kernel": "k_pass19w<float> (fine-level four-colour GS pass)",
@@ -192,6 +195,7 @@ def c4(args):
                               "ms_per_iteration": gs_it_ms,
                               "iteration_GBps_algorithmic": bytes_per_it / (gs_it_ms * 1e-3) / 1e9},
         "speedup_mg_vs_gs": sgs / sec,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_c4(rho.cpu().numpy(), g, args.cpu_budget_s),
         "sor_local_chebyshev": {"time_ms": ssor * 1e3, "converged": rsor.converged, "sweeps": rsor.iterations,
                                 "rel_residual": rsor.rel_residual,
                                 "ms_per_sweep": rsor.t_iter_ms / max(1, rsor.iterations)},
@@ -273,6 +277,7 @@ def spai(args):
         "data": "synthetic",
         "config": {"workload": "spai_mg_512^3_order2_V33_fp32coarse_lmax8", "unknowns": unknowns},
         "time_to_1e-8_ms": sec * 1e3, "cycles": row["cycles"], "rows": rows, "coarse_rows": coarse_rows,
+        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_spai(args.cpu_budget_s),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
                      "kernel": "k_nspai<double> (fused fine-level SPAI step)",
@@ -434,6 +439,70 @@ def cpu_baseline(rho_host, n, budget_s, with_multipole):
         sample += f"; oracle multipole boundary (lmax 8) took {t_mp:.1f} s (not in value)"
     return {"value": unknowns * cycles / el / 1e9, "unit": "Gcell-updates/s", "cores": 1,
             "kind": "oracle", "sample": sample}
+
+
+def _cpu_repeat(fn, budget_s):
+    """Run fn() single-threaded until budget_s has elapsed (at least once);
+    returns (calls, seconds)."""
+    from threadpoolctl import threadpool_limits
+    calls = 0
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        while True:
+            fn()
+            calls += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s:
+                break
+    return calls, el
+
+
+def cpu_baseline_c3(budget_s):
+    """Oracle 19-point V(2,2) cycles on the same workload recipe at 128^3
+    (64 clumps + turbulent floor), single thread."""
+    from oracle import smoothers as OS
+    import workloads as W
+    n, g = 128, 3
+    wl = W.config_c3(n=n, g=g)
+    rho = wl.rho.numpy()
+    u = np.zeros_like(rho)
+    cache = {}
+    calls, el = _cpu_repeat(lambda: OS.vcycle(u, rho, n, 1.0 / n, 6, g, _cache=cache), budget_s)
+    return {"value": (n - 1) ** 3 * calls / el / 1e9, "unit": "Gcell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{calls} oracle 19-point V(2,2) cycle(s) (FP64 NumPy) on the same recipe at 128^3 "
+                      f"(127^3 unknowns), single thread, {el:.1f} s"}
+
+
+def cpu_baseline_c4(rho_host, g, budget_s):
+    """Oracle r^2-scaled spherical operator (residual) applications on the
+    full C4 input, single thread."""
+    from oracle import multipole as OM
+    from oracle import operators as OO
+    r, th, ph, ds = OM.sph_axes(g.nr, g.nth, g.nph)
+    u = np.zeros_like(rho_host)
+    calls, el = _cpu_repeat(lambda: OO.sph_residual(u, rho_host, r, ds, th), budget_s)
+    return {"value": g.unknowns * calls / el / 1e9, "unit": "Gcell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{calls} oracle residual evaluation(s) of the r^2-scaled spherical operator on the full "
+                      f"{g.nr}x{g.nth}x{g.nph} input, single thread, {el:.1f} s (the oracle solves C4 directly; "
+                      f"this is its per-sweep building block)"}
+
+
+def cpu_baseline_spai(budget_s):
+    """Oracle SPAI V(3,3) cycles (order 2, Galerkin levels) on the same
+    recipe at 128^3, single thread."""
+    from oracle import spai as SP
+    import workloads as W
+    n = 128
+    wl = W.config_c3(n=n, g=1)
+    rho = wl.rho.numpy()
+    ops = SP.level_operators(2, n, 4)
+    f = SP.rhs_compact(rho, n, 2)
+    u = np.zeros_like(rho)
+    cache = {}
+    calls, el = _cpu_repeat(lambda: SP.vcycle(u, f, n, ops, SP.TABLE1[2], 3, 3, _cache=cache), budget_s)
+    return {"value": (n - 1) ** 3 * calls / el / 1e9, "unit": "Gcell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{calls} oracle SPAI V(3,3) cycle(s) (order 2, Galerkin coarse levels to 4 intervals) on "
+                      f"the same recipe at 128^3, single thread, {el:.1f} s"}
 
 
 def main():
