@@ -310,3 +310,56 @@ def test_spherical_sor_converges_to_the_oracle_solution():
     ghost, _, _ = OM.sph_boundary(rho, nr, nth, nph, 8, point_mass=mc)
     ref = OD.solve_sph(ghost, rho, r, ds, th)
     assert rel_l2(host(phi)[:, :, 1:nr + 1], ref[:, :, 1:nr + 1]) < CONV_TOL
+
+
+CART_METHODS = [("sor", {}), ("cg", {}), ("mg", {}), ("mg_ir32", {}), ("mg_spai", {"order": 2}),
+                ("mg_spai", {"order": 4}), ("mg_spai32", {"order": 2}), ("mg_spai", {"order": 2, "coarse_tol": 0.1})]
+
+
+@pytest.mark.parametrize("method,kw", CART_METHODS)
+def test_degenerate_cartesian_inputs(method, kw):
+    """Zero density with the multipole boundary: converged at once, Phi stays
+    zero.  Zero density with linear ghost values: the discrete solution is
+    that linear function (every operator here is exact on it)."""
+    say(f"degenerate inputs {method} {kw}")
+    n = 32
+    kw = dict(kw)
+    order = kw.pop("order", 2)
+    plan = pg.Plan(pg.cart_grid(n), pg.options(method, order=order, lmax=8, max_iter=20000, **kw))
+    rho = torch.zeros((n + 1,) * 3, dtype=torch.float64, device="cuda:0")
+    phi = torch.zeros_like(rho)
+    res = plan.solve(rho, phi, tol=1e-10)
+    assert res.converged and res.iterations == 0
+    assert float(phi.abs().max()) == 0.0
+    plan2 = pg.Plan(pg.cart_grid(n), pg.options(method, order=order, lmax=-1, max_iter=20000, **kw))
+    x = np.arange(n + 1) / n
+    z, y, xx = np.meshgrid(x, x, x, indexing="ij")
+    lin = 1.0 + 2.0 * xx - 0.5 * y + 0.25 * z
+    start = lin.copy()
+    start[1:n, 1:n, 1:n] = 0.0
+    phi2 = dev(start)
+    res2 = plan2.solve(rho, phi2, tol=1e-12)
+    assert res2.converged, res2
+    assert np.max(np.abs(host(phi2) - lin)) < 1e-9 * np.max(np.abs(lin))
+
+
+@pytest.mark.parametrize("method", ["bicgstab", "bicgstab_mg32", "sor"])
+def test_degenerate_spherical_inputs(method):
+    """Zero density, no point mass: converged at once with Phi zero; zero
+    density with constant radial ghosts: the solution is that constant."""
+    say(f"degenerate spherical inputs {method}")
+    nr, nth, nph = 16, 8, 16
+    extra = {"omega_mode": pg.OMEGA_CHEBYSHEV} if method == "sor" else {}
+    plan = pg.Plan(pg.sph_grid(nr, nth, nph), pg.options(method, lmax=8, max_iter=20000, **extra))
+    rho = torch.zeros((nph, nth, nr + 2), dtype=torch.float64, device="cuda:0")
+    phi = torch.zeros_like(rho)
+    res = plan.solve(rho, phi, tol=1e-10)
+    assert res.converged and res.iterations == 0
+    assert float(phi.abs().max()) == 0.0
+    plan2 = pg.Plan(pg.sph_grid(nr, nth, nph), pg.options(method, lmax=-1, max_iter=20000, **extra))
+    phi2 = torch.zeros_like(rho)
+    phi2[:, :, 0] = -3.0
+    phi2[:, :, -1] = -3.0
+    res2 = plan2.solve(rho, phi2, tol=1e-12)
+    assert res2.converged, res2
+    assert float((phi2 + 3.0).abs().max()) < 1e-9
