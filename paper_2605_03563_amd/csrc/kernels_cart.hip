@@ -537,6 +537,72 @@ __global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ Ec, G
   }
 }
 
+// Four-colour (19-point hierarchy) prolongation: a thread owns the four fine
+// nodes 4m + q of compact column m in row b and marches fine planes; the
+// coarse values it needs on a coarse plane (interpolated along x, and along
+// y when the fine row is odd) are formed once per coarse plane and kept for
+// the two or three fine planes that use them.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong4(const T* __restrict__ Ec, Geom Gc, T* __restrict__ Xf, Geom Gf) {
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int m = Gf.mlo() + bx * BX + (int)threadIdx.x;
+  const int b = Gf.g + by * BY + (int)threadIdx.y;
+  const int last = Gf.g + Gf.n - 2;
+  if (m > Gf.mhi() || b > last) return;
+  const int sh = Gf.g - 1;
+  const int kz = planes_per_block(Gf);
+  const int k0 = Gf.g + bz * kz;
+  const int k1 = min(k0 + kz - 1, last);
+  const int j = b - sh;
+  const int J = (j >> 1) + sh, oj = j & 1;
+  const T half = (T)0.5;
+  bool in[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) in[q] = Gf.inner(4 * m + q);
+  auto plane_vals = [&](int L, T* v) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = (T)0;
+    for (int db = 0; db <= oj; ++db) {
+      const int Bc = J + db;
+      const int sc = Bc + L + Gc.off;
+      const long long crow = Gc.row(Bc, L);
+      const T wy = oj ? half : (T)1;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!in[q]) continue;
+        const int i = 4 * m + q - sh;
+        const int I = (i >> 1) + sh;
+        T t = Ec[(long long)((I + sc) & 3) * Gc.cs + crow + (I >> 2)];
+        if (i & 1) t = half * (t + Ec[(long long)((I + 1 + sc) & 3) * Gc.cs + crow + ((I + 1) >> 2)]);
+        v[q] += wy * t;
+      }
+    }
+  };
+  int Lc = ((k0 - sh) >> 1) + sh;
+  T cv[4], nv[4];
+  plane_vals(Lc, cv);
+  plane_vals(Lc + 1, nv);
+  for (int k = k0; k <= k1; ++k) {
+    const int l = k - sh;
+    const int L = (l >> 1) + sh;
+    if (L != Lc) {  // one coarse plane further
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cv[q] = nv[q];
+      Lc = L;
+      plane_vals(L + 1, nv);
+    }
+    const int s = (b + k + Gf.off) & 3;
+    const long long row = Gf.row(b, k);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (!in[q]) continue;
+      const T e = (l & 1) ? half * (cv[q] + nv[q]) : cv[q];
+      Xf[(long long)((q + s) & 3) * Gf.cs + row + m] += e;
+    }
+  }
+}
+
 // Two-colour (7-point hierarchy, one ghost layer) prolongation: the fine
 // nodes 2m and 2m+1 of a row need the coarse values at coarse columns m and
 // m+1 of one or two coarse rows on one or two coarse planes; the coarse plane
@@ -975,6 +1041,13 @@ void prolong_add(const void* e_coarse, const Geom& Gc, void* phi_fine, const Geo
       k_prolong2<float><<<grid, blk, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
     else
       k_prolong2<double><<<grid, blk, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
+    return;
+  }
+  if (Gf.C == 4) {
+    if (f32)
+      k_prolong4<float><<<grid, blk, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
+    else
+      k_prolong4<double><<<grid, blk, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
     return;
   }
   if (f32)
