@@ -164,7 +164,7 @@ def c4(args):
     runs = {}
     for m in ("bicgstab_mg32", "bicgstab"):
         plan = pg.Plan(grid, pg.options(m, lmax=8, point_mass=4 * math.pi * g.r_min, max_iter=20000,
-                                        check_every=10 if m == "bicgstab" else 2), device=dev)
+                                        check_every=10 if m == "bicgstab" else 1), device=dev)
         phi = torch.zeros_like(rho)
         steps = max(1, args.steps // 2) if m == "bicgstab" else args.steps
         sec, res = _time_solves(plan, rho, phi, args.tol, steps, 1)
