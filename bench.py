@@ -56,7 +56,7 @@ def parse():
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--load", type=float, default=0.7, help="offered load relative to saturation")
-    ap.add_argument("--slots", type=int, default=4, help="concurrent request slots of the full configuration")
+    ap.add_argument("--slots", type=int, default=8, help="concurrent request slots of the full configuration")
     return ap.parse_args()
 
 
