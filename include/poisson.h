@@ -231,6 +231,14 @@ int poisson_op_vcycle(poisson_plan_t plan, const double* d_rho, double* d_phi, i
    started) on theirs; other Cartesian plans sweep the FP64 potential. */
 int poisson_op_sweep_resident(poisson_plan_t plan, int32_t sweeps);
 
+/* POISSON_BICGSTAB_MG32 plans: d_yhat = M^-1 d_y, M^-1 being one FP32
+   V(nu1, nu2) cycle of the spherical multigrid preconditioner from a zero
+   guess (the right preconditioner of the BiCGSTAB iteration, Sections
+   2.1.2-2.1.3).  Both arrays in the plan's spherical layout (FP64); the
+   unknowns of d_y are read, the unknowns of d_yhat written, radial ghosts of
+   either are not accessed.  POISSON_EINVAL for other plans. */
+int poisson_op_precond(poisson_plan_t plan, const double* d_y, double* d_yhat);
+
 /* ---- serving loop: continuous batching of independent solves -----------
    A persistent worker thread advances every admitted request by one
    multigrid iteration at a time on its own stream slot, so requests of

@@ -209,6 +209,11 @@ class Plan:
         _check(self.lib.poisson_op_prolong_add(self.handle, _ptr(coarse, self._dense_elems(1)),
                                                _ptr(fine, self._dense_elems(0))), "poisson_op_prolong_add")
 
+    def precond(self, y, yhat):
+        """yhat = M^-1 y, one FP32 multigrid cycle of a bicgstab_mg32 plan."""
+        ne = self.node_elems
+        _check(self.lib.poisson_op_precond(self.handle, _ptr(y, ne), _ptr(yhat, ne)), "poisson_op_precond")
+
     def vcycle(self, rho, phi, cycles=1):
         ne = self.node_elems
         _check(self.lib.poisson_op_vcycle(self.handle, _ptr(rho, ne), _ptr(phi, ne), cycles), "poisson_op_vcycle")

@@ -58,6 +58,7 @@ SIGNATURES = {
     "poisson_op_prolong_add": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "poisson_op_vcycle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "poisson_op_sweep_resident": (C.c_int, [C.c_void_p, C.c_int32]),
+    "poisson_op_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "poisson_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_size_t, C.c_int32, C.c_int32, C.c_int32,
                                         C.c_int32, C.c_double, C.c_int32, C.c_int32]),
     "poisson_server_submit": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,

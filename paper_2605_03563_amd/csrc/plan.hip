@@ -1736,6 +1736,19 @@ int poisson_op_vcycle(poisson_plan_t P, const double* d_rho, double* d_phi, int3
   return launch_check("poisson_op_vcycle");
 }
 
+int poisson_op_precond(poisson_plan_t P, const double* d_y, double* d_yhat) {
+  if (!P || !d_y || !d_yhat) {
+    set_error("null argument");
+    return POISSON_EINVAL;
+  }
+  if (!P->sph || P->slv.empty()) {
+    set_error("poisson_op_precond needs a POISSON_BICGSTAB_MG32 plan");
+    return POISSON_EINVAL;
+  }
+  sph_precond(P, d_y, d_yhat, P->st);
+  return launch_check("poisson_op_precond");
+}
+
 int poisson_op_sweep_resident(poisson_plan_t P, int32_t sweeps) {
   CHK(need_cart(P));
   if (sweeps < 0) {

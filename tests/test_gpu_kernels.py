@@ -11,7 +11,7 @@ import paper_2605_03563_amd as pg
 from oracle import multipole as OM
 from oracle import operators as OO
 from oracle import smoothers as OS
-from tests.gpu_util import dev, host, random_cart, rel_max, say
+from tests.gpu_util import dev, host, random_cart, rel_l2, rel_max, say
 from workloads import CartGrid, draw_clumps, clump_density, uniform_sphere
 
 pytestmark = pytest.mark.gpu
@@ -161,3 +161,24 @@ def test_spherical_apply():
     out = torch.zeros(u.shape, dtype=torch.float64, device="cuda:0")
     plan.apply(dev(u), out)
     assert rel_max(host(out)[:, :, 1:nr + 1], OO.sph_apply(u, ds, th)) < KTOL
+
+
+@pytest.mark.parametrize("dims", [(32, 16, 32), (20, 8, 48)])
+def test_spherical_preconditioner_cycle_matches_oracle(dims):
+    """One FP32 V(2,2) cycle of the spherical multigrid preconditioner against
+    the oracle's FP64 cycle on a random right-hand side (48 = 3 x 16: phi
+    lines of three segments on the fine level; 20 x 8 x 48 coarsens twice)."""
+    from oracle import sph_mg as SM
+    nr, nth, nph = dims
+    say(f"spherical preconditioner cycle {dims}")
+    r, th, ph, ds = OM.sph_axes(nr, nth, nph)
+    plan = pg.Plan(pg.sph_grid(nr, nth, nph), pg.options("bicgstab_mg32", lmax=-1))
+    rng = np.random.default_rng(sum(dims))
+    y = np.zeros((nph, nth, nr + 2))
+    y[:, :, 1:nr + 1] = rng.standard_normal((nph, nth, nr))
+    yhat = torch.zeros(y.shape, dtype=torch.float64, device="cuda:0")
+    plan.precond(dev(y), yhat)
+    ref = SM.vcycle(y[:, :, 1:nr + 1], ds)
+    got = host(yhat)[:, :, 1:nr + 1]
+    say(f"  rel L2 {rel_l2(got, ref):.2e}")
+    assert rel_l2(got, ref) < 1e-5   # FP32 cycle against the FP64 oracle
