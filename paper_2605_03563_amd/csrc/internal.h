@@ -200,7 +200,10 @@ void pbicg_xr(double* x, double* r, const double* phat, const double* shat, cons
 // neighbours in r and theta -- the other colour -- held fixed; across a pole
 // a line meets itself half a turn away, and that coupling is taken from the
 // values before the pass.
-void sph_line_pass(const SLev& L, int colour, hipStream_t st);
+// zero_guess (first sweep of a cycle from a zero guess, so u needs no
+// clearing): 1 = u is taken as zero (first colour), 2 = the pass's own lines
+// are taken as zero (second colour: only its cross-pole term reads them)
+void sph_line_pass(const SLev& L, int colour, int zero_guess, hipStream_t st);
 void sph_residual32(const SLev& L, hipStream_t st);
 void sph_restrict32(const SLev& Lf, const SLev& Lc, hipStream_t st);
 void sph_prolong_add32(const SLev& Lc, const SLev& Lf, hipStream_t st);

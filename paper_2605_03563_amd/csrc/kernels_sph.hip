@@ -285,7 +285,7 @@ __device__ inline float slev_diag(const SLev& L, int j) {
 // meet in the interface system X = G E (X: line values at segment ends,
 // E: the y values there), and each segment then adds the end loads:
 // x = y - a (x_left v + x_right w).  Y lives in LDS as [seg][thread].
-__global__ __launch_bounds__(1024) void k_sline(SLev L, int colour) {
+__global__ __launch_bounds__(1024) void k_sline(SLev L, int colour, int zero_guess) {
   extern __shared__ float lds[];
   const int nt = blockDim.x;
   const int t = threadIdx.x;
@@ -313,9 +313,15 @@ __global__ __launch_bounds__(1024) void k_sline(SLev L, int colour) {
     for (int q = 0; q < SL; ++q) {
       const int k = k0 + q;
       const long long idx = L.at(a, j, k);
-      const float up = (j + 1 < L.nth) ? L.u[idx + L.p0] : L.u[L.at(a, j, (k + half) % L.nph)];
-      const float um = (j > 0) ? L.u[idx - L.p0] : L.u[L.at(a, j, (k + half) % L.nph)];
-      const float rhs = L.f[idx] - (cr * L.u[idx + 1] + cl * L.u[idx - 1] + cjp * up + cjm * um);
+      // zero_guess 1: u is zero everywhere; 2: this colour's lines are still
+      // zero (the cross-pole term, which reads the line itself, is zero)
+      float rhs = L.f[idx];
+      if (zero_guess != 1) {
+        const float pole = (zero_guess == 2) ? 0.0f : L.u[L.at(a, j, (k + half) % L.nph)];
+        const float up = (j + 1 < L.nth) ? L.u[idx + L.p0] : pole;
+        const float um = (j > 0) ? L.u[idx - L.p0] : pole;
+        rhs -= cr * L.u[idx + 1] + cl * L.u[idx - 1] + cjp * up + cjm * um;
+      }
       d = (rhs - aphi * d) * m[q];
       Y[(size_t)q * nt + t] = d;
     }
@@ -482,11 +488,11 @@ void bicg_scalars(const double* partial, int nb, Scalars* scal, int stage, hipSt
   k_bicg_scalars<<<1, kFinishThreads, 0, st>>>(partial, nb, scal, stage);
 }
 
-void sph_line_pass(const SLev& L, int colour, hipStream_t st) {
+void sph_line_pass(const SLev& L, int colour, int zero_guess, hipStream_t st) {
   const int nt = L.nl * L.nseg;
   const size_t lds = sizeof(float) * ((size_t)L.seg * nt + (size_t)2 * L.nseg * L.nl);
   const int lines = (L.nr + 1) / 2;
-  k_sline<<<dim3((lines + L.nl - 1) / L.nl, L.nth), nt, lds, st>>>(L, colour);
+  k_sline<<<dim3((lines + L.nl - 1) / L.nl, L.nth), nt, lds, st>>>(L, colour, zero_guess);
 }
 void sph_residual32(const SLev& L, hipStream_t st) { k_sres32<<<lgrid(L), dim3(BX, BY), 0, st>>>(L); }
 void sph_restrict32(const SLev& Lf, const SLev& Lc, hipStream_t st) {

@@ -683,15 +683,18 @@ void svcycle(poisson_plan_s* P, int l, hipStream_t st) {
     sph_coarse32(P->scinv, L, st);
     return;
   }
-  fill_zero(L.u, true, L.count(), st);
+  // zero guess: the first colour-0 pass sees u = 0 and writes every colour-0
+  // line; the colour-1 pass then reads colour-0 values and, across a pole,
+  // its own (still zero) lines; radial ghosts stay zero from plan creation,
+  // so u needs no clearing
   for (int s = 0; s < P->opts.nu1; ++s)
-    for (int c = 0; c < 2; ++c) sph_line_pass(L, c, st);
+    for (int c = 0; c < 2; ++c) sph_line_pass(L, c, s == 0 ? (c == 0 ? 1 : 2) : 0, st);
   sph_residual32(L, st);
   sph_restrict32(L, P->slv[l + 1], st);
   svcycle(P, l + 1, st);
   sph_prolong_add32(P->slv[l + 1], L, st);
   for (int s = 0; s < P->opts.nu2; ++s)
-    for (int c = 1; c >= 0; --c) sph_line_pass(L, c, st);
+    for (int c = 1; c >= 0; --c) sph_line_pass(L, c, 0, st);
 }
 
 // yhat = M^-1 y with M^-1 one FP32 V-cycle (inputs / outputs FP64)
