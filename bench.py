@@ -50,7 +50,7 @@ def parse():
                          "--sweeps resident smoother sweeps and one 1 GiB reference copy; "
                          "prints no bench line")
     ap.add_argument("--sweeps", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "serving", "spai"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "serving", "spai"],
                     help="c2: the 255^3 FP64 multigrid solve (default bench line); serving: the "
                          "continuous-batching request stream (its own JSON line)")
     ap.add_argument("--requests", type=int, default=2000)
@@ -83,6 +83,55 @@ def _time_solves(plan, rho, phi, tol, steps, warmup):
             raise RuntimeError(f"solve did not converge: {res}")
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) / steps, res
+
+
+def bench_c1(args):
+    """32^3 cells, uniform sphere of radius 0.25 (rho = 1), multipole
+    boundary with lmax 4, red-black SOR at omega_opt (and with the Chebyshev
+    sequence) and CG to 1e-10; errors against the analytic potential and the
+    oracle's exact discrete solution."""
+    import torch
+
+    import paper_2605_03563_amd as pg
+    import workloads as W
+    from oracle import analytic as OA
+    from oracle import direct as OD
+    from oracle import multipole as OM
+
+    dev = "cuda:0"
+    n, lmax, tol = 32, 4, 1e-10
+    wl = W.config_c1(n=n, device=dev)
+    rho = wl.rho.contiguous()
+    rho_h = rho.cpu().numpy()
+    ghost, _ = OM.cart_boundary(rho_h, n, 1, lmax)
+    exact = OD.solve_cart(ghost, rho_h, n, 1.0 / n, 2, 1)
+    x = OM.cart_coords(n, 1)[1:n]
+    zz, yy, xx = np.meshgrid(x, x, x, indexing="ij")
+    ana = OA.uniform_sphere(np.stack([xx, yy, zz], -1), (0.5, 0.5, 0.5), 0.25)
+    s = slice(1, n)
+    rows = []
+    for name, method, kw in (("sor_omega_opt", "sor", {}), ("sor_chebyshev", "sor", {"omega_mode": pg.OMEGA_CHEBYSHEV}),
+                             ("cg", "cg", {})):
+        plan = pg.Plan(pg.cart_grid(n), pg.options(method, lmax=lmax, max_iter=100000, **kw), device=dev)
+        phi = torch.zeros_like(rho)
+        sec, res = _time_solves(plan, rho, phi, tol, args.steps, args.warmup)
+        got = phi.cpu().numpy()
+        rows.append({"solver": name, "iterations": res.iterations, "time_to_1e-10_ms": sec * 1e3,
+                     "gzups_per_iteration": (n - 1) ** 3 * res.iterations / (res.t_iter_ms * 1e-3) / 1e9,
+                     "err_vs_oracle_rel_l2": float(np.linalg.norm(got[s, s, s] - exact[s, s, s]) /
+                                                   np.linalg.norm(exact[s, s, s])),
+                     "err_vs_analytic_rel_l2": float(np.linalg.norm(got[s, s, s] - ana) / np.linalg.norm(ana))})
+        del plan
+    cg = rows[-1]
+    out = {
+        "metric": "Gcell-updates/s", "value": (n - 1) ** 3 * cg["iterations"] / (cg["time_to_1e-10_ms"] * 1e-3) / 1e9,
+        "unit": "Gcell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": cg["time_to_1e-10_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "c1_uniform_sphere_32^3_lmax4_cg_and_sor_tol1e-10", "unknowns": (n - 1) ** 3},
+        "rows": rows,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def c3(args):
@@ -517,7 +566,7 @@ def main():
         kernels_only(args)
         return
     if args.workload != "c2":
-        {"serving": serving, "c3": c3, "c4": c4, "spai": spai}[args.workload](args)
+        {"serving": serving, "c1": bench_c1, "c3": c3, "c4": c4, "spai": spai}[args.workload](args)
         return
 
     import torch
