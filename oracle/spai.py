@@ -16,10 +16,17 @@ Compact discretisations (weights times 1/h^2, right-hand side operator B):
   order 2: 7-point  (-6, 1, 0, 0),           B f = f;
   order 4: 19-point (-24, 2, 1, 0) / 6,      B f = (6 f_n + sum of 6 faces) / 12
            (the Mehrstellen scheme; L u = B (lap u) is exact for
-           polynomials of degree <= 5).
-The sixth-order 27-point stencil needs a right-hand side the paper does not
-give; it appears here only in the Fourier analysis (parity unpinned beyond
-that, see the Table 1 reading in the tests).
+           polynomials of degree <= 5);
+  order 6: 27-point (-128, 14, 3, 1) / 30 (the isotropic compact sixth-order
+           scheme the paper cites for Section 2.1.3).  Its truncation error
+           for lap u = f is (h^2/12) lap f + (h^4/360) (sum_d f_dddd +
+           4 sum_{d<e} f_ddee) + O(h^6), so B adds exactly that:
+           B f = f + (1/12) sum_d D_d f - (1/240) sum_d D_d D_d f
+                   + (1/90) sum_{d<e} D_d D_e f,
+           D_d the unit-spacing second difference along axis d.  The paper
+           does not give its right-hand side; this one reads f two nodes
+           beyond the unknowns (the density's second ghost layer) and makes
+           L u = B (lap u) exact for polynomials of degree <= 7.
 
 M(alpha, beta, gamma, delta) = h^2 * stencil (alpha, beta, gamma, delta)
 (Eq. Smoother); every level uses its own spacing h_l and the same
@@ -51,6 +58,17 @@ WEIGHTS = {
     6: (-128.0 / 30.0, 14.0 / 30.0, 3.0 / 30.0, 1.0 / 30.0),
 }
 
+# Smoother coefficients (omega, alpha, beta, gamma, delta) used by the
+# method.  Orders 2 and 4: Table 1 as printed.  Order 6: the printed delta
+# cell repeats mu and makes the smoother diverge; delta = 0.0151 is the value
+# that minimises the smoothing factor with the other four printed
+# coefficients kept (mu = 0.0912 against the printed 0.0909).
+COEFFS = {
+    2: TABLE1[2][:5],
+    4: TABLE1[4][:5],
+    6: TABLE1[6][:4] + (0.0151,),
+}
+
 OFFSETS = [d for d in itertools.product((-1, 0, 1), repeat=3)]
 
 
@@ -80,12 +98,38 @@ def embed(x_int: np.ndarray) -> np.ndarray:
 
 
 def rhs_compact(f_nodes: np.ndarray, n: int, order: int) -> np.ndarray:
-    """B f at the unknown nodes (f includes the boundary nodes)."""
+    """B f at the unknown nodes.  Orders 2 and 4: f_nodes holds nodes 0..n
+    (shape (n+1)^3); order 6: nodes -1..n+1 (shape (n+3)^3)."""
     if order == 2:
         return f_nodes[1:n, 1:n, 1:n].copy()
     if order == 4:
         return apply27(f_nodes, n, (6.0 / 12.0, 1.0 / 12.0, 0.0, 0.0))
-    raise ValueError("right-hand side operator given for orders 2 and 4 only")
+    if order != 6:
+        raise ValueError("compact orders are 2, 4 and 6")
+    if f_nodes.shape != (n + 3,) * 3:
+        raise ValueError("order 6 needs f on nodes -1..n+1")
+
+    def sh(dk, dj, di):
+        # f shifted by (dk, dj, di) nodes, at the unknowns 1..n-1
+        return f_nodes[2 + dk:n + 1 + dk, 2 + dj:n + 1 + dj, 2 + di:n + 1 + di]
+
+    axes = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+
+    def along(e, s):
+        return sh(e[0] * s, e[1] * s, e[2] * s)
+
+    f0 = sh(0, 0, 0)
+    d2 = [along(e, 1) - 2.0 * f0 + along(e, -1) for e in axes]
+    d4 = [along(e, 2) - 4.0 * along(e, 1) + 6.0 * f0 - 4.0 * along(e, -1) + along(e, -2) for e in axes]
+    mixed = 0.0
+    for a in range(3):
+        for b in range(a + 1, 3):
+            ea, eb = axes[a], axes[b]
+            corners = sum(sh(sa * ea[0] + sb * eb[0], sa * ea[1] + sb * eb[1], sa * ea[2] + sb * eb[2])
+                          for sa in (-1, 1) for sb in (-1, 1))
+            # D_a D_b f: the 3 x 3 tensor product of (1, -2, 1) in the (a, b) plane
+            mixed = mixed + corners - 2.0 * (along(ea, 1) + along(ea, -1) + along(eb, 1) + along(eb, -1)) + 4.0 * f0
+    return f0 + sum(d2) / 12.0 - sum(d4) / 240.0 + mixed / 90.0
 
 
 def symbol(w, kx, ky, kz):
@@ -255,7 +299,8 @@ def dst_solve(w_abs, rhs: np.ndarray, n: int) -> np.ndarray:
 
 def solve_cart(phi_ghost, f_nodes, n, order):
     """Exact discrete solution of L u = B f with the ghost values of
-    phi_ghost (one layer) and f = 4 pi G rho at every node."""
+    phi_ghost (one layer) and f = 4 pi G rho at every node (order 6: one
+    more layer of f, see rhs_compact)."""
     h = 1.0 / n
     w = tuple(x / (h * h) for x in WEIGHTS[order])
     z = phi_ghost.copy()
