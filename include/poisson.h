@@ -75,9 +75,14 @@ extern "C" {
 #define POISSON_MG_SPAI        6  /* Cartesian FP64 V(nu1, nu2) cycles with the SPAI Richardson
                                      smoother of Table 1 (Eqs. richardson, Smoother), Galerkin
                                      coarse operators R A P and compact radius-1 stencils:
-                                     order 2 (7-point) or 4 (19-point Mehrstellen, right-hand
-                                     side (6 f + face sum) / 12); coarsest level solved by a
-                                     dense inverse (Section 2.1.3) */
+                                     order 2 (7-point), 4 (19-point Mehrstellen, right-hand
+                                     side (6 f + face sum) / 12) or 6 (27-point
+                                     (-128, 14, 3, 1)/30h^2, right-hand side
+                                     (402 f + 40 faces - 3 axis nodes at distance 2 + 8 in-plane
+                                     diagonals) / 720, which reads rho's second ghost layer:
+                                     grid.ghost = 2; Table 1's order-6 delta taken as 0.0151);
+                                     coarsest level solved by a dense inverse, or by CG with
+                                     opts.coarse_tol (Section 2.1.3) */
 #define POISSON_MG_SPAI32      7  /* POISSON_MG_SPAI with every level below the finest stored in
                                      FP32 and all arithmetic in FP64 (the paper's mixed
                                      precision, Section 2.1.3) */
@@ -95,7 +100,8 @@ typedef struct {
                            spherical: nr, ntheta, nphi unknowns (ntheta, nphi even) */
     double  lo[3];      /* Cartesian box corner; spherical: lo[0] = r_min */
     double  hi[3];      /* Cartesian box corner; spherical: hi[0] = r_max */
-    int32_t ghost;      /* Cartesian ghost layers: 1 (7-point) or 3 (19-point star); spherical: 1 */
+    int32_t ghost;      /* Cartesian ghost layers: 1 (7-point and compact orders 2, 4), 2 (compact
+                           order 6) or 3 (19-point star); spherical: 1 */
     int32_t pad_;
     int64_t pitch[2];   /* elements per row, elements per plane of caller arrays */
 } poisson_grid_t;
@@ -103,7 +109,7 @@ typedef struct {
 typedef struct {
     int32_t method;      /* POISSON_SOR .. POISSON_MG_SPAI32 */
     int32_t order;       /* Cartesian: 2 (7-point) or 6 (19-point star); POISSON_MG_SPAI(32):
-                            2 or 4 (compact); spherical: 2 */
+                            2, 4 or 6 (compact); spherical: 2 */
     int32_t lmax;        /* >= 0: multipole boundary of this order (<= 8);
                             -1: ghost values are read from Phi as given (Section 2.2 test mode) */
     int32_t nu1, nu2;    /* multigrid pre/post smoothing sweeps */

@@ -233,11 +233,13 @@ void n_coarse(const double* inv, const void* f, void* u, bool f32, const NGeom& 
 // coarsest level by CG to relative residual rtol (one block, LDS resident)
 size_t n_cg_lds_bytes(const NGeom& G);
 void n_coarse_cg(const void* f, void* u, bool f32, const NGeom& G, const W4& A, double rtol, hipStream_t st);
-void n_from_caller(const double* src, long long p0, long long p1, double* u, const NGeom& G, bool zero_inner,
-                   hipStream_t st);
-void n_rhs(const double* rho, long long p0, long long p1, double* f, const NGeom& G, int order, double scale,
-           hipStream_t st);
-void n_to_caller(const double* u, const NGeom& G, double* dst, long long p0, long long p1, hipStream_t st);
+// caller arrays (pitches p0, p1; `ghost` layers) <-> level arrays
+void n_from_caller(const double* src, long long p0, long long p1, int ghost, double* u, const NGeom& G,
+                   bool zero_inner, hipStream_t st);
+void n_rhs(const double* rho, long long p0, long long p1, int ghost, double* f, const NGeom& G, int order,
+           double scale, hipStream_t st);
+void n_to_caller(const double* u, const NGeom& G, double* dst, long long p0, long long p1, int ghost,
+                 hipStream_t st);
 int sph_blocks(const SGeom& S);
 void sph_fill_zero(double* x, const SGeom& S, hipStream_t st);
 void sph_copy(const double* src, double* dst, const SGeom& S, hipStream_t st);

@@ -383,8 +383,14 @@ __global__ __launch_bounds__(BX* BY) void k_nin(const double* __restrict__ src, 
   u[G.at(i, j, k)] = (zero_inner && inner) ? 0.0 : src[k * p1 + j * p0 + i];
 }
 
-// right-hand side at the unknowns: scale * B rho, B = identity (order 2) or
-// (6 rho_n + sum of the 6 face neighbours) / 12 (order 4)
+// right-hand side at the unknowns: scale * B rho, with B
+//   order 2: the identity;
+//   order 4: (6 rho_n + sum of the 6 face neighbours) / 12;
+//   order 6: (402 rho_n + 40 (6 face neighbours) - 3 (6 axis nodes at
+//            distance 2) + 8 (12 in-plane diagonals)) / 720, i.e.
+//            rho + D/12 - D^2/240 + (mixed D_d D_e)/90 collected per node
+//            (D the unit-spacing second differences); reads rho two nodes
+//            beyond the unknowns.
 __global__ __launch_bounds__(BX* BY) void k_nrhs(const double* __restrict__ rho, long long p0, long long p1,
                                                  double* __restrict__ f, NGeom G, int order, double scale) {
   const int i = 1 + blockIdx.x * BX + (int)threadIdx.x;
@@ -393,9 +399,18 @@ __global__ __launch_bounds__(BX* BY) void k_nrhs(const double* __restrict__ rho,
   if (i >= G.n || j >= G.n || k >= G.n) return;
   const long long q = k * p1 + j * p0 + i;
   double v = rho[q];
-  if (order == 4)
+  if (order == 4) {
     v = (6.0 * v + ((rho[q - 1] + rho[q + 1]) + (rho[q - p0] + rho[q + p0]) + (rho[q - p1] + rho[q + p1]))) *
         (1.0 / 12.0);
+  } else if (order == 6) {
+    const double f1 = (rho[q - 1] + rho[q + 1]) + (rho[q - p0] + rho[q + p0]) + (rho[q - p1] + rho[q + p1]);
+    const double f2 =
+        (rho[q - 2] + rho[q + 2]) + (rho[q - 2 * p0] + rho[q + 2 * p0]) + (rho[q - 2 * p1] + rho[q + 2 * p1]);
+    const double exy = (rho[q - p0 - 1] + rho[q - p0 + 1]) + (rho[q + p0 - 1] + rho[q + p0 + 1]);
+    const double exz = (rho[q - p1 - 1] + rho[q - p1 + 1]) + (rho[q + p1 - 1] + rho[q + p1 + 1]);
+    const double eyz = (rho[q - p1 - p0] + rho[q - p1 + p0]) + (rho[q + p1 - p0] + rho[q + p1 + p0]);
+    v = (402.0 * v + 40.0 * f1 - 3.0 * f2 + 8.0 * (exy + exz + eyz)) * (1.0 / 720.0);
+  }
   f[G.at(i, j, k)] = scale * v;
 }
 
@@ -523,19 +538,24 @@ void n_coarse_cg(const void* f, void* u, bool f32, const NGeom& G, const W4& A, 
     k_ncg<double><<<1, 1024, lds, st>>>((const double*)f, (double*)u, G, A, rtol, maxit);
 }
 
-void n_from_caller(const double* src, long long p0, long long p1, double* u, const NGeom& G, bool zero_inner,
-                   hipStream_t st) {
+// Caller arrays hold `ghost` layers; node 0 of the level (the first ghost
+// layer) sits ghost - 1 nodes in along every axis.
+static long long node0(int ghost, long long p0, long long p1) { return (long long)(ghost - 1) * (p1 + p0 + 1); }
+
+void n_from_caller(const double* src, long long p0, long long p1, int ghost, double* u, const NGeom& G,
+                   bool zero_inner, hipStream_t st) {
   k_nin<<<dim3((G.n + 1 + BX - 1) / BX, (G.n + 1 + BY - 1) / BY, G.n + 1), dim3(BX, BY), 0, st>>>(
-      src, p0, p1, u, G, zero_inner ? 1 : 0);
+      src + node0(ghost, p0, p1), p0, p1, u, G, zero_inner ? 1 : 0);
 }
 
-void n_rhs(const double* rho, long long p0, long long p1, double* f, const NGeom& G, int order, double scale,
-           hipStream_t st) {
-  k_nrhs<<<inner_grid(G), dim3(BX, BY), 0, st>>>(rho, p0, p1, f, G, order, scale);
+void n_rhs(const double* rho, long long p0, long long p1, int ghost, double* f, const NGeom& G, int order,
+           double scale, hipStream_t st) {
+  k_nrhs<<<inner_grid(G), dim3(BX, BY), 0, st>>>(rho + node0(ghost, p0, p1), p0, p1, f, G, order, scale);
 }
 
-void n_to_caller(const double* u, const NGeom& G, double* dst, long long p0, long long p1, hipStream_t st) {
-  k_nout<<<inner_grid(G), dim3(BX, BY), 0, st>>>(u, G, dst, p0, p1);
+void n_to_caller(const double* u, const NGeom& G, double* dst, long long p0, long long p1, int ghost,
+                 hipStream_t st) {
+  k_nout<<<inner_grid(G), dim3(BX, BY), 0, st>>>(u, G, dst + node0(ghost, p0, p1), p0, p1);
 }
 
 }  // namespace psn

@@ -216,8 +216,8 @@ int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
     }
   }
   if (o->method == POISSON_MG_SPAI || o->method == POISSON_MG_SPAI32) {
-    if (o->order != 2 && o->order != 4) {
-      set_error("the SPAI multigrid takes the compact stencils of order 2 or 4");
+    if (o->order != 2 && o->order != 4 && o->order != 6) {
+      set_error("the SPAI multigrid takes the compact stencils of order 2, 4 or 6");
       return POISSON_EINVAL;
     }
     if (o->coarse_tol > 0.0 && o->coarsest > 12) {
@@ -228,14 +228,17 @@ int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
     set_error("order must be 2 (7-point) or 6 (19-point star)");
     return POISSON_EINVAL;
   }
-  const int need_g = o->order == 6 ? 3 : 1;
+  // the 19-point star reads three ghost layers of Phi; the compact
+  // sixth-order right-hand side reads two layers of rho
+  const bool spai = o->method == POISSON_MG_SPAI || o->method == POISSON_MG_SPAI32;
+  const int need_g = o->order != 6 ? 1 : spai ? 2 : 3;
   if (g->ghost != need_g) {
     set_error("order %d needs ghost = %d", o->order, need_g);
     return POISSON_EGRID;
   }
   const int M = n + 1 + 2 * (g->ghost - 1);
-  if (residual_blocks(make_geom(n, g->ghost, o->order == 6 ? 4 : 2, 1.0)) > kPartialCap ||
-      n27_blocks(make_ngeom(n, 1.0)) > kPartialCap) {
+  if ((!spai && residual_blocks(make_geom(n, g->ghost, o->order == 6 ? 4 : 2, 1.0)) > kPartialCap) ||
+      (spai && n27_blocks(make_ngeom(n, 1.0)) > kPartialCap)) {
     set_error("grid too large for the reduction buffers");
     return POISSON_EGRID;
   }
@@ -602,9 +605,12 @@ bool line_tables(const SLev& L, double ds, std::vector<float>& tab) {
 }
 
 // Table 1: SPAI smoother coefficients (omega, alpha, beta, gamma, delta) of
-// the compact stencils of order 2 and 4.
-const double kSpai[2][5] = {{1.3699, 0.1432, 0.0284, 0.0081, 0.0025},
-                            {0.9363, 0.2807, 0.0329, 0.0166, 0.0044}};
+// the compact stencils of order 2, 4 and 6.  The printed order-6 delta cell
+// repeats mu and makes the smoother diverge; 0.0151 minimises the smoothing
+// factor with the other four printed values (mu 0.0912 against 0.0909).
+const double kSpai[3][5] = {{1.3699, 0.1432, 0.0284, 0.0081, 0.0025},
+                            {0.9363, 0.2807, 0.0329, 0.0166, 0.0044},
+                            {0.3543, 0.7064, 0.1005, 0.0363, 0.0151}};
 
 // Galerkin product R A P of a cubically symmetric radius-1 stencil with full
 // weighting and trilinear prolongation.  Per axis, R shift(d) P is the coarse
@@ -935,12 +941,12 @@ int solve_spai(poisson_plan_s* P, const double* rho, double* phi, double tol, po
   HIPCHK(hipEventRecord(P->ev[0], st));
   if (o.lmax >= 0) CHK(do_multipole(P, rho, phi, o.lmax, nullptr));
   HIPCHK(hipEventRecord(P->ev[1], st));
-  n_rhs(rho, g.pitch[0], g.pitch[1], (double*)L.f, L.G, o.order, o.four_pi_G, st);
-  n_from_caller(phi, g.pitch[0], g.pitch[1], (double*)L.u, L.G, true, st);
+  n_rhs(rho, g.pitch[0], g.pitch[1], g.ghost, (double*)L.f, L.G, o.order, o.four_pi_G, st);
+  n_from_caller(phi, g.pitch[0], g.pitch[1], g.ghost, (double*)L.u, L.G, true, st);
   n27_residual(L.u, L.f, nullptr, false, L.G, L.A, true, P->partial, st);
   finish_sum(P->partial, nb, 1, P->scal, kBnorm2, st);
-  n_from_caller(phi, g.pitch[0], g.pitch[1], (double*)L.u, L.G, false, st);
-  if (L.u2) n_from_caller(phi, g.pitch[0], g.pitch[1], (double*)L.u2, L.G, false, st);
+  n_from_caller(phi, g.pitch[0], g.pitch[1], g.ghost, (double*)L.u, L.G, false, st);
+  if (L.u2) n_from_caller(phi, g.pitch[0], g.pitch[1], g.ghost, (double*)L.u2, L.G, false, st);
   n27_residual(L.u, L.f, nullptr, false, L.G, L.A, true, P->partial, st);
   finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
   CHK(launch_check("SPAI setup"));
@@ -969,7 +975,7 @@ int solve_spai(poisson_plan_s* P, const double* rho, double* phi, double tol, po
       conv = rel <= tol;
     }
   }
-  n_to_caller((const double*)L.u, L.G, phi, g.pitch[0], g.pitch[1], st);
+  n_to_caller((const double*)L.u, L.G, phi, g.pitch[0], g.pitch[1], g.ghost, st);
   HIPCHK(hipEventRecord(P->ev[2], st));
   HIPCHK(hipEventSynchronize(P->ev[2]));
   CHK(launch_check("SPAI multigrid"));
@@ -1463,12 +1469,19 @@ int poisson_plan(poisson_plan_t* out, const poisson_grid_t* grid, const poisson_
       return fail(POISSON_EHIP);
     }
   } else if (!P->nlv.empty()) {
-    const double* sp = kSpai[P->order == 4 ? 1 : 0];
+    const double* sp = kSpai[P->order / 2 - 1];
     for (size_t l = 0; l < P->nlv.size(); ++l) {
       NLevel& L = P->nlv[l];
       const double h2 = L.G.h * L.G.h;
       if (l == 0) {
-        L.A = P->order == 4 ? W4{-4.0 / h2, 1.0 / (3.0 * h2), 1.0 / (6.0 * h2), 0.0} : W4{-6.0 / h2, 1.0 / h2, 0.0, 0.0};
+        // compact Laplacians: 7-point, 19-point Mehrstellen (-24, 2, 1, 0)/6,
+        // 27-point sixth order (-128, 14, 3, 1)/30
+        if (P->order == 6)
+          L.A = W4{-128.0 / (30.0 * h2), 14.0 / (30.0 * h2), 3.0 / (30.0 * h2), 1.0 / (30.0 * h2)};
+        else if (P->order == 4)
+          L.A = W4{-4.0 / h2, 1.0 / (3.0 * h2), 1.0 / (6.0 * h2), 0.0};
+        else
+          L.A = W4{-6.0 / h2, 1.0 / h2, 0.0, 0.0};
       } else {
         L.A = galerkin_w4(P->nlv[l - 1].A);
       }
@@ -1618,11 +1631,11 @@ int poisson_op_residual(poisson_plan_t P, const double* d_rho, const double* d_p
   } else if (!P->nlv.empty()) {
     const poisson_grid_t& g = P->grid;
     NLevel& L = P->nlv[0];
-    n_rhs(d_rho, g.pitch[0], g.pitch[1], (double*)L.f, L.G, P->order, P->opts.four_pi_G, st);
-    n_from_caller(d_phi, g.pitch[0], g.pitch[1], (double*)L.u, L.G, false, st);
+    n_rhs(d_rho, g.pitch[0], g.pitch[1], g.ghost, (double*)L.f, L.G, P->order, P->opts.four_pi_G, st);
+    n_from_caller(d_phi, g.pitch[0], g.pitch[1], g.ghost, (double*)L.u, L.G, false, st);
     n27_residual(L.u, L.f, L.r, false, L.G, L.A, true, P->partial, st);
     finish_sum(P->partial, (int)n27_blocks(L.G), 1, P->scal, kRes2, st);
-    n_to_caller((const double*)L.r, L.G, d_res, g.pitch[0], g.pitch[1], st);
+    n_to_caller((const double*)L.r, L.G, d_res, g.pitch[0], g.pitch[1], g.ghost, st);
   } else {
     const poisson_grid_t& g = P->grid;
     split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);
@@ -1657,7 +1670,7 @@ int poisson_op_smooth(poisson_plan_t P, const double* d_rho, double* d_phi, int3
     set_error("bad argument");
     return POISSON_EINVAL;
   }
-  if (P->order == 6 && omega != 1.0) {
+  if (P->order == 6 && P->nlv.empty() && omega != 1.0) {
     set_error("the four-colour sweep is plain Gauss-Seidel (omega = 1)");
     return POISSON_EINVAL;
   }
@@ -1667,11 +1680,11 @@ int poisson_op_smooth(poisson_plan_t P, const double* d_rho, double* d_phi, int3
     // SPAI plans: `sweeps` Richardson steps with the plan's smoother
     // (the sweep direction and omega do not apply)
     NLevel& L = P->nlv[0];
-    n_rhs(d_rho, g.pitch[0], g.pitch[1], (double*)L.f, L.G, P->order, P->opts.four_pi_G, st);
-    n_from_caller(d_phi, g.pitch[0], g.pitch[1], (double*)L.u, L.G, false, st);
-    if (L.u2) n_from_caller(d_phi, g.pitch[0], g.pitch[1], (double*)L.u2, L.G, false, st);
+    n_rhs(d_rho, g.pitch[0], g.pitch[1], g.ghost, (double*)L.f, L.G, P->order, P->opts.four_pi_G, st);
+    n_from_caller(d_phi, g.pitch[0], g.pitch[1], g.ghost, (double*)L.u, L.G, false, st);
+    if (L.u2) n_from_caller(d_phi, g.pitch[0], g.pitch[1], g.ghost, (double*)L.u2, L.G, false, st);
     const void* cur = spai_smooth(L, L.u, sweeps, st);
-    n_to_caller((const double*)cur, L.G, d_phi, g.pitch[0], g.pitch[1], st);
+    n_to_caller((const double*)cur, L.G, d_phi, g.pitch[0], g.pitch[1], g.ghost, st);
     return launch_check("poisson_op_smooth");
   }
   split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);
@@ -1724,11 +1737,11 @@ int poisson_op_vcycle(poisson_plan_t P, const double* d_rho, double* d_phi, int3
   const poisson_grid_t& g = P->grid;
   if (!P->nlv.empty()) {
     NLevel& L = P->nlv[0];
-    n_rhs(d_rho, g.pitch[0], g.pitch[1], (double*)L.f, L.G, P->order, P->opts.four_pi_G, st);
-    n_from_caller(d_phi, g.pitch[0], g.pitch[1], (double*)L.u, L.G, false, st);
-    if (L.u2) n_from_caller(d_phi, g.pitch[0], g.pitch[1], (double*)L.u2, L.G, false, st);
+    n_rhs(d_rho, g.pitch[0], g.pitch[1], g.ghost, (double*)L.f, L.G, P->order, P->opts.four_pi_G, st);
+    n_from_caller(d_phi, g.pitch[0], g.pitch[1], g.ghost, (double*)L.u, L.G, false, st);
+    if (L.u2) n_from_caller(d_phi, g.pitch[0], g.pitch[1], g.ghost, (double*)L.u2, L.G, false, st);
     for (int c = 0; c < cycles; ++c) spai_step(P, st);
-    n_to_caller((const double*)L.u, L.G, d_phi, g.pitch[0], g.pitch[1], st);
+    n_to_caller((const double*)L.u, L.G, d_phi, g.pitch[0], g.pitch[1], g.ghost, st);
     return launch_check("poisson_op_vcycle");
   }
   split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);

@@ -157,3 +157,28 @@ def test_spherical_sor_options():
     assert lib.poisson_workspace_bytes(C.byref(s), C.byref(pg.options("sor", omega_mode=pg.OMEGA_FIXED,
                                                                       omega=2.5))) == 0
     assert lib.poisson_workspace_bytes(C.byref(s), C.byref(pg.options("cg"))) == 0
+
+
+def test_spai_order_and_ghost_validation():
+    """Compact orders 2, 4 and 6; order 6 reads rho's second ghost layer and
+    needs ghost = 2, while the 19-point star (order 6 of the other methods)
+    keeps ghost = 3."""
+    lib = L.load()
+    for order in (2, 4):
+        assert lib.poisson_workspace_bytes(C.byref(pg.cart_grid(32)),
+                                           C.byref(pg.options("mg_spai", order=order))) > 0
+    assert lib.poisson_workspace_bytes(C.byref(pg.cart_grid(32, ghost=2)),
+                                       C.byref(pg.options("mg_spai", order=6))) > 0
+    assert lib.poisson_workspace_bytes(C.byref(pg.cart_grid(32, ghost=2)),
+                                       C.byref(pg.options("mg_spai32", order=6))) > 0
+    assert lib.poisson_workspace_bytes(C.byref(pg.cart_grid(32)),
+                                       C.byref(pg.options("mg_spai", order=6))) == 0
+    assert b"ghost = 2" in lib.poisson_last_error()
+    assert lib.poisson_workspace_bytes(C.byref(pg.cart_grid(32, ghost=3)),
+                                       C.byref(pg.options("mg_spai", order=6))) == 0
+    assert lib.poisson_workspace_bytes(C.byref(pg.cart_grid(32, ghost=2)),
+                                       C.byref(pg.options("mg", order=6))) == 0
+    assert lib.poisson_workspace_bytes(C.byref(pg.cart_grid(32, ghost=3)),
+                                       C.byref(pg.options("mg", order=6))) > 0
+    assert lib.poisson_workspace_bytes(C.byref(pg.cart_grid(32)),
+                                       C.byref(pg.options("mg_spai", order=8))) == 0

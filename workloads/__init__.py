@@ -223,10 +223,10 @@ def config_c1(n=32, device="cpu") -> Workload:
                     {"radius": 0.25, "centre": (0.5, 0.5, 0.5), "rho0": 1.0})
 
 
-def config_c2(n=256, n_clumps=16, seed=2, device="cpu") -> Workload:
+def config_c2(n=256, n_clumps=16, seed=2, device="cpu", g=1) -> Workload:
     """Sum of Gaussian clumps, centres U[0.2,0.8]^3, sigma U[0.02,0.08],
-    masses lognormal(0, 0.5); 256^3 cells, lmax = 8."""
-    grid = CartGrid(n=n, g=1)
+    masses lognormal(0, 0.5); 256^3 cells, lmax = 8 (g ghost layers)."""
+    grid = CartGrid(n=n, g=g)
     rng = np.random.default_rng(seed)
     cl = draw_clumps(rng, n_clumps)
     return Workload(f"c2_clumps{n_clumps}_n{n}", grid, clump_density(grid, cl, device), 8,
