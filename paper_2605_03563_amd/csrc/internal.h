@@ -132,6 +132,12 @@ void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, i
 void residual(const void* phi, const void* f, bool in_f32, void* r_out, bool out_f32, const Geom& G,
               int order, bool zero_unknowns_in, double* partial, hipStream_t st);
 int residual_blocks(const Geom& G);   // partials written by residual()
+// f_coarse = R (f - L phi) for the 7-point operator without storing the fine
+// residual; resrestrict_ok tells whether the level's shape is supported
+// (two colours, one ghost layer, at most 256 intervals)
+bool resrestrict_ok(const Geom& Gf);
+void resrestrict(const void* phi, const void* f, bool f32, const Geom& Gf, void* f_coarse, const Geom& Gc,
+                 hipStream_t st);
 void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom& Gc, bool f32,
                  hipStream_t st);
 void prolong_add(const void* e_coarse, const Geom& Gc, void* phi_fine, const Geom& Gf, bool f32,

@@ -76,12 +76,16 @@ template <typename T>
 __device__ inline void store_stream(T* p, T v) { __builtin_nontemporal_store(v, p); }
 
 // 7-point red-black pass of colour c.  The thread owns compact column m of
-// row b and marches planes k0..k1.  The other colour's value at compact m of
-// plane k is, for the node updated on plane k, one x-neighbour, and the
-// z-neighbour of the nodes updated on planes k-1 and k+1, so it is loaded
-// once and kept in registers (zm, zc, zp).  ZG: zero initial guess -- the
-// other colour is taken as 0 (first pass of a cycle on a zeroed correction).
-template <typename T, bool SOR, bool ZG>
+// row b and KZP consecutive planes k0..k1 (k1 - k0 < KZP).  The other
+// colour's value at compact m of plane k is, for the node updated on plane
+// k, one x-neighbour, and the z-neighbour of the nodes updated on planes k-1
+// and k+1, so it is loaded once per plane (z[]).  Every load of the thread's
+// planes is issued before the first update: the loop is unrolled at compile
+// time, plane indices past k1 are clamped to planes inside the array, and
+// only the stores are predicated, so a wavefront keeps all of its planes'
+// loads in flight at once.  ZG: zero initial guess -- the other colour is
+// taken as 0 (first pass of a cycle on a zeroed correction).
+template <typename T, bool SOR, bool ZG, int KZP>
 __global__ __launch_bounds__(256) void k_pass7(T* __restrict__ X, const T* __restrict__ F, Geom G, int c,
                                                T omega, T h2) {
   int bx, by, bz;
@@ -93,35 +97,44 @@ __global__ __launch_bounds__(256) void k_pass7(T* __restrict__ X, const T* __res
   const int kz = planes_per_block(G);
   const int k0 = G.g + bz * kz;
   const int k1 = min(k0 + kz - 1, last);
-  T* __restrict__ Xc = X + (long long)c * G.cs;
-  const T* __restrict__ Xo = X + (long long)(c ^ 1) * G.cs;
-  const T* __restrict__ Fc = F + (long long)c * G.cs;
-  const T sixth = (T)(1.0 / 6.0);
   const long long plane = (long long)G.M * G.W;
-  const T* __restrict__ col = Xo + G.row(b, 0) + m;
-  T zm = (T)0, zc = (T)0;
-  if (!ZG) {
-    zm = col[(k0 - 1) * plane];
-    zc = col[k0 * plane];
-  }
-#pragma unroll 4
-  for (int k = k0; k <= k1; ++k) {
-    T zp = (T)0;
-    if (!ZG) zp = col[(k + 1) * plane];
-    const int r = (c - b - k - G.off) & 1;
-    const int a = 2 * m + r;
-    const long long row = G.row(b, k);
-    if (G.inner(a)) {
-      T s = (T)0;
-      if (!ZG) s = zc + Xo[row + m - 1 + 2 * r] + Xo[row - G.W + m] + Xo[row + G.W + m] + zm + zp;
-      const T gs = (s - h2 * Fc[row + m]) * sixth;
-      if (SOR)
-        Xc[row + m] = ((T)1 - omega) * Xc[row + m] + omega * gs;
-      else
-        store_stream(Xc + row + m, gs);
+  const long long W = G.W;
+  const long long q0 = G.row(b, 0) + m;  // (m, b) on plane 0
+  T* __restrict__ xc = X + (long long)c * G.cs + q0;
+  const T* __restrict__ xo = X + (long long)(c ^ 1) * G.cs + q0;
+  const T* __restrict__ fc = F + (long long)c * G.cs + q0;
+  const T sixth = (T)(1.0 / 6.0);
+  T z[KZP + 2];
+#pragma unroll
+  for (int t = 0; t < KZP + 2; ++t) z[t] = ZG ? (T)0 : xo[(long long)min(k0 - 1 + t, k1 + 1) * plane];
+  T xs[KZP], ym[KZP], yp[KZP], fv[KZP], old[KZP];
+#pragma unroll
+  for (int t = 0; t < KZP; ++t) {
+    const int k = min(k0 + t, k1);
+    const long long o = (long long)k * plane;
+    const int r = (c - b - k - G.off) & 1;  // node a = 2m + r of plane k has colour c
+    if (!ZG) {
+      xs[t] = xo[o + 2 * r - 1];
+      ym[t] = xo[o - W];
+      yp[t] = xo[o + W];
     }
-    zm = zc;
-    zc = zp;
+    fv[t] = fc[o];
+    if (SOR) old[t] = xc[o];
+  }
+#pragma unroll
+  for (int t = 0; t < KZP; ++t) {
+    const int k = k0 + t;
+    const int r = (c - b - k - G.off) & 1;
+    if (k <= k1 && G.inner(2 * m + r)) {
+      T s = (T)0;
+      if (!ZG) s = z[t + 1] + xs[t] + ym[t] + yp[t] + z[t] + z[t + 2];
+      const T gs = (s - h2 * fv[t]) * sixth;
+      T* __restrict__ dst = xc + (long long)k * plane;
+      if (SOR)
+        *dst = ((T)1 - omega) * old[t] + omega * gs;
+      else
+        store_stream(dst, gs);
+    }
   }
 }
 
@@ -401,11 +414,14 @@ __global__ __launch_bounds__(512) void k_residual(const T* __restrict__ X, const
 }
 
 // 7-point residual (no zero-unknown option): the thread owns the two nodes
-// a = 2m (colour s) and a = 2m+1 (colour 1-s) of row (b, k) and keeps both
-// colours' values at compact m of planes k-1, k, k+1 in registers, so each
-// plane costs two new centre loads, two x-neighbour loads, four y-neighbour
-// loads and the two right-hand sides.
-template <typename T, typename TO>
+// a = 2m (colour s) and a = 2m+1 (colour 1-s) of row (b, k) for KZP
+// consecutive planes.  Both colours' values at compact m are loaded once per
+// plane (z0, z1: centre values and z-neighbours); each plane adds two
+// x-neighbour loads, four y-neighbour loads and the two right-hand sides.  As
+// in the colour pass, the loop is unrolled at compile time, load indices past
+// k1 are clamped into the array and only the stores and sums are predicated,
+// so the loads of all planes can be in flight together.
+template <typename T, typename TO, int KZP>
 __global__ __launch_bounds__(256) void k_residual7(const T* __restrict__ X, const T* __restrict__ F,
                                                    TO* __restrict__ R, Geom G, T ih2,
                                                    double* __restrict__ partial) {
@@ -419,41 +435,66 @@ __global__ __launch_bounds__(256) void k_residual7(const T* __restrict__ X, cons
     const int kz = planes_per_block(G);
     const int k0 = G.g + bz * kz;
     const int k1 = min(k0 + kz - 1, last);
-    const T* __restrict__ X0 = X;
-    const T* __restrict__ X1 = X + G.cs;
     const long long plane = (long long)G.M * G.W;
-    const long long cb = G.row(b, 0) + m;
-    T lo0 = X0[cb + (k0 - 1) * plane], lo1 = X1[cb + (k0 - 1) * plane];
-    T cu0 = X0[cb + k0 * plane], cu1 = X1[cb + k0 * plane];
+    const long long W = G.W;
+    const long long q0 = G.row(b, 0) + m;  // (m, b) on plane 0
+    const T* __restrict__ x0 = X + q0;
+    const T* __restrict__ x1 = X + G.cs + q0;
+    // planes in chunks of CH: a chunk's loads are issued together (FP64:
+    // four planes, so that the values in flight stay within the registers)
+    constexpr int CH = sizeof(T) == 8 ? (KZP < 4 ? KZP : 4) : KZP;
+    T z0[KZP + 2], z1[KZP + 2];
+    T xl[KZP], xr[KZP], ya0[KZP], ya1[KZP], yb0[KZP], yb1[KZP], fa[KZP], fb[KZP];
     const bool inA = G.inner(2 * m), inB = G.inner(2 * m + 1);
-    for (int k = k0; k <= k1; ++k) {
-      const T hi0 = X0[cb + (k + 1) * plane], hi1 = X1[cb + (k + 1) * plane];
-      const int s = (b + k + G.off) & 1;  // colour of node a = 2m
-      const T* __restrict__ Pa = s ? X1 : X0;  // colour of A
-      const T* __restrict__ Pb = s ? X0 : X1;  // colour of B
-      const long long row = G.row(b, k);
-      const T uA = s ? cu1 : cu0, uB = s ? cu0 : cu1;
-      if (inA) {
-        // neighbours of A have B's colour
-        const T sx = Pb[row + m - 1] + uB;
-        const T sy = Pb[row - G.W + m] + Pb[row + G.W + m] + (s ? lo0 : lo1) + (s ? hi0 : hi1);
-        const long long idx = (long long)s * G.cs + row + m;
-        const T res = F[idx] - ((sx + sy) - (T)6 * uA) * ih2;
-        if (R) R[idx] = (TO)res;
-        acc += (double)res * (double)res;
+#pragma unroll
+    for (int c0 = 0; c0 < KZP; c0 += CH) {
+#pragma unroll
+      for (int t = (c0 == 0 ? 0 : c0 + 2); t < c0 + CH + 2; ++t) {
+        const long long o = (long long)min(k0 - 1 + t, k1 + 1) * plane;
+        z0[t] = x0[o];
+        z1[t] = x1[o];
       }
-      if (inB) {
-        const T sx = uA + Pa[row + m + 1];
-        const T sy = Pa[row - G.W + m] + Pa[row + G.W + m] + (s ? lo1 : lo0) + (s ? hi1 : hi0);
-        const long long idx = (long long)(s ^ 1) * G.cs + row + m;
-        const T res = F[idx] - ((sx + sy) - (T)6 * uB) * ih2;
-        if (R) R[idx] = (TO)res;
-        acc += (double)res * (double)res;
+#pragma unroll
+      for (int t = c0; t < c0 + CH; ++t) {
+        const int k = min(k0 + t, k1);
+        const long long o = (long long)k * plane;
+        const long long sa = (long long)((b + k + G.off) & 1) * G.cs;  // colour of A = 2m
+        const long long sb = G.cs - sa;                                 // colour of B = 2m+1
+        xl[t] = X[sb + q0 + o - 1];  // A's left neighbour (B's colour)
+        xr[t] = X[sa + q0 + o + 1];  // B's right neighbour (A's colour)
+        yb0[t] = X[sb + q0 + o - W];
+        yb1[t] = X[sb + q0 + o + W];
+        ya0[t] = X[sa + q0 + o - W];
+        ya1[t] = X[sa + q0 + o + W];
+        fa[t] = F[sa + q0 + o];
+        fb[t] = F[sb + q0 + o];
       }
-      lo0 = cu0;
-      lo1 = cu1;
-      cu0 = hi0;
-      cu1 = hi1;
+#pragma unroll
+      for (int t = c0; t < c0 + CH; ++t) {
+        const int k = k0 + t;
+        if (k <= k1) {
+          const int s = (b + k + G.off) & 1;
+          const long long o = (long long)k * plane;
+          const T uA = s ? z1[t + 1] : z0[t + 1], uB = s ? z0[t + 1] : z1[t + 1];
+          // z-neighbours of A have B's colour and vice versa
+          const T zbA = s ? z0[t] + z0[t + 2] : z1[t] + z1[t + 2];
+          const T zbB = s ? z1[t] + z1[t + 2] : z0[t] + z0[t + 2];
+          if (inA) {
+            const T sx = xl[t] + uB;
+            const T sy = yb0[t] + yb1[t] + zbA;
+            const T res = fa[t] - ((sx + sy) - (T)6 * uA) * ih2;
+            if (R) R[(long long)s * G.cs + q0 + o] = (TO)res;
+            acc += (double)res * (double)res;
+          }
+          if (inB) {
+            const T sx = uA + xr[t];
+            const T sy = ya0[t] + ya1[t] + zbB;
+            const T res = fb[t] - ((sx + sy) - (T)6 * uB) * ih2;
+            if (R) R[(long long)(s ^ 1) * G.cs + q0 + o] = (TO)res;
+            acc += (double)res * (double)res;
+          }
+        }
+      }
     }
   }
   if (partial) {
@@ -482,6 +523,144 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ Rf, Geom
       for (int da = -1; da <= 1; ++da)
         s += w[dk + 1] * w[db + 1] * w[da + 1] * Rf[Gf.at(a0 + da, b0 + db, k0 + dk)];
   Fc[Gc.at(A, B, K)] = s;
+}
+
+// Residual of the 7-point operator fused with full-weighting restriction:
+// f_c = R (f - L phi) on the inner coarse nodes, without storing the fine
+// residual.  Only for one ghost layer and two colours (fine node a of compact
+// column m is 2m or 2m+1, coarse node A sits on fine node 2A).
+//
+// A block spans every compact column of the level (blockDim.x = BXR >= n/2,
+// so levels up to 256 intervals)
+// and 2 TYC + 1 fine rows 2 B0 - 1 + ty, i.e. the rows of TYC coarse rows
+// B0 .. B0 + TYC - 1 (the last fine row is recomputed by the next block), and
+// marches fine planes 2 K0 - 1 .. 2 K1 + 1 for KZC coarse planes.  Per fine
+// plane each thread forms the residuals of its two nodes 2m, 2m+1 (as in the
+// residual kernel) and restricts along x with its left neighbour's odd
+// residual from LDS, rx = r(2m)/2 + (r(2m-1) + r(2m+1))/4; the centre fine row
+// of each coarse row then restricts along y from the rows above and below,
+// and the z weights 1/4, 1/2, 1/4 accumulate in registers; a coarse plane is
+// written when its last fine plane is done.  The loads of the next fine plane
+// are issued before the current one's LDS stages, all loads are clamped into
+// the array, and rows or nodes outside the unknowns contribute zero.
+template <typename T, int BXR, int TYC, int KZC>
+__global__ __launch_bounds__(BXR*(2 * TYC + 1)) void k_resrestrict7(const T* __restrict__ X,
+                                                                    const T* __restrict__ F, Geom Gf,
+                                                                    T* __restrict__ Fc, Geom Gc, T ih2) {
+  constexpr int TYF = 2 * TYC + 1;
+  __shared__ T s_odd[2][TYF][BXR];
+  __shared__ T s_rx[2][TYF][BXR];
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int n = Gf.n;            // fine intervals; unknowns 1..n-1 (g = 1)
+  const int nc = Gc.n;           // coarse intervals
+  const int B0 = 1 + by * TYC;
+  const int K0 = 1 + bz * KZC;
+  const int K1 = min(K0 + KZC - 1, nc - 1);
+  const int m = tx;                            // compact column (mlo = 0 for g = 1)
+  const int b = 2 * B0 - 1 + ty;               // fine row
+  const bool rowok = b <= n - 1 && m <= Gf.mhi();
+  const int bl = min(b, n - 1);                // row used for (discarded) loads
+  const int ml = min(m, Gf.mhi());
+  const long long plane = (long long)Gf.M * Gf.W;
+  const long long W = Gf.W;
+  const long long q0 = (long long)bl * W + ml;  // (m, b) on plane 0
+  const T* __restrict__ x0 = X + q0;
+  const T* __restrict__ x1 = X + Gf.cs + q0;
+  const bool inA = rowok && Gf.inner(2 * m), inB = rowok && Gf.inner(2 * m + 1);
+  const int kf0 = 2 * K0 - 1, kf1 = 2 * K1 + 1;
+  // loads of plane k: the z-window's next centre values (plane k+1) and the
+  // neighbours / right-hand sides of plane k
+  struct Ld {
+    T hi0, hi1, xl, xr, ya0, ya1, yb0, yb1, fa, fb;
+  };
+  auto load = [&](int k) {
+    Ld v;
+    const long long oz = (long long)min(k + 1, n) * plane;
+    v.hi0 = x0[oz];
+    v.hi1 = x1[oz];
+    const long long o = (long long)k * plane;
+    const long long sa = (long long)((bl + k + Gf.off) & 1) * Gf.cs;  // colour of node 2m
+    const long long sb = Gf.cs - sa;
+    v.xl = X[sb + q0 + o - 1];
+    v.xr = X[sa + q0 + o + 1];
+    v.yb0 = X[sb + q0 + o - W];
+    v.yb1 = X[sb + q0 + o + W];
+    v.ya0 = X[sa + q0 + o - W];
+    v.ya1 = X[sa + q0 + o + W];
+    v.fa = F[sa + q0 + o];
+    v.fb = F[sb + q0 + o];
+    return v;
+  };
+  T lo0 = x0[(long long)(kf0 - 1) * plane], lo1 = x1[(long long)(kf0 - 1) * plane];
+  T cu0 = x0[(long long)kf0 * plane], cu1 = x1[(long long)kf0 * plane];
+  Ld cur = load(kf0);
+  T acc = (T)0;
+  const bool centre = (ty & 1) && (B0 + (ty >> 1)) <= nc - 1;  // fine row 2B of coarse row B
+  const bool outx = m >= 1 && m <= nc - 1;                      // coarse column A = m inner
+  const T q = (T)0.25, hf = (T)0.5;
+  for (int k = kf0; k <= kf1; ++k) {
+    const Ld nxt = load(min(k + 1, kf1));
+    const int s = (bl + k + Gf.off) & 1;
+    const T uA = s ? cu1 : cu0, uB = s ? cu0 : cu1;
+    T rA = (T)0, rB = (T)0;
+    if (inA) {
+      const T sx = cur.xl + uB;
+      const T sy = cur.yb0 + cur.yb1 + (s ? lo0 + cur.hi0 : lo1 + cur.hi1);
+      rA = cur.fa - ((sx + sy) - (T)6 * uA) * ih2;
+    }
+    if (inB) {
+      const T sx = uA + cur.xr;
+      const T sy = cur.ya0 + cur.ya1 + (s ? lo1 + cur.hi1 : lo0 + cur.hi0);
+      rB = cur.fb - ((sx + sy) - (T)6 * uB) * ih2;
+    }
+    const int buf = k & 1;
+    s_odd[buf][ty][tx] = rB;
+    __syncthreads();
+    const T left = tx > 0 ? s_odd[buf][ty][tx - 1] : (T)0;
+    s_rx[buf][ty][tx] = hf * rA + q * (left + rB);
+    __syncthreads();
+    if (centre) {
+      const T ry = hf * s_rx[buf][ty][tx] + q * (s_rx[buf][ty - 1][tx] + s_rx[buf][ty + 1][tx]);
+      if (k & 1) {
+        // odd fine plane 2K+1: closes coarse plane K (unless k = kf0) and opens K+1
+        acc += q * ry;
+        const int K = (k - 1) >> 1;
+        if (k > kf0 && outx) Fc[Gc.at(m, B0 + (ty >> 1), K)] = acc;
+        acc = q * ry;
+      } else {
+        acc += hf * ry;
+      }
+    }
+    lo0 = cu0;
+    lo1 = cu1;
+    cu0 = cur.hi0;
+    cu1 = cur.hi1;
+    cur = nxt;
+  }
+}
+
+template <typename T, int BXR, int TYC, int KZC>
+static void resrestrict7_go(const T* phi, const T* f, const Geom& Gf, T* fc, const Geom& Gc, hipStream_t st) {
+  const int nc = Gc.n;
+  const T ih2 = (T)(1.0 / (Gf.h * Gf.h));
+  const dim3 grid(1, (nc - 1 + TYC - 1) / TYC, (nc - 1 + KZC - 1) / KZC);
+  k_resrestrict7<T, BXR, TYC, KZC><<<grid, dim3(BXR, 2 * TYC + 1), 0, st>>>(phi, f, Gf, fc, Gc, ih2);
+}
+
+// Large levels: several coarse rows and planes per block (little recomputed
+// halo); small levels: one coarse row and plane per block (short dependent
+// chains, many blocks).
+template <typename T>
+static void resrestrict7_t(const T* phi, const T* f, const Geom& Gf, T* fc, const Geom& Gc, hipStream_t st) {
+  const int mc = Gf.mhi() + 1;
+  if (mc <= 32)
+    resrestrict7_go<T, 64, 1, 1>(phi, f, Gf, fc, Gc, st);
+  else if (mc <= 64)
+    resrestrict7_go<T, 64, 1, 4>(phi, f, Gf, fc, Gc, st);
+  else
+    resrestrict7_go<T, 128, 2, 4>(phi, f, Gf, fc, Gc, st);
 }
 
 // phi_fine += P e_coarse, P = 8 R^T (trilinear interpolation).  One thread
@@ -957,6 +1136,27 @@ void copy_ghosts_split(const double* src, void* dst, bool dst_f32, const Geom& G
     k_ghost_copy<double><<<node_grid(G.M), dim3(BX, BY), 0, st>>>(src, (double*)dst, G);
 }
 
+// planes per thread fixed at compile time: KZ on large levels, one on small
+template <typename T, bool SOR, bool ZG>
+static void pass7_kz(T* x, const T* f, const Geom& G, int colour, T omega, T h2, dim3 grid, dim3 blk,
+                     hipStream_t st) {
+  if (kz_for(G) == KZ)
+    k_pass7<T, SOR, ZG, KZ><<<grid, blk, 0, st>>>(x, f, G, colour, omega, h2);
+  else
+    k_pass7<T, SOR, ZG, 1><<<grid, blk, 0, st>>>(x, f, G, colour, omega, h2);
+}
+
+template <typename T>
+static void pass7_launch(T* x, const T* f, const Geom& G, int colour, bool sor, bool zg, T omega, T h2, dim3 grid,
+                         dim3 blk, hipStream_t st) {
+  if (sor)
+    pass7_kz<T, true, false>(x, f, G, colour, omega, h2, grid, blk, st);
+  else if (zg)
+    pass7_kz<T, false, true>(x, f, G, colour, (T)1, h2, grid, blk, st);
+  else
+    pass7_kz<T, false, false>(x, f, G, colour, (T)1, h2, grid, blk, st);
+}
+
 void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, int colour, double omega,
                  hipStream_t st, int zmask) {
   const dim3 grid = col_grid(G), blk(BX, BY);
@@ -965,23 +1165,10 @@ void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, i
     const bool sor = omega != 1.0;
     const bool zg = (zmask >> (colour ^ 1)) & 1;
     if (f32) {
-      float* x = (float*)phi;
-      const float* ff = (const float*)f;
-      if (sor)
-        k_pass7<float, true, false><<<grid, blk, 0, st>>>(x, ff, G, colour, (float)omega, (float)h2);
-      else if (zg)
-        k_pass7<float, false, true><<<grid, blk, 0, st>>>(x, ff, G, colour, 1.0f, (float)h2);
-      else
-        k_pass7<float, false, false><<<grid, blk, 0, st>>>(x, ff, G, colour, 1.0f, (float)h2);
+      pass7_launch<float>((float*)phi, (const float*)f, G, colour, sor, zg, (float)omega, (float)h2, grid, blk,
+                          st);
     } else {
-      double* x = (double*)phi;
-      const double* ff = (const double*)f;
-      if (sor)
-        k_pass7<double, true, false><<<grid, blk, 0, st>>>(x, ff, G, colour, omega, h2);
-      else if (zg)
-        k_pass7<double, false, true><<<grid, blk, 0, st>>>(x, ff, G, colour, 1.0, h2);
-      else
-        k_pass7<double, false, false><<<grid, blk, 0, st>>>(x, ff, G, colour, 1.0, h2);
+      pass7_launch<double>((double*)phi, (const double*)f, G, colour, sor, zg, omega, h2, grid, blk, st);
     }
   } else {
     if (f32)
@@ -1000,7 +1187,10 @@ static void residual_t(const T* phi, const T* f, TO* r, const Geom& G, int order
     if (zu)
       k_residual<T, TO, 2, true><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
     else
-      k_residual7<T, TO><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
+      if (kz_for(G) == KZ)
+        k_residual7<T, TO, KZ><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
+      else
+        k_residual7<T, TO, 1><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
   } else {
     // both variants launch on the staged grid so that partial-sum counts agree
     const dim3 sg = staged_grid(G), sb(BX, TBY);
@@ -1023,6 +1213,16 @@ void residual(const void* phi, const void* f, bool in_f32, void* r_out, bool out
     residual_t<double, double>((const double*)phi, (const double*)f, (double*)r_out, G, order, zu, partial,
                                st);
   }
+}
+
+bool resrestrict_ok(const Geom& Gf) { return Gf.C == 2 && Gf.g == 1 && Gf.n >= 4 && Gf.mhi() + 1 <= 128; }
+
+void resrestrict(const void* phi, const void* f, bool f32, const Geom& Gf, void* f_coarse, const Geom& Gc,
+                 hipStream_t st) {
+  if (f32)
+    resrestrict7_t<float>((const float*)phi, (const float*)f, Gf, (float*)f_coarse, Gc, st);
+  else
+    resrestrict7_t<double>((const double*)phi, (const double*)f, Gf, (double*)f_coarse, Gc, st);
 }
 
 void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom& Gc, bool f32, hipStream_t st) {

@@ -672,9 +672,13 @@ void vcycle(poisson_plan_s* P, int l, bool zero_guess, hipStream_t st) {
       if (zero_guess && s == 0) zmask = ((1 << C) - 1) & ~((1 << (c + 1)) - 1);  // colours > c
       colour_pass(L.phi, L.f, f32, L.G, P->order, c, 1.0, st, zmask);
     }
-  residual(L.phi, L.f, f32, L.tmp, f32, L.G, P->order, false, nullptr, st);
   Level& Lc = P->lv[l + 1];
-  restrict_fw(L.tmp, L.G, Lc.f, Lc.G, f32, st);
+  if (P->order == 2 && resrestrict_ok(L.G)) {
+    resrestrict(L.phi, L.f, f32, L.G, Lc.f, Lc.G, st);
+  } else {
+    residual(L.phi, L.f, f32, L.tmp, f32, L.G, P->order, false, nullptr, st);
+    restrict_fw(L.tmp, L.G, Lc.f, Lc.G, f32, st);
+  }
   vcycle(P, l + 1, true, st);
   prolong_add(Lc.phi, Lc.G, L.phi, L.G, f32, st);
   for (int s = 0; s < o.nu2; ++s)
