@@ -3,6 +3,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <vector>
 #include <stdint.h>
 #include <stddef.h>
 
@@ -163,8 +165,29 @@ void cg_scalars(const double* partial, int nb, Scalars* scal, int stage, hipStre
 int cg_blocks(const Geom& G);
 
 // multipole (Section 2.2)
-void cart_moments(const double* rho, long long p0, long long p1, int n, int g, double h, double cx,
-                  double cy, double cz, int lmax, double* partial, hipStream_t st);
+// Monomial form of the regular solid harmonics (device copies): monomial t
+// (degree-ordered, all a + b + c <= kLmaxMax) is mono[t] = a | b << 4 | c << 8;
+// R_q (q = l^2 + l + m) = sum over e in [toff[q], toff[q+1]) of
+// tcoef[e] x^a y^b z^c with (a, b, c) = monomial tmono[e].
+struct MomTables {
+  const int* mono;
+  const int* toff;
+  const int* tmono;
+  const double* tcoef;
+};
+constexpr int kMonoMax = (kLmaxMax + 1) * (kLmaxMax + 2) * (kLmaxMax + 3) / 6;  // 165
+constexpr int kTermMax = 1024;  // bound on the number of terms (415 at lmax 8)
+// host construction of the tables from the recurrence; returns false if the
+// term count exceeds kTermMax
+bool build_mom_tables(std::vector<int>& mono, std::vector<int>& toff, std::vector<int>& tmono,
+                      std::vector<double>& tcoef);
+// scratch of the separable Cartesian moments (bytes) for n intervals
+size_t cart_moment_scratch(int n);
+// q (nq = (lmax+1)^2 values, point_mass added to q_00) of the Cartesian node
+// array rho by separable monomial sums
+void cart_moments(const double* rho, long long p0, long long p1, int n, int g, double h, double cx, double cy,
+                  double cz, int lmax, const MomTables& tab, double point_mass, double* scratch, double* q,
+                  hipStream_t st);
 void sph_moments(const double* rho, const SGeom& S, int lmax, bool inner, double* partial, hipStream_t st);
 void finish_moments(const double* partial, int nq, double point_mass, double* q, hipStream_t st);
 void cart_ghosts(double* phi, long long p0, long long p1, int n, int g, double h, double lo, double cx,

@@ -114,31 +114,149 @@ __device__ inline void store_partials(double* acc, double* __restrict__ partial)
   }
 }
 
+// ------------------------------------------------- Cartesian moments, separable
+// R_lm is a homogeneous polynomial of degree l, so the Cartesian moments are
+// fixed combinations of the monomial moments
+//   M_abc = h^3 sum_nodes rho x^a y^b z^c,   a + b + c <= lmax,
+// which factor along the axes: T_b(i,k) = sum_j rho y_j^b (threads along x
+// march y), V_ab(k) = sum_i x_i^a T_b(i,k) (one block per plane), M_abc =
+// sum_k z_k^c V_ab(k) (one block), and q_lm = sum C_lm^abc M_abc with the
+// monomial coefficients of R_lm (host table from the same recurrence as
+// regular_solid).  Every sum runs in a fixed order.
+
+// Stage 1: thread (i, k) of chunk c sums rows j = c, c + JCH, ... < E
+// (interleaved, so both chunks stream the whole plane); T[c][k][b][i] with
+// row pitch TP.
+constexpr int kMomChunks = 2;
 template <int LMAX>
-__global__ __launch_bounds__(kMomThreads) void k_cart_moments(const double* __restrict__ rho, long long p0,
-                                                              long long p1, int n, int g, double h, double cx,
-                                                              double cy, double cz, double lo,
-                                                              double* __restrict__ partial) {
-  constexpr int NQ = (LMAX + 1) * (LMAX + 1);
-  double acc[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+__global__ __launch_bounds__(256) void k_mom_rows(const double* __restrict__ rho, long long p0, long long p1, int n,
+                                                  int g, double h, double y0, double* __restrict__ T, int TP) {
   const int E = n - 1;
-  const long long total = (long long)E * E * E;
-  const double w = h * h * h;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
-       t += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(t % E);
-    const int j = (int)((t / E) % E);
-    const int k = (int)(t / ((long long)E * E));
-    const double v = rho[(long long)(k + g) * p1 + (long long)(j + g) * p0 + (i + g)];
-    if (v == 0.0) continue;
-    const double x = lo + (i + 1) * h - cx;
-    const double y = lo + (j + 1) * h - cy;
-    const double z = lo + (k + 1) * h - cz;
-    regular_solid<LMAX>(x, y, z, w * v, acc);
+  const int i = blockIdx.x * 64 + (int)threadIdx.x;
+  const int k = blockIdx.y * 4 + (int)threadIdx.y;
+  const int c = blockIdx.z;
+  if (i >= E || k >= E) return;
+  const double* __restrict__ col = rho + (long long)(k + g) * p1 + (long long)g * p0 + (i + g);
+  double acc[LMAX + 1];
+#pragma unroll
+  for (int b = 0; b <= LMAX; ++b) acc[b] = 0.0;
+  int j = c;
+  // eight rows per round, loads first
+  for (; j + 7 * kMomChunks < E; j += 8 * kMomChunks) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = col[(long long)(j + u * kMomChunks) * p0];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const double y = y0 + (j + u * kMomChunks) * h;
+      double t = v[u];
+#pragma unroll
+      for (int b = 0; b <= LMAX; ++b) {
+        acc[b] += t;
+        t *= y;
+      }
+    }
   }
-  store_partials<LMAX>(acc, partial);
+  for (; j < E; j += kMomChunks) {
+    const double y = y0 + j * h;
+    double t = col[(long long)j * p0];
+#pragma unroll
+    for (int b = 0; b <= LMAX; ++b) {
+      acc[b] += t;
+      t *= y;
+    }
+  }
+  double* __restrict__ out = T + ((long long)(c * E + k) * (LMAX + 1)) * TP + i;
+#pragma unroll
+  for (int b = 0; b <= LMAX; ++b) out[(long long)b * TP] = acc[b];
+}
+
+// Stage 2: one block per plane k; V[k][ab] for the (a, b) pairs with
+// a + b <= LMAX in the order a = 0.., b = 0..LMAX-a.  Each wave reduces its
+// products with shuffles, the waves' sums meet in LDS.
+template <int LMAX>
+__global__ __launch_bounds__(256) void k_mom_cols(const double* __restrict__ T, int TP, int n, double h, double x0,
+                                                  double* __restrict__ V) {
+  constexpr int NAB = (LMAX + 1) * (LMAX + 2) / 2;
+  __shared__ double red[NAB][4];
+  const int E = n - 1;
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x;
+  double acc[NAB];
+#pragma unroll
+  for (int q = 0; q < NAB; ++q) acc[q] = 0.0;
+  for (int i = tid; i < E; i += 256) {
+    double tb[LMAX + 1];
+#pragma unroll
+    for (int b = 0; b <= LMAX; ++b) {
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < kMomChunks; ++c) s += T[((long long)(c * E + k) * (LMAX + 1) + b) * TP + i];
+      tb[b] = s;
+    }
+    const double x = x0 + i * h;
+    double xa = 1.0;
+    int q = 0;
+#pragma unroll
+    for (int a = 0; a <= LMAX; ++a) {
+#pragma unroll
+      for (int b = 0; b + a <= LMAX; ++b) acc[q++] += xa * tb[b];
+      xa *= x;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NAB; ++q) {
+    const double w = wave_sum(acc[q]);
+    if ((tid & 63) == 0) red[q][tid >> 6] = w;
+  }
+  __syncthreads();
+  if (tid < NAB) V[(long long)k * NAB + tid] = (red[tid][0] + red[tid][1]) + (red[tid][2] + red[tid][3]);
+}
+
+// Stage 3: one block; thread t < NM owns monomial (a, b, c) = mono[t]
+// (packed a | b << 4 | c << 8) and sums over the planes; then thread q < nq
+// forms q_lm = sum of its terms coef * M[mono index] (+ point mass on q_00).
+template <int LMAX>
+__global__ __launch_bounds__(256) void k_mom_finish(const double* __restrict__ V, int n, double h, double z0,
+                                                    const int* __restrict__ mono, const int* __restrict__ toff,
+                                                    const int* __restrict__ tmono, const double* __restrict__ tcoef,
+                                                    double point_mass, double* __restrict__ q) {
+  constexpr int NAB = (LMAX + 1) * (LMAX + 2) / 2;
+  constexpr int NM = (LMAX + 1) * (LMAX + 2) * (LMAX + 3) / 6;
+  constexpr int NQ = (LMAX + 1) * (LMAX + 1);
+  __shared__ double M[NM];
+  const int E = n - 1;
+  const int t = threadIdx.x;
+  if (t < NM) {
+    const int a = mono[t] & 15, b = (mono[t] >> 4) & 15, c = (mono[t] >> 8) & 15;
+    // index of (a, b) in V's pair order
+    const int ab = a * (LMAX + 1) - a * (a - 1) / 2 + b;
+    double s0 = 0.0, s1 = 0.0;
+    int k = 0;
+    for (; k + 1 < E; k += 2) {
+      const double za = z0 + k * h, zb = za + h;
+      double pa = 1.0, pb = 1.0;
+      for (int u = 0; u < c; ++u) {
+        pa *= za;
+        pb *= zb;
+      }
+      s0 += pa * V[(long long)k * NAB + ab];
+      s1 += pb * V[(long long)(k + 1) * NAB + ab];
+    }
+    if (k < E) {
+      const double za = z0 + k * h;
+      double pa = 1.0;
+      for (int u = 0; u < c; ++u) pa *= za;
+      s0 += pa * V[(long long)k * NAB + ab];
+    }
+    M[t] = (s0 + s1) * (h * h * h);
+  }
+  __syncthreads();
+  if (t < NQ) {
+    double s = 0.0;
+    for (int e = toff[t]; e < toff[t + 1]; ++e) s += tcoef[e] * M[tmono[e]];
+    q[t] = s + (t == 0 ? point_mass : 0.0);
+  }
 }
 
 template <int LMAX, bool INNER>
@@ -262,13 +380,134 @@ __global__ __launch_bounds__(256) void k_sph_ghosts(double* __restrict__ phi, SG
     default: CALL(8); break;     \
   }
 
+// Host: the recurrence of regular_solid carried out on polynomials (dense
+// complex coefficient arrays over x^a y^b z^c, a, b, c <= kLmaxMax).
+namespace {
+constexpr int kP = kLmaxMax + 1;
+struct Poly {
+  double re[kP][kP][kP] = {};
+  double im[kP][kP][kP] = {};
+};
+}  // namespace
+
+bool build_mom_tables(std::vector<int>& mono, std::vector<int>& toff, std::vector<int>& tmono,
+                      std::vector<double>& tcoef) {
+  const int L = kLmaxMax;
+  // monomials ordered by total degree
+  int index[kP][kP][kP];
+  mono.clear();
+  for (int d = 0; d <= L; ++d)
+    for (int a = d; a >= 0; --a)
+      for (int b = d - a; b >= 0; --b) {
+        const int c = d - a - b;
+        index[a][b][c] = (int)mono.size();
+        mono.push_back(a | (b << 4) | (c << 8));
+      }
+  std::vector<std::vector<std::pair<int, double>>> terms(kNqMax);
+  auto emit = [&](int qi, const double (&p)[kP][kP][kP], double scale) {
+    for (int a = 0; a < kP; ++a)
+      for (int b = 0; b < kP; ++b)
+        for (int c = 0; c < kP; ++c)
+          if (p[a][b][c] != 0.0) terms[qi].push_back({index[a][b][c], scale * p[a][b][c]});
+  };
+  Poly q;  // Q_mm
+  q.re[0][0][0] = 1.0;
+  for (int m = 0; m <= L; ++m) {
+    if (m > 0) {
+      // Q_mm = Q_{m-1,m-1} (x + i y) sqrt((2m-1)/(2m))
+      const double f = sqrt((2.0 * m - 1.0) / (2.0 * m));
+      Poly nq;
+      for (int a = 0; a < kP; ++a)
+        for (int b = 0; b < kP; ++b)
+          for (int c = 0; c < kP; ++c) {
+            const double r = q.re[a][b][c], i = q.im[a][b][c];
+            if (r == 0.0 && i == 0.0) continue;
+            if (a + 1 < kP) {  // times x
+              nq.re[a + 1][b][c] += f * r;
+              nq.im[a + 1][b][c] += f * i;
+            }
+            if (b + 1 < kP) {  // times i y
+              nq.re[a][b + 1][c] -= f * i;
+              nq.im[a][b + 1][c] += f * r;
+            }
+          }
+      q = nq;
+    }
+    Poly p = q, pp;
+    for (int l = m; l <= L; ++l) {
+      if (l > m) {
+        // Q_lm = [(2l-1) z Q_{l-1,m} - r^2 sqrt((l+m-1)(l-m-1)) Q_{l-2,m}] / sqrt((l+m)(l-m))
+        const double ca = (2.0 * l - 1.0) / sqrt((double)(l + m) * (double)(l - m));
+        const double cb = sqrt((double)(l + m - 1) * (double)(l - m - 1)) / sqrt((double)(l + m) * (double)(l - m));
+        Poly np;
+        for (int a = 0; a < kP; ++a)
+          for (int b = 0; b < kP; ++b)
+            for (int c = 0; c < kP; ++c) {
+              if (c + 1 < kP) {
+                np.re[a][b][c + 1] += ca * p.re[a][b][c];
+                np.im[a][b][c + 1] += ca * p.im[a][b][c];
+              }
+              const double r = pp.re[a][b][c], i = pp.im[a][b][c];
+              if (r == 0.0 && i == 0.0) continue;
+              if (a + 2 < kP) {
+                np.re[a + 2][b][c] -= cb * r;
+                np.im[a + 2][b][c] -= cb * i;
+              }
+              if (b + 2 < kP) {
+                np.re[a][b + 2][c] -= cb * r;
+                np.im[a][b + 2][c] -= cb * i;
+              }
+              if (c + 2 < kP) {
+                np.re[a][b][c + 2] -= cb * r;
+                np.im[a][b][c + 2] -= cb * i;
+              }
+            }
+        pp = p;
+        p = np;
+      }
+      if (m == 0) {
+        emit(l * l + l, p.re, 1.0);
+      } else {
+        emit(l * l + l + m, p.re, 1.4142135623730951);
+        emit(l * l + l - m, p.im, 1.4142135623730951);
+      }
+    }
+  }
+  toff.assign(1, 0);
+  tmono.clear();
+  tcoef.clear();
+  for (int qi = 0; qi < kNqMax; ++qi) {
+    for (const auto& t : terms[qi]) {
+      tmono.push_back(t.first);
+      tcoef.push_back(t.second);
+    }
+    toff.push_back((int)tmono.size());
+  }
+  return (int)tmono.size() <= kTermMax;
+}
+
+size_t cart_moment_scratch(int n) {
+  const int E = n - 1;
+  const long long TP = (E + 63) / 64 * 64;
+  return sizeof(double) * ((long long)kMomChunks * E * (kLmaxMax + 1) * TP +
+                           (long long)E * ((kLmaxMax + 1) * (kLmaxMax + 2) / 2));
+}
+
 void cart_moments(const double* rho, long long p0, long long p1, int n, int g, double h, double cx, double cy,
-                  double cz, int lmax, double* partial, hipStream_t st) {
-  // lo is recovered from the centre: node array index a has position
-  // lo + (a - (g-1)) h; the kernel uses unknown index i (node i+1) directly.
+                  double cz, int lmax, const MomTables& tab, double point_mass, double* scratch, double* q,
+                  hipStream_t st) {
+  // unknown i (node i + 1) sits at lo + (i + 1) h; lo = centre - n h / 2
   const double lo = cx - 0.5 * n * h;
-#define PSN_CALL(L) \
-  k_cart_moments<L><<<kMomBlocks, kMomThreads, 0, st>>>(rho, p0, p1, n, g, h, cx, cy, cz, lo, partial)
+  const double x0 = lo + h - cx, y0 = (cy - 0.5 * n * h) + h - cy, z0 = (cz - 0.5 * n * h) + h - cz;
+  const int E = n - 1;
+  const int TP = (E + 63) / 64 * 64;
+  double* T = scratch;
+  double* V = scratch + (long long)kMomChunks * E * (kLmaxMax + 1) * TP;
+  const dim3 g1((E + 63) / 64, (E + 3) / 4, kMomChunks), b1(64, 4);
+#define PSN_CALL(L)                                                                                     \
+  k_mom_rows<L><<<g1, b1, 0, st>>>(rho, p0, p1, n, g, h, y0, T, TP);                                    \
+  k_mom_cols<L><<<E, 256, 0, st>>>(T, TP, n, h, x0, V);                                                 \
+  k_mom_finish<L><<<1, 256, 0, st>>>(V, n, h, z0, tab.mono, tab.toff, tab.tmono, tab.tcoef, point_mass, q)
   PSN_LMAX_SWITCH(lmax, PSN_CALL)
 #undef PSN_CALL
 }

@@ -288,6 +288,13 @@ void carve(poisson_plan_s* P, Carver& cv) {
   P->partial = (double*)cv.take(sizeof(double) * std::max<long long>(2 * kPartialCap, (long long)kNqMax * kMomBlocks));
   P->scal = (Scalars*)cv.take(sizeof(Scalars));
   P->qlm = (double*)cv.take(sizeof(double) * 2 * kNqMax);
+  if (!P->sph) {
+    P->mom_mono = (int*)cv.take(sizeof(int) * kMonoMax);
+    P->mom_toff = (int*)cv.take(sizeof(int) * (kNqMax + 1));
+    P->mom_tmono = (int*)cv.take(sizeof(int) * kTermMax);
+    P->mom_tcoef = (double*)cv.take(sizeof(double) * kTermMax);
+    P->mom_scratch = (double*)cv.take(cart_moment_scratch(g.n[0]));
+  }
   if (P->sph) {
     const long long elems = g.pitch[1] * (long long)g.n[2];
     const size_t vb = sizeof(double) * elems;
@@ -858,8 +865,9 @@ int do_multipole(poisson_plan_s* P, const double* rho, double* phi, int lmax, do
     const int n = g.n[0];
     const double h = (g.hi[0] - g.lo[0]) / n;
     const double cx = 0.5 * (g.lo[0] + g.hi[0]), cy = 0.5 * (g.lo[1] + g.hi[1]), cz = 0.5 * (g.lo[2] + g.hi[2]);
-    cart_moments(rho, g.pitch[0], g.pitch[1], n, g.ghost, h, cx, cy, cz, lmax, P->partial, st);
-    finish_moments(P->partial, nq, P->opts.point_mass, P->qlm, st);
+    const MomTables tab{P->mom_mono, P->mom_toff, P->mom_tmono, P->mom_tcoef};
+    cart_moments(rho, g.pitch[0], g.pitch[1], n, g.ghost, h, cx, cy, cz, lmax, tab, P->opts.point_mass,
+                 P->mom_scratch, P->qlm, st);
     cart_ghosts(phi, g.pitch[0], g.pitch[1], n, g.ghost, h, g.lo[0], cx, cy, cz, lmax, P->qlm, G, st);
   } else {
     sph_moments(rho, P->S, lmax, false, P->partial, st);
@@ -1377,6 +1385,27 @@ int poisson_plan(poisson_plan_t* out, const poisson_grid_t* grid, const poisson_
   // zero the whole workspace once: ghosts of correction and direction
   // vectors must stay zero and are never written afterwards
   fill_zero(d_workspace, false, (long long)(need / sizeof(double)), st);
+  if (!P->sph) {
+    // monomial tables of the Cartesian multipole moments
+    std::vector<int> mono, toff, tmono;
+    std::vector<double> tcoef;
+    if (!build_mom_tables(mono, toff, tmono, tcoef)) {
+      set_error("multipole term table exceeds its bound");
+      return fail(POISSON_ENUMERIC);
+    }
+    if (hipMemcpyAsync(P->mom_mono, mono.data(), sizeof(int) * mono.size(), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(P->mom_toff, toff.data(), sizeof(int) * toff.size(), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(P->mom_tmono, tmono.data(), sizeof(int) * tmono.size(), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(P->mom_tcoef, tcoef.data(), sizeof(double) * tcoef.size(), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      set_error("upload of the multipole tables failed");
+      return fail(POISSON_EHIP);
+    }
+  }
   if (P->sph) {
     const poisson_grid_t& g = *grid;
     SGeom& S = P->S;

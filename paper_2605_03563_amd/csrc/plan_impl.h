@@ -71,6 +71,12 @@ struct poisson_plan_s {
   double* partial = nullptr;
   psn::Scalars* scal = nullptr;
   double* qlm = nullptr;  // 2 * kNqMax
+  // Cartesian moments: monomial tables and the separable sums' scratch
+  int* mom_mono = nullptr;
+  int* mom_toff = nullptr;
+  int* mom_tmono = nullptr;
+  double* mom_tcoef = nullptr;
+  double* mom_scratch = nullptr;
   double* host = nullptr; // pinned scalars
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   hipGraphExec_t step_exec = nullptr;
