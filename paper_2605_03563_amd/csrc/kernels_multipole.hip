@@ -120,14 +120,13 @@ __device__ inline void store_partials(double* acc, double* __restrict__ partial)
 //   M_abc = h^3 sum_nodes rho x^a y^b z^c,   a + b + c <= lmax,
 // which factor along the axes: T_b(i,k) = sum_j rho y_j^b (threads along x
 // march y), V_ab(k) = sum_i x_i^a T_b(i,k) (one block per plane), M_abc =
-// sum_k z_k^c V_ab(k) (one block), and q_lm = sum C_lm^abc M_abc with the
+// sum_k z_k^c V_ab(k) (one block per monomial), and q_lm = sum C_lm^abc M_abc with the
 // monomial coefficients of R_lm (host table from the same recurrence as
 // regular_solid).  Every sum runs in a fixed order.
 
-// Stage 1: thread (i, k) of chunk c sums rows j = c, c + JCH, ... < E
-// (interleaved, so both chunks stream the whole plane); T[c][k][b][i] with
-// row pitch TP.
-constexpr int kMomChunks = 2;
+// Stage 1: thread (i, k) of chunk c sums rows j = c, c + kMomChunks, ... < E
+// (interleaved chunks); T[c][k][b][i] with row pitch TP.
+constexpr int kMomChunks = 4;
 template <int LMAX>
 __global__ __launch_bounds__(256) void k_mom_rows(const double* __restrict__ rho, long long p0, long long p1, int n,
                                                   int g, double h, double y0, double* __restrict__ T, int TP) {
@@ -213,50 +212,37 @@ __global__ __launch_bounds__(256) void k_mom_cols(const double* __restrict__ T, 
   if (tid < NAB) V[(long long)k * NAB + tid] = (red[tid][0] + red[tid][1]) + (red[tid][2] + red[tid][3]);
 }
 
-// Stage 3: one block; thread t < NM owns monomial (a, b, c) = mono[t]
-// (packed a | b << 4 | c << 8) and sums over the planes; then thread q < nq
-// forms q_lm = sum of its terms coef * M[mono index] (+ point mass on q_00).
+// Stage 3: one block per monomial u = (a, b, c) (packed a | b << 4 | c << 8
+// in mono[u]): M_u = h^3 sum_k z_k^c V_ab(k), fixed-order block sum.
 template <int LMAX>
-__global__ __launch_bounds__(256) void k_mom_finish(const double* __restrict__ V, int n, double h, double z0,
-                                                    const int* __restrict__ mono, const int* __restrict__ toff,
-                                                    const int* __restrict__ tmono, const double* __restrict__ tcoef,
-                                                    double point_mass, double* __restrict__ q) {
+__global__ __launch_bounds__(256) void k_mom_z(const double* __restrict__ V, int n, double h, double z0,
+                                               const int* __restrict__ mono, double* __restrict__ M) {
   constexpr int NAB = (LMAX + 1) * (LMAX + 2) / 2;
-  constexpr int NM = (LMAX + 1) * (LMAX + 2) * (LMAX + 3) / 6;
-  constexpr int NQ = (LMAX + 1) * (LMAX + 1);
-  __shared__ double M[NM];
   const int E = n - 1;
+  const int u = blockIdx.x;
+  const int a = mono[u] & 15, b = (mono[u] >> 4) & 15, c = (mono[u] >> 8) & 15;
+  const int ab = a * (LMAX + 1) - a * (a - 1) / 2 + b;  // index of (a, b) in V's pair order
+  double s = 0.0;
+  for (int k = threadIdx.x; k < E; k += 256) {
+    const double z = z0 + k * h;
+    double zc = 1.0;
+    for (int e = 0; e < c; ++e) zc *= z;
+    s += zc * V[(long long)k * NAB + ab];
+  }
+  s = block_sum(s);
+  if (threadIdx.x == 0) M[u] = s * (h * h * h);
+}
+
+// Stage 4: thread q < nq forms q_lm = sum of its terms coef * M[monomial]
+// (+ point mass on q_00).
+__global__ __launch_bounds__(128) void k_mom_q(const double* __restrict__ M, int nq, const int* __restrict__ toff,
+                                               const int* __restrict__ tmono, const double* __restrict__ tcoef,
+                                               double point_mass, double* __restrict__ q) {
   const int t = threadIdx.x;
-  if (t < NM) {
-    const int a = mono[t] & 15, b = (mono[t] >> 4) & 15, c = (mono[t] >> 8) & 15;
-    // index of (a, b) in V's pair order
-    const int ab = a * (LMAX + 1) - a * (a - 1) / 2 + b;
-    double s0 = 0.0, s1 = 0.0;
-    int k = 0;
-    for (; k + 1 < E; k += 2) {
-      const double za = z0 + k * h, zb = za + h;
-      double pa = 1.0, pb = 1.0;
-      for (int u = 0; u < c; ++u) {
-        pa *= za;
-        pb *= zb;
-      }
-      s0 += pa * V[(long long)k * NAB + ab];
-      s1 += pb * V[(long long)(k + 1) * NAB + ab];
-    }
-    if (k < E) {
-      const double za = z0 + k * h;
-      double pa = 1.0;
-      for (int u = 0; u < c; ++u) pa *= za;
-      s0 += pa * V[(long long)k * NAB + ab];
-    }
-    M[t] = (s0 + s1) * (h * h * h);
-  }
-  __syncthreads();
-  if (t < NQ) {
-    double s = 0.0;
-    for (int e = toff[t]; e < toff[t + 1]; ++e) s += tcoef[e] * M[tmono[e]];
-    q[t] = s + (t == 0 ? point_mass : 0.0);
-  }
+  if (t >= nq) return;
+  double s = 0.0;
+  for (int e = toff[t]; e < toff[t + 1]; ++e) s += tcoef[e] * M[tmono[e]];
+  q[t] = s + (t == 0 ? point_mass : 0.0);
 }
 
 template <int LMAX, bool INNER>
@@ -490,7 +476,7 @@ size_t cart_moment_scratch(int n) {
   const int E = n - 1;
   const long long TP = (E + 63) / 64 * 64;
   return sizeof(double) * ((long long)kMomChunks * E * (kLmaxMax + 1) * TP +
-                           (long long)E * ((kLmaxMax + 1) * (kLmaxMax + 2) / 2));
+                           (long long)E * ((kLmaxMax + 1) * (kLmaxMax + 2) / 2) + kMonoMax);
 }
 
 void cart_moments(const double* rho, long long p0, long long p1, int n, int g, double h, double cx, double cy,
@@ -503,11 +489,15 @@ void cart_moments(const double* rho, long long p0, long long p1, int n, int g, d
   const int TP = (E + 63) / 64 * 64;
   double* T = scratch;
   double* V = scratch + (long long)kMomChunks * E * (kLmaxMax + 1) * TP;
+  double* M = V + (long long)E * ((kLmaxMax + 1) * (kLmaxMax + 2) / 2);
+  const int nq = (lmax + 1) * (lmax + 1);
+  const int nm = (lmax + 1) * (lmax + 2) * (lmax + 3) / 6;
   const dim3 g1((E + 63) / 64, (E + 3) / 4, kMomChunks), b1(64, 4);
 #define PSN_CALL(L)                                                                                     \
   k_mom_rows<L><<<g1, b1, 0, st>>>(rho, p0, p1, n, g, h, y0, T, TP);                                    \
   k_mom_cols<L><<<E, 256, 0, st>>>(T, TP, n, h, x0, V);                                                 \
-  k_mom_finish<L><<<1, 256, 0, st>>>(V, n, h, z0, tab.mono, tab.toff, tab.tmono, tab.tcoef, point_mass, q)
+  k_mom_z<L><<<nm, 256, 0, st>>>(V, n, h, z0, tab.mono, M);                                            \
+  k_mom_q<<<1, 128, 0, st>>>(M, nq, tab.toff, tab.tmono, tab.tcoef, point_mass, q)
   PSN_LMAX_SWITCH(lmax, PSN_CALL)
 #undef PSN_CALL
 }
