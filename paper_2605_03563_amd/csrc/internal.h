@@ -15,7 +15,6 @@ namespace psn {
 constexpr int kLmaxMax = 8;
 constexpr int kNqMax = (kLmaxMax + 1) * (kLmaxMax + 1);  // 81 real moments
 constexpr int kRowAlign = 32;       // compact rows padded to 32 elements
-constexpr int kMomBlocks = 1024;    // blocks of the moment kernels (partials per moment)
 
 // ---------------------------------------------------------------------------
 // Colour-split level layout.
@@ -188,8 +187,11 @@ size_t cart_moment_scratch(int n);
 void cart_moments(const double* rho, long long p0, long long p1, int n, int g, double h, double cx, double cy,
                   double cz, int lmax, const MomTables& tab, double point_mass, double* scratch, double* q,
                   hipStream_t st);
-void sph_moments(const double* rho, const SGeom& S, int lmax, bool inner, double* partial, hipStream_t st);
-void finish_moments(const double* partial, int nq, double point_mass, double* q, hipStream_t st);
+// q (outer, + point_mass on q_00) and qbar (inner) of the log-spherical
+// array rho by ray sums; scratch of sph_moment_scratch(nth, nph) bytes
+size_t sph_moment_scratch(int nth, int nph);
+void sph_moments(const double* rho, const SGeom& S, int lmax, double point_mass, double* scratch, double* q,
+                 double* qbar, hipStream_t st);
 void cart_ghosts(double* phi, long long p0, long long p1, int n, int g, double h, double lo, double cx,
                  double cy, double cz, int lmax, const double* q, double G, hipStream_t st);
 void sph_ghosts(double* phi, const SGeom& S, int lmax, const double* q, const double* qbar,

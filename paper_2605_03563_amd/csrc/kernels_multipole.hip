@@ -10,17 +10,15 @@
 // R_l0 = Q_l0, R_lm = sqrt2 Re Q_lm, R_l,-m = sqrt2 Im Q_lm (m > 0).
 // The irregular harmonics of the expansion, I_lm(x) = R_lm(x) / r^(2l+1),
 // are evaluated as R_lm(x / r^2) / r.  The moment sums are the per-node
-// quadrature of Eqs. outer_multipole / inner_multipole; each thread keeps all
-// (lmax+1)^2 accumulators in registers over a grid-stride loop, then a
-// fixed-order block and grid reduction makes the result deterministic.
+// quadrature of Eqs. outer_multipole / inner_multipole, computed by
+// separable sums (Cartesian: monomial moments; spherical: radial sums per
+// ray, then phi and theta), each in a fixed order.
 #include "internal.h"
 #include "reduce.h"
 
 namespace psn {
 
 namespace {
-
-constexpr int kMomThreads = 256;
 
 template <int LMAX>
 __device__ inline void regular_solid(double x, double y, double z, double w, double* __restrict__ acc) {
@@ -102,16 +100,6 @@ __device__ inline double dot_irregular(double x, double y, double z, const doubl
   const double r2 = x * x + y * y + z * z;
   const double ir2 = 1.0 / r2;
   return dot_regular<LMAX>(x * ir2, y * ir2, z * ir2, q) * sqrt(ir2);
-}
-
-template <int LMAX>
-__device__ inline void store_partials(double* acc, double* __restrict__ partial) {
-  constexpr int NQ = (LMAX + 1) * (LMAX + 1);
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) {
-    const double s = block_sum(acc[q]);
-    if (threadIdx.x == 0) partial[(long long)q * kMomBlocks + blockIdx.x] = s;
-  }
 }
 
 // ------------------------------------------------- Cartesian moments, separable
@@ -245,46 +233,132 @@ __global__ __launch_bounds__(128) void k_mom_q(const double* __restrict__ M, int
   q[t] = s + (t == 0 ? point_mass : 0.0);
 }
 
-template <int LMAX, bool INNER>
-__global__ __launch_bounds__(kMomThreads) void k_sph_moments(const double* __restrict__ rho, SGeom S,
-                                                             double* __restrict__ partial) {
-  constexpr int NQ = (LMAX + 1) * (LMAX + 1);
-  double acc[NQ];
+// ------------------------------------------------- spherical moments by rays
+// On a ray of direction n(theta_j, phi_k), R_lm(r n) = r^l R_lm(n), and with
+// the log-radius weight w = r^3 sin(theta) ds dtheta dphi the moments are
+//   q_lm  = dA sum_j sin(theta_j) sum_k R_lm(n_jk) sum_i rho_ijk r_i^(3+l),
+//   qb_lm = dA sum_j sin(theta_j) sum_k R_lm(n_jk) sum_i rho_ijk r_i^(2-l)
+// (inner: R_lm(x / r^2) / r).  R_lm(n) = A_l|m|(theta) c_m(phi) with c_m =
+// cos(m phi) (m >= 0) or sin(|m| phi) (m < 0) and A_l|m| = R_l|m| at phi = 0.
+// Stage 1: one wavefront per ray sums the 2 (lmax+1) radial powers (both
+// expansions in one read of rho); stage 2: one block per theta_j sums over
+// phi with c_m and applies sin(theta_j) A(theta_j); stage 3: one block per
+// moment sums over theta.  All sums in a fixed order.
+
+// Stage 1: S[ray][0..L] outer, S[ray][L+1..2L+1] inner, ray = k * nth + j.
+template <int LMAX>
+__global__ __launch_bounds__(256) void k_sph_rays(const double* __restrict__ rho, SGeom S, double* __restrict__ R) {
+  constexpr int NS = 2 * (LMAX + 1);
+  const int lane = threadIdx.x & 63;
+  const int ray = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (ray >= S.nth * S.nph) return;  // whole wavefronts leave together
+  const int j = ray % S.nth, k = ray / S.nth;
+  const double* __restrict__ row = rho + S.at(1, j, k);
+  double acc[NS];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-  const long long total = (long long)S.nr * S.nth * S.nph;
-  const double wang = S.ds * S.dth * S.dph;
-  for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
-       t += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(t % S.nr);
-    const int j = (int)((t / S.nr) % S.nth);
-    const int k = (int)(t / ((long long)S.nr * S.nth));
-    const double v = rho[S.at(i + 1, j, k)];
-    if (v == 0.0) continue;
+  for (int e = 0; e < NS; ++e) acc[e] = 0.0;
+  for (int i = lane; i < S.nr; i += 64) {
+    const double v = row[i];
     const double r = S.r_min * exp(i * S.ds);
-    const double th = (j + 0.5) * S.dth;
-    const double ph = k * S.dph;
-    const double st = sin(th);
-    const double w = r * r * r * st * wang * v;
-    const double x = r * st * cos(ph), y = r * st * sin(ph), z = r * cos(th);
-    if (INNER) {
-      const double ir2 = 1.0 / (r * r);
-      regular_solid<LMAX>(x * ir2, y * ir2, z * ir2, w / r, acc);
-    } else {
-      regular_solid<LMAX>(x, y, z, w, acc);
+    const double ir = 1.0 / r;
+    double po = v * r * r * r, pi = v * r * r;  // rho r^3, rho r^2
+#pragma unroll
+    for (int l = 0; l <= LMAX; ++l) {
+      acc[l] += po;
+      acc[LMAX + 1 + l] += pi;
+      po *= r;
+      pi *= ir;
     }
   }
-  store_partials<LMAX>(acc, partial);
+#pragma unroll
+  for (int e = 0; e < NS; ++e) {
+    const double t = wave_sum(acc[e]);
+    if (lane == 0) R[(long long)ray * NS + e] = t;
+  }
 }
 
-// one block per moment: fixed-order sum of its kMomBlocks partials
-__global__ __launch_bounds__(256) void k_finish_moments(const double* __restrict__ partial, double point_mass,
-                                                        double* __restrict__ q) {
-  const int c = blockIdx.x;
+// Stage 2: block j; thread t takes phi_k for k = t, t + 256, ...; G[j][2 NQ]
+// (outer then inner, index l^2 + l + m).
+template <int LMAX>
+__global__ __launch_bounds__(256) void k_sph_phi(const double* __restrict__ R, SGeom S, double* __restrict__ G) {
+  constexpr int NS = 2 * (LMAX + 1);
+  constexpr int NQ = (LMAX + 1) * (LMAX + 1);
+  __shared__ double red[2 * NQ][4];
+  __shared__ double A[NQ];
+  const int j = blockIdx.x;
+  const int tid = threadIdx.x;
+  const double th = (j + 0.5) * S.dth;
+  if (tid == 0) {
+    // R_lm at phi = 0: A_l|m| in the m >= 0 entries (the m < 0 entries vanish)
+    double a[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) a[q] = 0.0;
+    regular_solid<LMAX>(sin(th), 0.0, cos(th), 1.0, a);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) A[q] = a[q];
+  }
+  // one m at a time keeps the live partial sums to 4 (lmax + 1)
+#pragma unroll
+  for (int m = 0; m <= LMAX; ++m) {
+    double co[LMAX + 1], ci[LMAX + 1], so[LMAX + 1], si[LMAX + 1];
+#pragma unroll
+    for (int l = 0; l <= LMAX; ++l) co[l] = ci[l] = so[l] = si[l] = 0.0;
+    for (int k = tid; k < S.nph; k += 256) {
+      const double* __restrict__ s = R + ((long long)k * S.nth + j) * NS;
+      double sm, cm;
+      sincos(m * (k * S.dph), &sm, &cm);
+#pragma unroll
+      for (int l = m; l <= LMAX; ++l) {
+        const double vo = s[l], vi = s[LMAX + 1 + l];
+        co[l] += cm * vo;
+        ci[l] += cm * vi;
+        so[l] += sm * vo;
+        si[l] += sm * vi;
+      }
+    }
+#pragma unroll
+    for (int l = m; l <= LMAX; ++l) {
+      const int qc = l * l + l + m, qs = l * l + l - m;
+      const double a = wave_sum(co[l]), b = wave_sum(ci[l]);
+      if ((tid & 63) == 0) {
+        red[qc][tid >> 6] = a;
+        red[NQ + qc][tid >> 6] = b;
+      }
+      if (m > 0) {
+        const double c = wave_sum(so[l]), d = wave_sum(si[l]);
+        if ((tid & 63) == 0) {
+          red[qs][tid >> 6] = c;
+          red[NQ + qs][tid >> 6] = d;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const double st = sin(th);
+  for (int q = tid; q < 2 * NQ; q += 256) {
+    const int qq = q % NQ;
+    const int l = (int)sqrt((double)qq + 0.5);
+    const int m = qq - l * l - l;
+    const double a = A[l * l + l + (m < 0 ? -m : m)];
+    G[(long long)j * 2 * NQ + q] = st * a * ((red[q][0] + red[q][1]) + (red[q][2] + red[q][3]));
+  }
+}
+
+// Stage 3: block q sums G[j][q] over theta; q < NQ outer (+ point mass on
+// q_00), q >= NQ inner.
+__global__ __launch_bounds__(256) void k_sph_theta(const double* __restrict__ G, int nth, int nq, double dA,
+                                                   double point_mass, double* __restrict__ q_out,
+                                                   double* __restrict__ qb_out) {
+  const int q = blockIdx.x;
   double s = 0.0;
-  for (int b = threadIdx.x; b < kMomBlocks; b += blockDim.x) s += partial[(long long)c * kMomBlocks + b];
+  for (int j = threadIdx.x; j < nth; j += 256) s += G[(long long)j * 2 * nq + q];
   s = block_sum(s);
-  if (threadIdx.x == 0) q[c] = s + (c == 0 ? point_mass : 0.0);
+  if (threadIdx.x == 0) {
+    if (q < nq)
+      q_out[q] = dA * s + (q == 0 ? point_mass : 0.0);
+    else
+      qb_out[q - nq] = dA * s;
+  }
 }
 
 // Every ghost node of the Cartesian node array: z ghost planes, then y ghost
@@ -502,18 +576,23 @@ void cart_moments(const double* rho, long long p0, long long p1, int n, int g, d
 #undef PSN_CALL
 }
 
-void sph_moments(const double* rho, const SGeom& S, int lmax, bool inner, double* partial, hipStream_t st) {
-#define PSN_CALL(L)                                                                      \
-  if (inner)                                                                             \
-    k_sph_moments<L, true><<<kMomBlocks, kMomThreads, 0, st>>>(rho, S, partial);         \
-  else                                                                                   \
-    k_sph_moments<L, false><<<kMomBlocks, kMomThreads, 0, st>>>(rho, S, partial)
-  PSN_LMAX_SWITCH(lmax, PSN_CALL)
-#undef PSN_CALL
+size_t sph_moment_scratch(int nth, int nph) {
+  return sizeof(double) * ((long long)nth * nph * 2 * (kLmaxMax + 1) + (long long)nth * 2 * kNqMax);
 }
 
-void finish_moments(const double* partial, int nq, double point_mass, double* q, hipStream_t st) {
-  k_finish_moments<<<nq, 256, 0, st>>>(partial, point_mass, q);
+void sph_moments(const double* rho, const SGeom& S, int lmax, double point_mass, double* scratch, double* q,
+                 double* qbar, hipStream_t st) {
+  const int nq = (lmax + 1) * (lmax + 1);
+  double* R = scratch;
+  double* G = scratch + (long long)S.nth * S.nph * 2 * (kLmaxMax + 1);
+  const unsigned rays = (unsigned)S.nth * S.nph;
+  const double dA = S.ds * S.dth * S.dph;
+#define PSN_CALL(L)                                                      \
+  k_sph_rays<L><<<(rays + 3) / 4, 256, 0, st>>>(rho, S, R);             \
+  k_sph_phi<L><<<S.nth, 256, 0, st>>>(R, S, G);                          \
+  k_sph_theta<<<2 * nq, 256, 0, st>>>(G, S.nth, nq, dA, point_mass, q, qbar)
+  PSN_LMAX_SWITCH(lmax, PSN_CALL)
+#undef PSN_CALL
 }
 
 void cart_ghosts(double* phi, long long p0, long long p1, int n, int g, double h, double lo, double cx, double cy,

@@ -285,7 +285,7 @@ int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
 void carve(poisson_plan_s* P, Carver& cv) {
   const poisson_grid_t& g = P->grid;
   const poisson_opts_t& o = P->opts;
-  P->partial = (double*)cv.take(sizeof(double) * std::max<long long>(2 * kPartialCap, (long long)kNqMax * kMomBlocks));
+  P->partial = (double*)cv.take(sizeof(double) * 2 * kPartialCap);
   P->scal = (Scalars*)cv.take(sizeof(Scalars));
   P->qlm = (double*)cv.take(sizeof(double) * 2 * kNqMax);
   if (!P->sph) {
@@ -296,6 +296,7 @@ void carve(poisson_plan_s* P, Carver& cv) {
     P->mom_scratch = (double*)cv.take(cart_moment_scratch(g.n[0]));
   }
   if (P->sph) {
+    P->mom_scratch = (double*)cv.take(sph_moment_scratch(g.n[1], g.n[2]));
     const long long elems = g.pitch[1] * (long long)g.n[2];
     const size_t vb = sizeof(double) * elems;
     P->sc.cot = (const double*)cv.take(sizeof(double) * g.n[1]);
@@ -870,10 +871,7 @@ int do_multipole(poisson_plan_s* P, const double* rho, double* phi, int lmax, do
                  P->mom_scratch, P->qlm, st);
     cart_ghosts(phi, g.pitch[0], g.pitch[1], n, g.ghost, h, g.lo[0], cx, cy, cz, lmax, P->qlm, G, st);
   } else {
-    sph_moments(rho, P->S, lmax, false, P->partial, st);
-    finish_moments(P->partial, nq, P->opts.point_mass, P->qlm, st);
-    sph_moments(rho, P->S, lmax, true, P->partial, st);
-    finish_moments(P->partial, nq, 0.0, P->qlm + kNqMax, st);
+    sph_moments(rho, P->S, lmax, P->opts.point_mass, P->mom_scratch, P->qlm, P->qlm + kNqMax, st);
     sph_ghosts(phi, P->S, lmax, P->qlm, P->qlm + kNqMax, P->opts.point_mass, G, st);
   }
   CHK(launch_check("multipole_boundary"));

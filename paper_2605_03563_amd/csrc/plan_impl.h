@@ -71,7 +71,8 @@ struct poisson_plan_s {
   double* partial = nullptr;
   psn::Scalars* scal = nullptr;
   double* qlm = nullptr;  // 2 * kNqMax
-  // Cartesian moments: monomial tables and the separable sums' scratch
+  // multipole moments: monomial tables (Cartesian) and the scratch of the
+  // separable (Cartesian) or ray (spherical) sums
   int* mom_mono = nullptr;
   int* mom_toff = nullptr;
   int* mom_tmono = nullptr;
