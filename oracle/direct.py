@@ -144,11 +144,15 @@ def _sph_mode_matrix(m, nph, nth, nr, ds, th):
         cjp = 1.0 / dth ** 2 + cot[j] / (2 * dth)
         for i in range(nr):
             row = j * nr + i
-            diag = -2.0 / ds ** 2 - 2.0 / dth ** 2 + sphi
+            if isinstance(ds, (int, float)):
+                cl, cr = 1.0 / ds ** 2 - 1.0 / (2 * ds), 1.0 / ds ** 2 + 1.0 / (2 * ds)
+            else:
+                cl, cr = ds.cl[i], ds.cr[i]
+            diag = -(cl + cr) - 2.0 / dth ** 2 + sphi
             if i + 1 < nr:
-                add(row, row + 1, 1.0 / ds ** 2 + 1.0 / (2 * ds))
+                add(row, row + 1, cr)
             if i - 1 >= 0:
-                add(row, row - 1, 1.0 / ds ** 2 - 1.0 / (2 * ds))
+                add(row, row - 1, cl)
             if j + 1 < nth:
                 add(row, row + nr, cjp)
             else:
@@ -162,8 +166,9 @@ def _sph_mode_matrix(m, nph, nth, nr, ds, th):
 
 
 def solve_sph(phi_ghost, rho_nodes, r, ds, th, four_pi_G=1.0):
-    """Exact solution on the log-spherical grid; phi_ghost [nph][nth][nr+2]
-    carries the radial ghost values.  Returns the full array."""
+    """Exact solution on the spherical grid (ds: log spacing or a
+    radial.RadialMap); phi_ghost [nph][nth][nr+2] carries the radial ghost
+    values.  Returns the full array."""
     nph, nth, m2 = phi_ghost.shape
     nr = m2 - 2
     z = phi_ghost.copy()

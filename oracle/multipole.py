@@ -122,16 +122,23 @@ def cart_boundary(rho_nodes: np.ndarray, n: int, g: int, lmax: int, four_pi_G=1.
 
 
 def sph_boundary(rho_nodes: np.ndarray, nr, nth, nph, lmax, four_pi_G=1.0,
-                 point_mass=0.0, r_min=1e-3, r_max=1.0):
-    """Radial ghost shells of the log-spherical grid: outer expansion at
-    i = nr, inner expansion (+ central point mass) at i = -1.  rho_nodes has
-    shape [nph][nth][nr+2].  Returns (phi_array, q, qbar)."""
+                 point_mass=0.0, r_min=1e-3, r_max=1.0, rmap=None):
+    """Radial ghost shells of the spherical grid: outer expansion at i = nr,
+    inner expansion (+ central point mass) at i = -1.  rho_nodes has shape
+    [nph][nth][nr+2].  rmap: a radial.RadialMap (radii and radial volume
+    weights r^2 R'), else the log grid over r_min..r_max.  Returns
+    (phi_array, q, qbar)."""
     G = four_pi_G / (4 * math.pi)
     r, th, ph, ds = sph_axes(nr, nth, nph, r_min, r_max)
     dth, dph = math.pi / nth, 2 * math.pi / nph
+    if rmap is not None:
+        r = rmap.r
+        wr = rmap.w
+    else:
+        wr = r[1:nr + 1] ** 3 * ds
     ri = r[1:nr + 1]
     pts = sph_points(ri, th, ph).reshape(-1, 3)
-    w = (ri[None, None, :] ** 3) * ds * np.sin(th)[None, :, None] * dth * dph
+    w = wr[None, None, :] * np.sin(th)[None, :, None] * dth * dph
     rw = (rho_nodes[:, :, 1:nr + 1] * w).ravel()
     q = moments_outer(lmax, pts, rw)
     qbar = moments_inner(lmax, pts, rw)

@@ -69,8 +69,9 @@ def rhs_norm(u, f_nodes, n, h, order, g):
 # --------------------------------------------------------------------------
 # log-spherical
 # --------------------------------------------------------------------------
-def sph_apply(u: np.ndarray, ds: float, th: np.ndarray) -> np.ndarray:
-    """r^2-scaled Laplacian on the unknowns; u is [nph][nth][nr+2]."""
+def sph_apply(u: np.ndarray, ds, th: np.ndarray) -> np.ndarray:
+    """r^2-scaled Laplacian on the unknowns; u is [nph][nth][nr+2].  ds: the
+    log-grid spacing, or a radial.RadialMap (radial couplings cl, cr)."""
     nph, nth, m = u.shape
     nr = m - 2
     dth = math.pi / nth
@@ -78,7 +79,10 @@ def sph_apply(u: np.ndarray, ds: float, th: np.ndarray) -> np.ndarray:
     c = u[:, :, 1:nr + 1]
     up = u[:, :, 2:nr + 2]
     um = u[:, :, 0:nr]
-    out = (up - 2 * c + um) / ds ** 2 + (up - um) / (2 * ds)
+    if isinstance(ds, (int, float)):
+        out = (up - 2 * c + um) / ds ** 2 + (up - um) / (2 * ds)
+    else:
+        out = ds.cr[None, None, :] * up + ds.cl[None, None, :] * um - (ds.cl + ds.cr)[None, None, :] * c
     # colatitude neighbours, reflected across the poles with phi + pi
     half = nph // 2
     flip = np.roll(c, -half, axis=0)           # value at phi + pi
@@ -99,4 +103,5 @@ def sph_rhs(rho_nodes, r, four_pi_G=1.0):
 
 
 def sph_residual(u, rho_nodes, r, ds, th, four_pi_G=1.0):
+    """b - A u; ds as in sph_apply."""
     return sph_rhs(rho_nodes, r, four_pi_G) - sph_apply(u, ds, th)

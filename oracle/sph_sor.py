@@ -30,13 +30,21 @@ import numpy as np
 from . import operators as O
 
 
-def local_rjac(nr: int, nth: int, nph: int, ds: float, th: np.ndarray) -> np.ndarray:
-    """r_J at every colatitude (shape nth), Eq. local_rjac in s = ln r."""
+def local_rjac(nr: int, nth: int, nph: int, ds, th: np.ndarray) -> np.ndarray:
+    """r_J, Eq. local_rjac: at every colatitude (shape nth) on the log grid
+    (ds a float); on a mapped radial grid (ds a radial.RadialMap) the radial
+    weight r^2 / R'^2 = (cl + cr) / 2 varies with i and r_J has shape
+    [nth][nr]."""
     dth = math.pi / nth
     dph = 2.0 * math.pi / nph
-    wr = 1.0 / ds ** 2
-    wt = 1.0 / dth ** 2
-    wp = 1.0 / (np.sin(th) * dph) ** 2
+    if isinstance(ds, (int, float)):
+        wr = 1.0 / ds ** 2
+        wt = 1.0 / dth ** 2
+        wp = 1.0 / (np.sin(th) * dph) ** 2
+    else:
+        wr = ((ds.cl + ds.cr) / 2.0)[None, :]
+        wt = 1.0 / dth ** 2
+        wp = (1.0 / (np.sin(th) * dph) ** 2)[:, None]
     num = math.cos(math.pi / nr) * wr + math.cos(math.pi / nth) * wt + math.cos(math.pi / nph) * wp
     return num / (wr + wt + wp)
 
@@ -62,13 +70,16 @@ def colours(nr: int, nth: int, nph: int) -> np.ndarray:
 
 
 def diagonal(nr, nth, nph, ds, th) -> np.ndarray:
-    """Diagonal of the r^2-scaled operator per colatitude (shape nth)."""
+    """Diagonal of the r^2-scaled operator: per colatitude (shape nth) on the
+    log grid, [nth][nr] on a mapped radial grid."""
     dth = math.pi / nth
     dph = 2.0 * math.pi / nph
-    return -2.0 / ds ** 2 - 2.0 / dth ** 2 - 2.0 / (np.sin(th) * dph) ** 2
+    if isinstance(ds, (int, float)):
+        return -2.0 / ds ** 2 - 2.0 / dth ** 2 - 2.0 / (np.sin(th) * dph) ** 2
+    return (-(ds.cl + ds.cr)[None, :] - 2.0 / dth ** 2 - (2.0 / (np.sin(th) * dph) ** 2)[:, None])
 
 
-def colour_pass(u: np.ndarray, rho_nodes: np.ndarray, r: np.ndarray, ds: float, th: np.ndarray, colour: int,
+def colour_pass(u: np.ndarray, rho_nodes: np.ndarray, r: np.ndarray, ds, th: np.ndarray, colour: int,
                 omega_j: np.ndarray, four_pi_G: float = 1.0) -> np.ndarray:
     """Every unknown of `colour` becomes u + omega_j (u_GS - u), u_GS solving
     its own row of r^2 lap u = r^2 4 pi G rho for it (in place; the radial
@@ -77,9 +88,12 @@ def colour_pass(u: np.ndarray, rho_nodes: np.ndarray, r: np.ndarray, ds: float, 
     nr = m - 2
     col = colours(nr, nth, nph)
     res = O.sph_residual(u, rho_nodes, r, ds, th, four_pi_G)
-    d = diagonal(nr, nth, nph, ds, th)[None, :, None]
-    # u_GS = u + res / d (the residual with u itself, divided by the diagonal)
-    w = np.broadcast_to(np.asarray(omega_j, dtype=np.float64)[None, :, None], res.shape)
+    d = diagonal(nr, nth, nph, ds, th)
+    d = d[None, :, None] if d.ndim == 1 else d[None, :, :]
+    # u_GS = u + res / d (the residual with u itself, divided by the diagonal);
+    # omega per colatitude (log grid) or per colatitude and radius
+    om = np.asarray(omega_j, dtype=np.float64)
+    w = np.broadcast_to(om[None, :, None] if om.ndim == 1 else om[None, :, :], res.shape)
     upd = np.where(col == colour, w * res / d, 0.0)
     u[:, :, 1:nr + 1] += upd
     return u
