@@ -104,6 +104,22 @@ typedef struct {
                            order 6) or 3 (19-point star); spherical: 1 */
     int32_t pad_;
     int64_t pitch[2];   /* elements per row, elements per plane of caller arrays */
+    /* Spherical radial padding (Section 3.3; zero on Cartesian grids).  The
+       log core runs from r_in = lo[0] (first core unknown) to r_out = hi[0]
+       (last core unknown) with equal steps ds in ln r.  ext_out > 0: ext_out
+       more cells continue the log map outward (the last node is the outer
+       ghost).  ext_in > 0: ext_in cells continue inward along the quartic
+       Q(xi) = r_in (1 + ds xi + (ds xi)^2/2 + (ds xi)^3/6) + c4 xi^4 of the
+       map coordinate xi (xi = 0 at r_in), which matches the log map and its
+       first three derivatives at r_in and reaches r_pad at xi = -ext_in (the
+       inner ghost); it must increase monotonically.  n[0] counts every radial
+       unknown, pads included: n[0] = nlog + max(ext_in-1, 0) +
+       max(ext_out-1, 0) with nlog >= 2 core unknowns.  The operator is
+       discretised on the map coordinate (a u_xixi + b u_xi, a = (r/R')^2,
+       b = 2r/R' - r^2 R''/R'^3), the s = ln r form on the plain log grid. */
+    int32_t ext_in;
+    int32_t ext_out;
+    double  r_pad;
 } poisson_grid_t;
 
 typedef struct {

@@ -63,7 +63,11 @@ def cart_grid(n: int, ghost: int = 1, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1.0), pi
     return g
 
 
-def sph_grid(nr: int, nth: int, nph: int, r_min=1e-3, r_max=1.0, pitch_r: Optional[int] = None):
+def sph_grid(nr: int, nth: int, nph: int, r_min=1e-3, r_max=1.0, pitch_r: Optional[int] = None,
+             ext_in: int = 0, ext_out: int = 0, r_pad: float = 0.0):
+    """Spherical grid: nr radial unknowns (pads included), the log core from
+    r_min to r_max; ext_in / ext_out pad cells inside / outside it (the inner
+    pad ends at r_pad)."""
     pr = nr + 2 if pitch_r is None else pitch_r
     g = L.Grid()
     g.coord = SPHERICAL_LOG
@@ -72,6 +76,7 @@ def sph_grid(nr: int, nth: int, nph: int, r_min=1e-3, r_max=1.0, pitch_r: Option
     g.hi[:] = [r_max, math.pi, 2 * math.pi]
     g.ghost = 1
     g.pitch[:] = [pr, pr * nth]
+    g.ext_in, g.ext_out, g.r_pad = ext_in, ext_out, r_pad
     return g
 
 

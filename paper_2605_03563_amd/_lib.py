@@ -18,7 +18,8 @@ OMEGA_OPT, OMEGA_OPT_A, OMEGA_CHEBYSHEV, OMEGA_FIXED = 0, 1, 2, 3
 class Grid(C.Structure):
     _fields_ = [("coord", C.c_int32), ("n", C.c_int32 * 3), ("lo", C.c_double * 3),
                 ("hi", C.c_double * 3), ("ghost", C.c_int32), ("pad_", C.c_int32),
-                ("pitch", C.c_int64 * 2)]
+                ("pitch", C.c_int64 * 2), ("ext_in", C.c_int32), ("ext_out", C.c_int32),
+                ("r_pad", C.c_double)]
 
 
 class Opts(C.Structure):

@@ -62,7 +62,9 @@ struct SGeom {
   int nr, nth, nph;
   int pad_;
   long long p0, p1;   // row pitch (>= nr + 2), plane pitch (>= nth * p0)
-  double ds, dth, dph, r_min;
+  double ds, dth, dph, r_min;  // ds: log-core step in ln r; r_min: first unknown's radius
+  const double* rr;   // radius per radial index 0 .. nr+1 (ghosts at 0 and nr+1)
+  const double* rw;   // radial volume weight r^2 R' per radial index (unknowns)
   __host__ __device__ long long at(int i, int j, int k) const { return (long long)k * p1 + (long long)j * p0 + i; }
 };
 
@@ -198,16 +200,20 @@ void sph_ghosts(double* phi, const SGeom& S, int lmax, const double* q, const do
                 double point_mass, double G, hipStream_t st);
 
 // spherical operator and BiCGSTAB building blocks (FP64, natural layout)
-struct SphCoef { const double* cot; const double* isin2; const double* r2; };
+// cot: cot(theta_j)/(2 dtheta); isin2: 1/sin^2(theta_j); r2: r^2 per radial
+// index; rcl, rcr: radial couplings to i-1 and i+1 per radial index
+struct SphCoef { const double* cot; const double* isin2; const double* r2; const double* rcl; const double* rcr; };
+
 void sph_residual(const double* u, const double* rho, double* r, const SGeom& S, const SphCoef& c,
                   double four_pi_G, bool zero_unknowns_in, double* partial, hipStream_t st);
 void sph_apply(const double* u, double* out, const SGeom& S, const SphCoef& c, hipStream_t st);
 // one SOR colour pass (colours 0..3: parity + 2 in the second half turn) with
-// relaxation factor omega[j] per colatitude, and one step of the Chebyshev
-// sequence omega <- 1 / (1 - rj^2 omega / 4)
+// relaxation factor omega[j (nr+2) + i] per colatitude and radial index, and
+// one step of the Chebyshev sequence omega <- 1 / (1 - rj^2 omega / 4) over
+// n entries
 void sph_sor_pass(double* u, const double* rho, const SGeom& S, const SphCoef& c, double four_pi_G,
                   const double* omega, int colour, hipStream_t st);
-void sph_omega_next(double* omega, const double* rj, int nth, hipStream_t st);
+void sph_omega_next(double* omega, const double* rj, int n, hipStream_t st);
 // right-preconditioned BiCGSTAB: p = r + beta (p - omega v), phat = B^-1 p;
 // s = r - alpha v, shat = B^-1 s (B: red-black block lower triangle);
 // out = A xhat with dots (mode 0: w.out; mode 1: w.out and out.out);

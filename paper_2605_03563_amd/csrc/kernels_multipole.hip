@@ -235,10 +235,11 @@ __global__ __launch_bounds__(128) void k_mom_q(const double* __restrict__ M, int
 
 // ------------------------------------------------- spherical moments by rays
 // On a ray of direction n(theta_j, phi_k), R_lm(r n) = r^l R_lm(n), and with
-// the log-radius weight w = r^3 sin(theta) ds dtheta dphi the moments are
-//   q_lm  = dA sum_j sin(theta_j) sum_k R_lm(n_jk) sum_i rho_ijk r_i^(3+l),
-//   qb_lm = dA sum_j sin(theta_j) sum_k R_lm(n_jk) sum_i rho_ijk r_i^(2-l)
-// (inner: R_lm(x / r^2) / r).  R_lm(n) = A_l|m|(theta) c_m(phi) with c_m =
+// the volume weight w_i sin(theta) dtheta dphi (w_i = r^2 R' per unit of the
+// radial map coordinate; r^3 ds on the log grid) the moments are
+//   q_lm  = dA sum_j sin(theta_j) sum_k R_lm(n_jk) sum_i rho_ijk w_i r_i^l,
+//   qb_lm = dA sum_j sin(theta_j) sum_k R_lm(n_jk) sum_i rho_ijk w_i r_i^(-l-1)
+// (inner: R_lm(x / r^2) / r), dA = dtheta dphi.  R_lm(n) = A_l|m|(theta) c_m(phi) with c_m =
 // cos(m phi) (m >= 0) or sin(|m| phi) (m < 0) and A_l|m| = R_l|m| at phi = 0.
 // Stage 1: one wavefront per ray sums the 2 (lmax+1) radial powers (both
 // expansions in one read of rho); stage 2: one block per theta_j sums over
@@ -258,10 +259,10 @@ __global__ __launch_bounds__(256) void k_sph_rays(const double* __restrict__ rho
 #pragma unroll
   for (int e = 0; e < NS; ++e) acc[e] = 0.0;
   for (int i = lane; i < S.nr; i += 64) {
-    const double v = row[i];
-    const double r = S.r_min * exp(i * S.ds);
+    const double v = row[i] * S.rw[i + 1];
+    const double r = S.rr[i + 1];
     const double ir = 1.0 / r;
-    double po = v * r * r * r, pi = v * r * r;  // rho r^3, rho r^2
+    double po = v, pi = v * ir;  // rho w, rho w / r
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l) {
       acc[l] += po;
@@ -413,7 +414,7 @@ __global__ __launch_bounds__(256) void k_sph_ghosts(double* __restrict__ phi, SG
   const int u = outer ? t - per : t;
   const int j = u % S.nth, k = u / S.nth;
   const int i = outer ? S.nr + 1 : 0;
-  const double r = S.r_min * exp((i - 1) * S.ds);
+  const double r = S.rr[i];
   const double th = (j + 0.5) * S.dth, ph = k * S.dph;
   const double st = sin(th);
   const double x = r * st * cos(ph), y = r * st * sin(ph), z = r * cos(th);
@@ -586,7 +587,7 @@ void sph_moments(const double* rho, const SGeom& S, int lmax, double point_mass,
   double* R = scratch;
   double* G = scratch + (long long)S.nth * S.nph * 2 * (kLmaxMax + 1);
   const unsigned rays = (unsigned)S.nth * S.nph;
-  const double dA = S.ds * S.dth * S.dph;
+  const double dA = S.dth * S.dph;
 #define PSN_CALL(L)                                                      \
   k_sph_rays<L><<<(rays + 3) / 4, 256, 0, st>>>(rho, S, R);             \
   k_sph_phi<L><<<S.nth, 256, 0, st>>>(R, S, G);                          \

@@ -1,8 +1,10 @@
-// Log-spherical Poisson operator (Eq. 2 multiplied by r^2, s = ln r) and the
-// fused BiCGSTAB kernels (Section 2.1.2: BiCGSTAB for the non-symmetric
-// direct finite-difference spherical Laplacian) for gfx950, FP64.
-//   r^2 lap u = u_ss + u_s + u_tt + cot(t) u_t + u_pp / sin^2(t)
-// with 2nd-order central differences; radial ghosts hold Dirichlet values,
+// Spherical Poisson operator (Eq. 2 multiplied by r^2) and the fused
+// BiCGSTAB kernels (Section 2.1.2: BiCGSTAB for the non-symmetric direct
+// finite-difference spherical Laplacian) for gfx950, FP64.
+//   r^2 lap u = a u_xixi + b u_xi + u_tt + cot(t) u_t + u_pp / sin^2(t)
+// on the radial map coordinate xi (a = 1/ds^2, b = 1/ds on the log grid,
+// i.e. u_ss + u_s), with 2nd-order central differences: the radial couplings
+// cl = a - b/2, cr = a + b/2 come per radial index from tables; radial ghosts hold Dirichlet values,
 // the colatitude neighbour past a pole is the node at phi + pi, phi is
 // periodic.  Direction vectors keep zero radial ghosts.
 #include "internal.h"
@@ -15,7 +17,9 @@ namespace {
 constexpr int BX = 64, BY = 4;
 
 struct Coef {
-  double ids2, i2ds, idt2, idp2;
+  double idt2, idp2;
+  const double* rcl;  // radial couplings per radial index
+  const double* rcr;
 };
 
 inline dim3 sgrid(const SGeom& S) { return dim3((S.nr + BX - 1) / BX, (S.nth + BY - 1) / BY, S.nph); }
@@ -30,8 +34,8 @@ __device__ inline double sph_op(const F& V, const SGeom& S, const Coef& c, const
   const double jp = (j + 1 < S.nth) ? V(i, j + 1, k) : V(i, S.nth - 1, (k + half) % S.nph);
   const double jm = (j > 0) ? V(i, j - 1, k) : V(i, 0, (k + half) % S.nph);
   const double kp = V(i, j, (k + 1) % S.nph), km = V(i, j, (k + S.nph - 1) % S.nph);
-  return (ip - 2.0 * u + im) * c.ids2 + (ip - im) * c.i2ds + (jp - 2.0 * u + jm) * c.idt2 + cot2[j] * (jp - jm) +
-         (kp - 2.0 * u + km) * isin2[j] * c.idp2;
+  return c.rcr[i] * ip + c.rcl[i] * im - (c.rcl[i] + c.rcr[i]) * u + (jp - 2.0 * u + jm) * c.idt2 +
+         cot2[j] * (jp - jm) + (kp - 2.0 * u + km) * isin2[j] * c.idp2;
 }
 
 __device__ inline bool active(const SGeom& S, int i, int j, int k) {
@@ -92,14 +96,14 @@ __global__ __launch_bounds__(256) void k_sph_sor(double* __restrict__ U, const d
   auto V = [&](int ii, int jj, int kk) -> double { return U[S.at(ii, jj, kk)]; };
   const long long idx = S.at(i, j, k);
   const double res = fpg * r2[i] * rho[idx] - sph_op(V, S, c, cot2, isin2, i, j, k);
-  const double d = -2.0 * c.ids2 - 2.0 * c.idt2 - 2.0 * isin2[j] * c.idp2;
-  U[idx] += omega[j] * res / d;
+  const double d = -(c.rcl[i] + c.rcr[i]) - 2.0 * c.idt2 - 2.0 * isin2[j] * c.idp2;
+  U[idx] += omega[(long long)j * (S.nr + 2) + i] * res / d;
 }
 
-// next term of the relaxation sequence at every colatitude (Eq. omega_n)
-__global__ void k_sph_omega(double* __restrict__ omega, const double* __restrict__ rj, int nth) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < nth) omega[j] = 1.0 / (1.0 - rj[j] * rj[j] * omega[j] / 4.0);
+// next term of the relaxation sequence at every node of the table (Eq. omega_n)
+__global__ void k_sph_omega(double* __restrict__ omega, const double* __restrict__ rj, int n) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) omega[e] = 1.0 / (1.0 - rj[e] * rj[e] * omega[e] / 4.0);
 }
 
 // Right-preconditioned BiCGSTAB (Section 2.1.2: a multi-colour Gauss-Seidel
@@ -110,8 +114,8 @@ __global__ void k_sph_omega(double* __restrict__ omega, const double* __restrict
 // even) are left out of B.  scal->v: 0 rho, 1 alpha, 2 omega, 3 beta,
 // 4 rhat.v, 5 t.s, 6 t.t, 7 r.r.
 
-__device__ inline double sph_diag(const SGeom& S, const Coef& c, const double* __restrict__ isin2, int j) {
-  return -2.0 * c.ids2 - 2.0 * c.idt2 - 2.0 * isin2[j] * c.idp2;
+__device__ inline double sph_diag(const Coef& c, const double* __restrict__ isin2, int i, int j) {
+  return -(c.rcl[i] + c.rcr[i]) - 2.0 * c.idt2 - 2.0 * isin2[j] * c.idp2;
 }
 
 __device__ inline bool is_red(int i, int j, int k) { return ((i + j + k) & 1) == 0; }
@@ -129,7 +133,7 @@ __global__ __launch_bounds__(256) void k_pbicg_p(const double* __restrict__ R, d
   const long long idx = S.at(i, j, k);
   const double pv = R[idx] + beta * (P[idx] - omega * Vv[idx]);
   P[idx] = pv;
-  if (Ph && is_red(i, j, k)) Ph[idx] = pv / sph_diag(S, c, isin2, j);
+  if (Ph && is_red(i, j, k)) Ph[idx] = pv / sph_diag(c, isin2, i, j);
 }
 
 // s = r - alpha v;   shat = s / D on red nodes
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(256) void k_pbicg_s(const double* __restrict__ R, c
   const long long idx = S.at(i, j, k);
   const double sv = R[idx] - scal->v[1] * Vv[idx];
   Sv[idx] = sv;
-  if (Sh && is_red(i, j, k)) Sh[idx] = sv / sph_diag(S, c, isin2, j);
+  if (Sh && is_red(i, j, k)) Sh[idx] = sv / sph_diag(c, isin2, i, j);
 }
 
 // black nodes of xhat = B^-1 y: (y - sum over red neighbours of a_n xhat_n) / D
@@ -158,15 +162,14 @@ __global__ __launch_bounds__(256) void k_gs_black(const double* __restrict__ Y, 
   const int half = S.nph >> 1;
   // value of a neighbour if it is red, else 0 (radial ghosts of xhat are 0)
   auto red = [&](int ii, int jj, int kk) -> double { return is_red(ii, jj, kk) ? Xh[S.at(ii, jj, kk)] : 0.0; };
-  const double cr = c.ids2 + c.i2ds, cl = c.ids2 - c.i2ds;
-  double s = cr * red(i + 1, j, k) + cl * red(i - 1, j, k);
+  double s = c.rcr[i] * red(i + 1, j, k) + c.rcl[i] * red(i - 1, j, k);
   const double cjp = c.idt2 + cot2[j], cjm = c.idt2 - cot2[j];
   s += cjp * ((j + 1 < S.nth) ? red(i, j + 1, k) : red(i, S.nth - 1, (k + half) % S.nph));
   s += cjm * ((j > 0) ? red(i, j - 1, k) : red(i, 0, (k + half) % S.nph));
   const double cp = isin2[j] * c.idp2;
   s += cp * (red(i, j, (k + 1) % S.nph) + red(i, j, (k + S.nph - 1) % S.nph));
   const long long idx = S.at(i, j, k);
-  Xh[idx] = (Y[idx] - s) / sph_diag(S, c, isin2, j);
+  Xh[idx] = (Y[idx] - s) / sph_diag(c, isin2, i, j);
 }
 
 // out = A xhat with dots: mode 0: partial0 += a.out (a = rhat);
@@ -415,12 +418,12 @@ __global__ __launch_bounds__(256) void k_scast_out(SLev L, double* __restrict__ 
 
 inline dim3 lgrid(const SLev& L) { return dim3((L.nr + BX - 1) / BX, (L.nth + BY - 1) / BY, L.nph); }
 
-Coef make_coef(const SGeom& S) {
+Coef make_coef(const SGeom& S, const SphCoef& sc) {
   Coef c;
-  c.ids2 = 1.0 / (S.ds * S.ds);
-  c.i2ds = 1.0 / (2.0 * S.ds);
   c.idt2 = 1.0 / (S.dth * S.dth);
   c.idp2 = 1.0 / (S.dph * S.dph);
+  c.rcl = sc.rcl;
+  c.rcr = sc.rcr;
   return c;
 }
 
@@ -433,7 +436,7 @@ int sph_blocks(const SGeom& S) {
 
 void sph_residual(const double* u, const double* rho, double* r, const SGeom& S, const SphCoef& c,
                   double four_pi_G, bool zu, double* partial, hipStream_t st) {
-  const Coef cf = make_coef(S);
+  const Coef cf = make_coef(S, c);
   if (zu)
     k_sph_residual<true><<<sgrid(S), dim3(BX, BY), 0, st>>>(u, rho, r, S, cf, c.cot, c.isin2, c.r2, four_pi_G,
                                                            partial);
@@ -443,36 +446,36 @@ void sph_residual(const double* u, const double* rho, double* r, const SGeom& S,
 }
 
 void sph_apply(const double* u, double* out, const SGeom& S, const SphCoef& c, hipStream_t st) {
-  k_sph_apply<<<sgrid(S), dim3(BX, BY), 0, st>>>(u, out, S, make_coef(S), c.cot, c.isin2);
+  k_sph_apply<<<sgrid(S), dim3(BX, BY), 0, st>>>(u, out, S, make_coef(S, c), c.cot, c.isin2);
 }
 
 void pbicg_direction(const double* r, double* p, const double* v, double* phat, const SGeom& S, const SphCoef& c,
                      const Scalars* scal, hipStream_t st) {
-  const Coef cf = make_coef(S);
+  const Coef cf = make_coef(S, c);
   k_pbicg_p<<<sgrid(S), dim3(BX, BY), 0, st>>>(r, p, v, phat, S, cf, c.isin2, scal);
   k_gs_black<<<sgrid(S), dim3(BX, BY), 0, st>>>(p, phat, S, cf, c.cot, c.isin2);
 }
 
 void pbicg_update_p(const double* r, double* p, const double* v, const SGeom& S, const SphCoef& c,
                     const Scalars* scal, hipStream_t st) {
-  k_pbicg_p<<<sgrid(S), dim3(BX, BY), 0, st>>>(r, p, v, nullptr, S, make_coef(S), c.isin2, scal);
+  k_pbicg_p<<<sgrid(S), dim3(BX, BY), 0, st>>>(r, p, v, nullptr, S, make_coef(S, c), c.isin2, scal);
 }
 
 void pbicg_update_s(const double* r, const double* v, double* s, const SGeom& S, const SphCoef& c,
                     const Scalars* scal, hipStream_t st) {
-  k_pbicg_s<<<sgrid(S), dim3(BX, BY), 0, st>>>(r, v, s, nullptr, S, make_coef(S), c.isin2, scal);
+  k_pbicg_s<<<sgrid(S), dim3(BX, BY), 0, st>>>(r, v, s, nullptr, S, make_coef(S, c), c.isin2, scal);
 }
 
 void pbicg_s(const double* r, const double* v, double* s, double* shat, const SGeom& S, const SphCoef& c,
              const Scalars* scal, hipStream_t st) {
-  const Coef cf = make_coef(S);
+  const Coef cf = make_coef(S, c);
   k_pbicg_s<<<sgrid(S), dim3(BX, BY), 0, st>>>(r, v, s, shat, S, cf, c.isin2, scal);
   k_gs_black<<<sgrid(S), dim3(BX, BY), 0, st>>>(s, shat, S, cf, c.cot, c.isin2);
 }
 
 void pbicg_apply(const double* xhat, double* out, const double* w, int mode, const SGeom& S, const SphCoef& c,
                  double* partial, hipStream_t st) {
-  const Coef cf = make_coef(S);
+  const Coef cf = make_coef(S, c);
   if (mode == 0)
     k_apply_dot<0><<<sgrid(S), dim3(BX, BY), 0, st>>>(xhat, out, w, S, cf, c.cot, c.isin2, partial);
   else
@@ -515,11 +518,11 @@ void sph_cast_out(const SLev& L0, double* x, const SGeom& S, hipStream_t st) {
 void sph_sor_pass(double* u, const double* rho, const SGeom& S, const SphCoef& c, double four_pi_G,
                   const double* omega, int colour, hipStream_t st) {
   const dim3 g((S.nr + BX - 1) / BX, (S.nth + BY - 1) / BY, S.nph / 2);
-  k_sph_sor<<<g, dim3(BX, BY), 0, st>>>(u, rho, S, make_coef(S), c.cot, c.isin2, c.r2, four_pi_G, omega, colour);
+  k_sph_sor<<<g, dim3(BX, BY), 0, st>>>(u, rho, S, make_coef(S, c), c.cot, c.isin2, c.r2, four_pi_G, omega, colour);
 }
 
-void sph_omega_next(double* omega, const double* rj, int nth, hipStream_t st) {
-  k_sph_omega<<<(nth + 255) / 256, 256, 0, st>>>(omega, rj, nth);
+void sph_omega_next(double* omega, const double* rj, int n, hipStream_t st) {
+  k_sph_omega<<<(n + 255) / 256, 256, 0, st>>>(omega, rj, n);
 }
 
 void sph_fill_zero(double* x, const SGeom& S, hipStream_t st) {

@@ -111,6 +111,68 @@ bool line_split(int nph, int* seg, int* nseg, int* nl) {
   return true;
 }
 
+// Radial nodes of the spherical grid (Section 3.3).  Radial index a = 0 ..
+// nr+1 (a = 0 and nr+1 the ghosts) sits at map coordinate xi = a - 1 - p,
+// p = max(ext_in - 1, 0) inner pad unknowns; the log core r_in e^(xi ds)
+// covers xi = 0 .. nlog-1 and continues outward; with an inner pad, xi < 0
+// follows the quartic Q(xi) that matches the log map's value and first
+// three derivatives at xi = 0 and reaches r_pad at xi = -ext_in.  The
+// operator on the map coordinate is a u_xixi + b u_xi with a = (r/R')^2,
+// b = 2r/R' - r^2 R''/R'^3, i.e. couplings cl = a - b/2, cr = a + b/2; the
+// radial volume weight is r^2 R'.
+bool sph_radial_map(const poisson_grid_t& g, std::vector<double>& r, std::vector<double>& cl,
+                    std::vector<double>& cr, std::vector<double>& w, double& ds) {
+  const int nr = g.n[0];
+  const int ein = g.ext_in, eout = g.ext_out;
+  const int p = ein > 0 ? ein - 1 : 0, q = eout > 0 ? eout - 1 : 0;
+  const int nlog = nr - p - q;
+  if (nlog < 2 || ein < 0 || eout < 0) return false;
+  const double rin = g.lo[0];
+  ds = log(g.hi[0] / rin) / (nlog - 1);
+  double c4 = 0.0;
+  if (ein > 0) {
+    const double E = ein, x = ds * E;
+    c4 = (g.r_pad - rin * (1.0 - x + x * x / 2.0 - x * x * x / 6.0)) / (E * E * E * E);
+  }
+  auto eval = [&](double xi, double& R, double& R1, double& R2) {
+    if (ein > 0 && xi < 0.0) {
+      const double d = ds, x = d * xi;
+      R = rin * (1.0 + x + x * x / 2.0 + x * x * x / 6.0) + c4 * xi * xi * xi * xi;
+      R1 = rin * d * (1.0 + x + x * x / 2.0) + 4.0 * c4 * xi * xi * xi;
+      R2 = rin * d * d * (1.0 + x) + 12.0 * c4 * xi * xi;
+    } else {
+      R = rin * exp(xi * ds);
+      R1 = ds * R;
+      R2 = ds * ds * R;
+    }
+  };
+  if (ein > 0) {
+    // the pad must map monotonically (R' > 0 on [-ext_in, 0])
+    for (int t = 0; t <= 2000; ++t) {
+      double R, R1, R2;
+      eval(-ein + ein * (t / 2000.0), R, R1, R2);
+      if (!(R1 > 0.0) || !(R > 0.0)) return false;
+    }
+  }
+  r.assign(nr + 2, 0.0);
+  cl.assign(nr + 2, 0.0);
+  cr.assign(nr + 2, 0.0);
+  w.assign(nr + 2, 0.0);
+  for (int a = 0; a < nr + 2; ++a) {
+    double R, R1, R2;
+    eval((double)(a - 1 - p), R, R1, R2);
+    r[a] = R;
+    if (a >= 1 && a <= nr) {
+      const double aa = (R / R1) * (R / R1);
+      const double bb = 2.0 * R / R1 - R * R * R2 / (R1 * R1 * R1);
+      cl[a] = aa - 0.5 * bb;
+      cr[a] = aa + 0.5 * bb;
+      w[a] = R * R * R1;
+    }
+  }
+  return true;
+}
+
 int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
   if (!g || !o) {
     set_error("null grid or options");
@@ -176,6 +238,26 @@ int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
       set_error("spherical grid needs 0 < r_min < r_max");
       return POISSON_EGRID;
     }
+    if (g->ext_in < 0 || g->ext_out < 0) {
+      set_error("radial pads need ext_in, ext_out >= 0");
+      return POISSON_EGRID;
+    }
+    if (g->ext_in > 0 && !(g->r_pad > 0.0 && g->r_pad < g->lo[0])) {
+      set_error("an inner pad needs 0 < r_pad < r_in");
+      return POISSON_EGRID;
+    }
+    {
+      std::vector<double> r, cl, cr, w;
+      double ds;
+      if (!sph_radial_map(*g, r, cl, cr, w, ds)) {
+        set_error("radial pads leave fewer than two log-core unknowns or a non-monotone inner pad");
+        return POISSON_EGRID;
+      }
+    }
+    if ((g->ext_in > 0 || g->ext_out > 0) && o->method == POISSON_BICGSTAB_MG32) {
+      set_error("the FP32 multigrid preconditioner is built for the plain log grid (no radial pads)");
+      return POISSON_EINVAL;
+    }
     if (g->pitch[0] < g->n[0] + 2 || g->pitch[1] < (int64_t)g->n[1] * g->pitch[0]) {
       set_error("pitch too small for the spherical grid");
       return POISSON_EINVAL;
@@ -205,6 +287,10 @@ int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
   }
   if (n < 2) {
     set_error("need at least 2 intervals");
+    return POISSON_EGRID;
+  }
+  if (g->ext_in != 0 || g->ext_out != 0) {
+    set_error("radial pads belong to spherical grids");
     return POISSON_EGRID;
   }
   const double h = (g->hi[0] - g->lo[0]) / n;
@@ -302,6 +388,10 @@ void carve(poisson_plan_s* P, Carver& cv) {
     P->sc.cot = (const double*)cv.take(sizeof(double) * g.n[1]);
     P->sc.isin2 = (const double*)cv.take(sizeof(double) * g.n[1]);
     P->sc.r2 = (const double*)cv.take(sizeof(double) * (g.n[0] + 2));
+    P->sc.rcl = (const double*)cv.take(sizeof(double) * (g.n[0] + 2));
+    P->sc.rcr = (const double*)cv.take(sizeof(double) * (g.n[0] + 2));
+    P->S.rr = (const double*)cv.take(sizeof(double) * (g.n[0] + 2));
+    P->S.rw = (const double*)cv.take(sizeof(double) * (g.n[0] + 2));
     P->sr = (double*)cv.take(vb);
     P->srh = (double*)cv.take(vb);
     for (int i = 0; i < 2; ++i) {
@@ -311,8 +401,10 @@ void carve(poisson_plan_s* P, Carver& cv) {
     P->ss = (double*)cv.take(vb);
     P->stt = (double*)cv.take(vb);
     if (o.method == POISSON_SOR) {
-      P->somega = (double*)cv.take(sizeof(double) * g.n[1]);
-      P->srj = (double*)cv.take(sizeof(double) * g.n[1]);
+      // relaxation factors and local spectral radii per colatitude and radial index
+      const size_t nrel = (size_t)g.n[1] * (g.n[0] + 2);
+      P->somega = (double*)cv.take(sizeof(double) * nrel);
+      P->srj = (double*)cv.take(sizeof(double) * nrel);
     }
     P->slv.clear();
     if (o.method == POISSON_BICGSTAB_MG32) {
@@ -1100,8 +1192,8 @@ int solve_cart(poisson_plan_s* P, const double* rho, double* phi, double tol, po
 }
 
 // ------------------------------------------------------------ spherical solve
-// SOR on the log-spherical grid (Section 2.1.1): red half-sweep (colours 0,
-// 2), then black (1, 3); the relaxation factors are per colatitude -- the
+// SOR on the spherical grid (Section 2.1.1): red half-sweep (colours 0,
+// 2), then black (1, 3); the relaxation factors are per colatitude and radius -- the
 // local omega_opt of Eqs. omega_final and local_rjac, the local Chebyshev
 // sequence of Eq. omega_n from n = 1 advanced after every half-sweep, or a
 // fixed omega.
@@ -1129,7 +1221,7 @@ void sph_sor_sweep(poisson_plan_s* P, const double* rho, double* phi, hipStream_
   for (int half = 0; half < 2; ++half) {
     sph_sor_pass(phi, rho, P->S, P->sc, P->opts.four_pi_G, P->somega, half, st);
     sph_sor_pass(phi, rho, P->S, P->sc, P->opts.four_pi_G, P->somega, half + 2, st);
-    if (cheb) sph_omega_next(P->somega, P->srj, P->S.nth, st);
+    if (cheb) sph_omega_next(P->somega, P->srj, P->S.nth * (P->S.nr + 2), st);
   }
 }
 
@@ -1412,8 +1504,12 @@ int poisson_plan(poisson_plan_t* out, const poisson_grid_t* grid, const poisson_
     S.nph = g.n[2];
     S.p0 = g.pitch[0];
     S.p1 = g.pitch[1];
-    S.r_min = g.lo[0];
-    S.ds = log(g.hi[0] / g.lo[0]) / (S.nr - 1);
+    std::vector<double> rr, rcl, rcr, rw;
+    if (!sph_radial_map(g, rr, rcl, rcr, rw, S.ds)) {
+      set_error("invalid radial map");
+      return fail(POISSON_EGRID);
+    }
+    S.r_min = rr[1];
     S.dth = M_PI / S.nth;
     S.dph = 2.0 * M_PI / S.nph;
     std::vector<double> cot(S.nth), isin2(S.nth), r2(S.nr + 2);
@@ -1422,9 +1518,15 @@ int poisson_plan(poisson_plan_t* out, const poisson_grid_t* grid, const poisson_
       cot[j] = cos(th) / sin(th) / (2.0 * S.dth);
       isin2[j] = 1.0 / (sin(th) * sin(th));
     }
-    for (int i = 0; i < S.nr + 2; ++i) {
-      const double r = S.r_min * exp((i - 1) * S.ds);
-      r2[i] = r * r;
+    for (int i = 0; i < S.nr + 2; ++i) r2[i] = rr[i] * rr[i];
+    const size_t rb = sizeof(double) * (S.nr + 2);
+    if (hipMemcpyAsync((void*)P->sc.rcl, rcl.data(), rb, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync((void*)P->sc.rcr, rcr.data(), rb, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync((void*)S.rr, rr.data(), rb, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync((void*)S.rw, rw.data(), rb, hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+      set_error("upload of the radial tables failed");
+      return fail(POISSON_EHIP);
     }
     if (hipMemcpyAsync((void*)P->sc.cot, cot.data(), sizeof(double) * S.nth, hipMemcpyHostToDevice, st) != hipSuccess ||
         hipMemcpyAsync((void*)P->sc.isin2, isin2.data(), sizeof(double) * S.nth, hipMemcpyHostToDevice, st) !=
@@ -1435,16 +1537,23 @@ int poisson_plan(poisson_plan_t* out, const poisson_grid_t* grid, const poisson_
       return fail(POISSON_EHIP);
     }
     if (P->srj) {
-      // Eq. local_rjac in s = ln r: the weights ds^-2, dtheta^-2,
-      // (sin(theta) dphi)^-2 are the metric ones times r^2, so r cancels
-      std::vector<double> rj(S.nth);
+      // Eq. local_rjac: the weights (dr)^-2, (r dtheta)^-2, (r sin(theta)
+      // dphi)^-2 times r^2 are the operator's diagonal couplings a_i =
+      // (cl + cr)/2 (ds^-2 on the log grid, where r_J depends on theta only),
+      // dtheta^-2 and (sin(theta) dphi)^-2; one entry per (j, radial index)
+      const int ni = S.nr + 2;
+      std::vector<double> rj((size_t)S.nth * ni, 0.0);
       for (int j = 0; j < S.nth; ++j) {
         const double th = (j + 0.5) * S.dth;
-        const double wr = 1.0 / (S.ds * S.ds), wt = 1.0 / (S.dth * S.dth);
+        const double wt = 1.0 / (S.dth * S.dth);
         const double wp = 1.0 / (sin(th) * sin(th) * S.dph * S.dph);
-        rj[j] = (cos(M_PI / S.nr) * wr + cos(M_PI / S.nth) * wt + cos(M_PI / S.nph) * wp) / (wr + wt + wp);
+        for (int i = 1; i <= S.nr; ++i) {
+          const double wr = 0.5 * (rcl[i] + rcr[i]);
+          rj[(size_t)j * ni + i] =
+              (cos(M_PI / S.nr) * wr + cos(M_PI / S.nth) * wt + cos(M_PI / S.nph) * wp) / (wr + wt + wp);
+        }
       }
-      if (hipMemcpyAsync(P->srj, rj.data(), sizeof(double) * S.nth, hipMemcpyHostToDevice, st) != hipSuccess ||
+      if (hipMemcpyAsync(P->srj, rj.data(), sizeof(double) * rj.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess) {
         set_error("upload of the local spectral radii failed");
         return fail(POISSON_EHIP);

@@ -35,7 +35,7 @@ def test_library_exports_every_declared_function():
 
 
 def test_struct_layouts_match_header_sizes():
-    assert C.sizeof(L.Grid) == 4 + 12 + 24 + 24 + 4 + 4 + 16
+    assert C.sizeof(L.Grid) == 4 + 12 + 24 + 24 + 4 + 4 + 16 + 4 + 4 + 8
     assert C.sizeof(L.Opts) == 10 * 4 + 4 * 8
     assert C.sizeof(L.Stats) == 8 + 5 * 8 + 8 + 8
 
@@ -182,3 +182,25 @@ def test_spai_order_and_ghost_validation():
                                        C.byref(pg.options("mg", order=6))) > 0
     assert lib.poisson_workspace_bytes(C.byref(pg.cart_grid(32)),
                                        C.byref(pg.options("mg_spai", order=8))) == 0
+
+
+def test_radial_pad_validation():
+    """Pads belong to spherical grids; the inner pad needs 0 < r_pad < r_in and
+    a monotone quartic; at least two log-core unknowns remain; the FP32
+    multigrid preconditioner takes plain log grids only."""
+    lib = L.load()
+    ok = pg.sph_grid(60, 8, 16, 0.5, 1.0, ext_in=8, ext_out=6, r_pad=0.3)
+    assert lib.poisson_workspace_bytes(C.byref(ok), C.byref(pg.options("bicgstab"))) > 0
+    assert lib.poisson_workspace_bytes(C.byref(ok), C.byref(pg.options("sor"))) > 0
+    assert lib.poisson_workspace_bytes(C.byref(ok), C.byref(pg.options("bicgstab_mg32"))) == 0
+    bad_pad = pg.sph_grid(60, 8, 16, 0.5, 1.0, ext_in=8, r_pad=0.6)
+    assert lib.poisson_workspace_bytes(C.byref(bad_pad), C.byref(pg.options("bicgstab"))) == 0
+    assert b"r_pad" in lib.poisson_last_error()
+    too_few = pg.sph_grid(12, 8, 16, 0.5, 1.0, ext_in=8, ext_out=6, r_pad=0.3)
+    assert lib.poisson_workspace_bytes(C.byref(too_few), C.byref(pg.options("bicgstab"))) == 0
+    # a pad of many cells over a large log step cannot be monotone
+    non_mono = pg.sph_grid(40, 8, 16, 0.01, 1.0, ext_in=20, r_pad=0.009)
+    assert lib.poisson_workspace_bytes(C.byref(non_mono), C.byref(pg.options("bicgstab"))) == 0
+    cart = pg.cart_grid(32)
+    cart.ext_in = 2
+    assert lib.poisson_workspace_bytes(C.byref(cart), C.byref(pg.options("mg"))) == 0

@@ -1,0 +1,150 @@
+"""Spherical solves on the padded radial grid (Section 3.3: log core, outer
+pad continuing the log map, inner pad along the quartic down to r_in,pad)
+against the oracle on the same map: operator, residual, multipole shells,
+SOR sweeps with per-radius relaxation factors, converged BiCGSTAB and SOR."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2605_03563_amd as pg
+from oracle import direct as OD
+from oracle import multipole as OM
+from oracle import operators as OO
+from oracle import sph_sor as SS
+from oracle.radial import RadialMap
+from tests.gpu_util import dev, host, rel_l2, rel_max, say
+
+pytestmark = pytest.mark.gpu
+KTOL = 1e-12
+CONV_TOL = 1e-9
+
+# the paper's pad shape scaled down: log steps of a few percent, the inner
+# pad ending at r_in / 2
+NR, NTH, NPH = 40, 8, 16
+R_IN, R_OUT, EXT_IN, EXT_OUT, R_PAD = 0.2, 1.0, 8, 6, 0.1
+
+
+def _grid_and_map(nr=NR, nth=NTH, nph=NPH):
+    g = pg.sph_grid(nr, nth, nph, R_IN, R_OUT, ext_in=EXT_IN, ext_out=EXT_OUT, r_pad=R_PAD)
+    m = RadialMap(nr, R_IN, R_OUT, ext_in=EXT_IN, ext_out=EXT_OUT, r_pad=R_PAD)
+    th = (np.arange(nth) + 0.5) * math.pi / nth
+    return g, m, th
+
+
+def _padded_density(m, nth, nph, seed):
+    """r^-2 with an m = 2 perturbation inside the log core, zero in the pads
+    (the zero-padding of Section 3.3)."""
+    rng = np.random.default_rng(seed)
+    th = (np.arange(nth) + 0.5) * math.pi / nth
+    ph = np.arange(nph) * 2 * math.pi / nph
+    phase = rng.uniform(0, math.pi)
+    ang = 1.0 + 0.1 * np.sin(th)[None, :] ** 2 * np.cos(2 * (ph[:, None] - phase))
+    core = (m.r >= R_IN * (1 - 1e-12)) & (m.r <= 0.8 * R_OUT)
+    radial = np.where(core, 1.0 / m.r ** 2, 0.0)
+    radial[0] = radial[-1] = 0.0
+    return ang[:, :, None] * radial[None, None, :]
+
+
+def test_operator_and_residual_on_padded_grid():
+    say("padded grid: operator and residual")
+    g, m, th = _grid_and_map()
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((NPH, NTH, NR + 2))
+    rho = rng.standard_normal((NPH, NTH, NR + 2))
+    plan = pg.Plan(g, pg.options("bicgstab", lmax=-1))
+    out = torch.zeros(u.shape, dtype=torch.float64, device="cuda:0")
+    plan.apply(dev(u), out)
+    ref = OO.sph_apply(u, m, th)
+    assert rel_max(host(out)[:, :, 1:NR + 1], ref) < KTOL
+    res = torch.zeros(u.shape, dtype=torch.float64, device="cuda:0")
+    n2 = plan.residual(dev(rho), dev(u), res)
+    rref = OO.sph_residual(u, rho, m.r, m, th)
+    assert rel_max(host(res)[:, :, 1:NR + 1], rref) < KTOL
+    assert n2 == pytest.approx(float(np.sum(rref * rref)), rel=1e-12)
+
+
+def test_multipole_shells_on_padded_grid():
+    """Moments with the mapped radial weights and both ghost shells (the
+    inner one at r_pad) against the oracle."""
+    say("padded grid: multipole")
+    g, m, th = _grid_and_map()
+    rho = _padded_density(m, NTH, NPH, 3)
+    mc = 0.05
+    plan = pg.Plan(g, pg.options("bicgstab", lmax=8, point_mass=mc))
+    phi = torch.zeros(rho.shape, dtype=torch.float64, device="cuda:0")
+    q = np.array(plan.multipole_boundary(dev(rho), phi, 8))
+    ref_phi, rq, rqb = OM.sph_boundary(rho, NR, NTH, NPH, 8, point_mass=mc, rmap=m)
+    assert rel_max(q[:81], rq) < KTOL
+    assert rel_max(q[81:], rqb) < KTOL
+    got = host(phi)
+    assert rel_max(got[:, :, 0], ref_phi[:, :, 0]) < KTOL
+    assert rel_max(got[:, :, -1], ref_phi[:, :, -1]) < KTOL
+
+
+@pytest.mark.parametrize("mode", ["chebyshev", "opt"])
+def test_sor_sweeps_with_per_radius_factors(mode):
+    """Three sweeps: on the padded grid r_J (Eq. local_rjac) varies with the
+    radius through the operator's radial coupling, and so do the factors."""
+    say(f"padded grid: SOR sweeps ({mode})")
+    g, m, th = _grid_and_map()
+    rng = np.random.default_rng(8)
+    u = rng.standard_normal((NPH, NTH, NR + 2))
+    rho = rng.standard_normal((NPH, NTH, NR + 2))
+    om = pg.OMEGA_CHEBYSHEV if mode == "chebyshev" else pg.OMEGA_OPT
+    plan = pg.Plan(g, pg.options("sor", lmax=-1, omega_mode=om))
+    x = dev(u)
+    plan.smooth(dev(rho), x, sweeps=3)
+    rj = SS.local_rjac(NR, NTH, NPH, m, th)
+    assert np.ptp(rj[0]) > 1e-3
+    ref = u.copy()
+    w = SS.omega_first(rj) if mode == "chebyshev" else SS.omega_opt(rj)
+    for _ in range(3):
+        wr = w
+        if mode == "chebyshev":
+            w = SS.omega_next(w, rj)
+        wb = w
+        if mode == "chebyshev":
+            w = SS.omega_next(w, rj)
+        SS.sweep(ref, rho, m.r, m, th, wr, wb)
+    assert rel_max(host(x), ref) < KTOL
+
+
+@pytest.mark.parametrize("method", ["bicgstab", "sor"])
+def test_converged_solve_on_padded_grid(method):
+    """Padded density with the multipole boundary at r_pad and r_out,pad:
+    BiCGSTAB (Gauss-Seidel preconditioner) and SOR (local Chebyshev factors)
+    equal the oracle's per-mode sparse LU solution on the same map."""
+    say(f"padded grid: converged {method}")
+    nr, nth, nph = 48, 8, 16
+    g, m, th = _grid_and_map(nr, nth, nph)
+    rho = _padded_density(m, nth, nph, 11)
+    kw = {"max_iter": 60000, "omega_mode": pg.OMEGA_CHEBYSHEV, "check_every": 10} if method == "sor" else {}
+    plan = pg.Plan(g, pg.options(method, lmax=8, **kw))
+    phi = torch.zeros(rho.shape, dtype=torch.float64, device="cuda:0")
+    res = plan.solve(dev(rho), phi, tol=1e-12)
+    say(f"  {res.iterations} iterations")
+    assert res.converged, res
+    ghost, _, _ = OM.sph_boundary(rho, nr, nth, nph, 8, rmap=m)
+    ref = OD.solve_sph(ghost, rho, m.r, m, th)
+    assert rel_l2(host(phi)[:, :, 1:nr + 1], ref[:, :, 1:nr + 1]) < CONV_TOL
+
+
+def test_plain_log_grid_unchanged_by_the_tables():
+    """Without pads the tabulated operator is the s = ln r one: a converged
+    BiCGSTAB solve on C4's density (32 x 16 x 16) equals the log-grid
+    oracle."""
+    import workloads as W
+    say("plain log grid through the radial tables")
+    nr, nth, nph = 32, 16, 16
+    wl = W.config_c4(nr=nr, nth=nth, nph=nph)
+    rho = wl.rho.numpy()
+    r, th, ph, ds = OM.sph_axes(nr, nth, nph)
+    plan = pg.Plan(pg.sph_grid(nr, nth, nph), pg.options("bicgstab", lmax=8))
+    phi = torch.zeros(rho.shape, dtype=torch.float64, device="cuda:0")
+    res = plan.solve(dev(rho), phi, tol=1e-12)
+    assert res.converged, res
+    ghost, _, _ = OM.sph_boundary(rho, nr, nth, nph, 8)
+    ref = OD.solve_sph(ghost, rho, r, ds, th)
+    assert rel_l2(host(phi)[:, :, 1:nr + 1], ref[:, :, 1:nr + 1]) < CONV_TOL
