@@ -240,7 +240,7 @@ template <typename T, typename TO>
 __global__ __launch_bounds__(BX * TBY) void k_residual19s(const T* __restrict__ X, const T* __restrict__ F,
                                                           TO* __restrict__ R, Geom G, T ih2,
                                                           double* __restrict__ partial) {
-  __shared__ T tile[TROWS][4][TCOLS];
+  __shared__ T tile[2][TROWS][4][TCOLS];  // double-buffered by plane parity
   int bx, by, bz;
   xcd_block(bx, by, bz);
   const int tx = threadIdx.x, ty = threadIdx.y;
@@ -267,17 +267,24 @@ __global__ __launch_bounds__(BX * TBY) void k_residual19s(const T* __restrict__ 
 #pragma unroll
     for (int q = 0; q < 4; ++q) win[d + 3][q] = (colok && rowok) ? load(b, k0 + d, m, q) : (T)0;
   double acc = 0.0;
+  const bool live = m <= G.mhi() && b <= last;
   for (int k = k0; k <= k1; ++k) {
+    const int buf = k & 1;
 #pragma unroll
     for (int q = 0; q < 4; ++q) win[6][q] = (colok && rowok) ? load(b, k + 3, m, q) : (T)0;
+    // right-hand sides of the column's four nodes, loaded before the barrier
+    const int s = (b + k + G.off) & 3;
+    T fq[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) tile[ty + 3][q][tx + 1] = win[3][q];
+    for (int q = 0; q < 4; ++q) fq[q] = live ? F[(long long)((q + s) & 3) * G.cs + k * plane + cb] : (T)0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tile[buf][ty + 3][q][tx + 1] = win[3][q];
     if (ty < 6) {
       const int hb = ty < 3 ? b0 - 3 + ty : b0 + TBY + (ty - 3);
       const int tr = ty < 3 ? ty : TBY + ty;
       const bool ok = hb >= 0 && hb < G.M && colok;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) tile[tr][q][tx + 1] = ok ? load(hb, k, m, q) : (T)0;
+      for (int q = 0; q < 4; ++q) tile[buf][tr][q][tx + 1] = ok ? load(hb, k, m, q) : (T)0;
     }
     if (tx < 2) {
       const int hm = tx == 0 ? m0 - 1 : m0 + BX;
@@ -286,12 +293,11 @@ __global__ __launch_bounds__(BX * TBY) void k_residual19s(const T* __restrict__ 
         const int hb = b0 - 3 + tr;
         const bool ok = hb >= 0 && hb < G.M && hm >= 0 && hm < G.W;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) tile[tr][q][tc] = ok ? load(hb, k, hm, q) : (T)0;
+        for (int q = 0; q < 4; ++q) tile[buf][tr][q][tc] = ok ? load(hb, k, hm, q) : (T)0;
       }
     }
     __syncthreads();
-    if (m <= G.mhi() && b <= last) {
-      const int s = (b + k + G.off) & 3;
+    if (live) {
       const int r0 = ty + 3;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -302,18 +308,20 @@ __global__ __launch_bounds__(BX * TBY) void k_residual19s(const T* __restrict__ 
         for (int d = 1; d <= 3; ++d) {
           // x: positions q +- d, possibly in the neighbouring compact column
           const int qp = q + d, qm = q - d;
-          const T xp = tile[r0][qp & 3][tx + 1 + (qp >> 2)];
-          const T xm = tile[r0][qm & 3][tx + 1 + (qm >> 2)];
-          sd[d - 1] = xp + xm + tile[r0 + d][q][tx + 1] + tile[r0 - d][q][tx + 1] + win[3 + d][q] + win[3 - d][q];
+          const T xp = tile[buf][r0][qp & 3][tx + 1 + (qp >> 2)];
+          const T xm = tile[buf][r0][qm & 3][tx + 1 + (qm >> 2)];
+          sd[d - 1] = xp + xm + tile[buf][r0 + d][q][tx + 1] + tile[buf][r0 - d][q][tx + 1] + win[3 + d][q] +
+                      win[3 - d][q];
         }
         const T lap = ((T)(3.0 * kC0) * win[3][q] + (T)kC1 * sd[0] + (T)kC2 * sd[1] + (T)kC3 * sd[2]) * ih2;
         const long long idx = (long long)((q + s) & 3) * G.cs + k * plane + cb;
-        const T res = F[idx] - lap;
+        const T res = fq[q] - lap;
         if (R) R[idx] = (TO)res;
         acc += (double)res * (double)res;
       }
     }
-    __syncthreads();
+    // the next plane writes the other buffer; the plane after it waits at
+    // that plane's barrier, which every thread passes only after this compute
 #pragma unroll
     for (int d = 0; d < 6; ++d)
 #pragma unroll
