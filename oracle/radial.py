@@ -61,6 +61,19 @@ class RadialMap:
         self.cr = a + b / 2.0
         self.w = r * r * r1                               # radial volume weight per unit xi
 
+    def level_couplings(self, level: int, n: int):
+        """(cl, cr) of the operator rediscretised on multigrid level `level`,
+        whose n radial unknowns pair the cells of the level below two by two:
+        unknown I sits at xi = 2^level I + (2^level - 1)/2 - p (the mean of
+        the nodes it pairs) with spacing h = 2^level; a = (r / (h R'))^2,
+        b = 2 r / (h R') - r^2 R'' / (h R'^3)."""
+        h = float(2 ** level)
+        xi = h * np.arange(n) + (h - 1.0) / 2.0 - self.p
+        r, r1, r2 = self.R(xi), self._d1(xi), self._d2(xi)
+        a = (r / (h * r1)) ** 2
+        b = 2.0 * r / (h * r1) - r * r * r2 / (h * r1 ** 3)
+        return a - b / 2.0, a + b / 2.0
+
     def xi(self, i):
         """Map coordinate of radial index i (0 .. nr-1 unknowns, -1 and nr ghosts)."""
         return np.asarray(i, dtype=np.float64) - self.p

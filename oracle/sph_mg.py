@@ -17,6 +17,10 @@ multigrid; this follows the construction chosen for it:
   injection of the coarse correction into its 8 fine nodes; coarsest level:
   a dense solve.
 
+On a padded radial grid (radial.RadialMap in place of ds) every level takes
+the radial couplings of the map rediscretised on it (RadialMap.level_couplings:
+unknowns at the means of the nodes they pair, spacing doubled per level).
+
 Test infrastructure: imported by tests only.  FP64 throughout (the GPU cycle
 runs in FP32; the tests state the tolerance).
 """
@@ -49,10 +53,33 @@ def coefs(nth: int, nph: int, ds: float):
     return dth, cot2, aphi, diag
 
 
+class _Level:
+    """Radial couplings of one level of a mapped radial grid."""
+    def __init__(self, rmap, level, nr):
+        self.rmap, self.level = rmap, level
+        self.cl, self.cr = rmap.level_couplings(level, nr)
+
+    def coarser(self, nr):
+        return _Level(self.rmap, self.level + 1, nr)
+
+
+def _radial(ds, nr):
+    """(cl, cr) per radial unknown: from a float spacing (log grid) or a level
+    of a mapped grid."""
+    if isinstance(ds, (int, float)):
+        return (np.full(nr, 1 / ds ** 2 - 1 / (2 * ds)), np.full(nr, 1 / ds ** 2 + 1 / (2 * ds)))
+    return ds.cl, ds.cr
+
+
+def level0(rmap, nr):
+    """The finest level of the mapped grid rmap, to pass in place of ds."""
+    return _Level(rmap, 0, nr)
+
+
 def apply(u: np.ndarray, ds: float) -> np.ndarray:
     """r^2 lap u on the unknowns of u [nph][nth][nr] (zero radial ghosts)."""
     nph, nth, nr = u.shape
-    dth, cot2, aphi, diag = coefs(nth, nph, ds)
+    dth, cot2, aphi, diag = coefs(nth, nph, ds if isinstance(ds, (int, float)) else 1.0)
     z = np.zeros((nph, nth, 1))
     up = np.concatenate([u[:, :, 1:], z], axis=2)
     um = np.concatenate([z, u[:, :, :-1]], axis=2)
@@ -64,30 +91,36 @@ def apply(u: np.ndarray, ds: float) -> np.ndarray:
     km = np.roll(u, 1, axis=0)
     c2 = cot2[None, :, None]
     ap = aphi[None, :, None]
-    return ((1 / ds ** 2 + 1 / (2 * ds)) * up + (1 / ds ** 2 - 1 / (2 * ds)) * um + (1 / dth ** 2 + c2) * jp
-            + (1 / dth ** 2 - c2) * jm + ap * (kp + km) + diag[None, :, None] * u)
+    if isinstance(ds, (int, float)):
+        return ((1 / ds ** 2 + 1 / (2 * ds)) * up + (1 / ds ** 2 - 1 / (2 * ds)) * um + (1 / dth ** 2 + c2) * jp
+                + (1 / dth ** 2 - c2) * jm + ap * (kp + km) + diag[None, :, None] * u)
+    cl, cr = ds.cl[None, None, :], ds.cr[None, None, :]
+    dang = (-2.0 / dth ** 2 - 2.0 * aphi)[None, :, None]
+    return (cr * up + cl * um + (1 / dth ** 2 + c2) * jp + (1 / dth ** 2 - c2) * jm + ap * (kp + km)
+            + (dang - (cl + cr)) * u)
 
 
 def line_pass(u: np.ndarray, f: np.ndarray, ds: float, colour: int) -> np.ndarray:
     """Solve every line (i, j) of the colour exactly along phi, in place."""
     nph, nth, nr = u.shape
-    dth, cot2, aphi, diag = coefs(nth, nph, ds)
+    dth, cot2, aphi, _ = coefs(nth, nph, 1.0)
+    cl, cr = _radial(ds, nr)
     half = nph // 2
     old = u.copy()
     for j in range(nth):
-        C = np.zeros((nph, nph))
-        for k in range(nph):
-            C[k, k] = diag[j]
-            C[k, (k + 1) % nph] += aphi[j]
-            C[k, (k - 1) % nph] += aphi[j]
         for i in range(nr):
             if (i + j) % 2 != colour:
                 continue
+            C = np.zeros((nph, nph))
+            for k in range(nph):
+                C[k, k] = -(cl[i] + cr[i]) - 2.0 / dth ** 2 - 2.0 * aphi[j]
+                C[k, (k + 1) % nph] += aphi[j]
+                C[k, (k - 1) % nph] += aphi[j]
             ip = old[:, j, i + 1] if i + 1 < nr else np.zeros(nph)
             im = old[:, j, i - 1] if i > 0 else np.zeros(nph)
             jp = old[:, j + 1, i] if j + 1 < nth else np.roll(old[:, j, i], -half)
             jm = old[:, j - 1, i] if j > 0 else np.roll(old[:, j, i], -half)
-            rhs = f[:, j, i] - ((1 / ds ** 2 + 1 / (2 * ds)) * ip + (1 / ds ** 2 - 1 / (2 * ds)) * im
+            rhs = f[:, j, i] - (cr[i] * ip + cl[i] * im
                                 + (1 / dth ** 2 + cot2[j]) * jp + (1 / dth ** 2 - cot2[j]) * jm)
             u[:, j, i] = np.linalg.solve(C, rhs)
     return u
@@ -119,7 +152,7 @@ def vcycle(f: np.ndarray, ds: float, nu1: int = 2, nu2: int = 2, _lv=None, _cach
     if _cache is None:
         _cache = {}
     if len(_lv) == 1:
-        key = (nr, nth, nph, ds)
+        key = (nr, nth, nph, ds if isinstance(ds, (int, float)) else (id(ds.rmap), ds.level))
         if key not in _cache:
             _cache[key] = np.linalg.inv(dense_matrix(nr, nth, nph, ds))
         return (_cache[key] @ f.ravel()).reshape(f.shape)
@@ -128,7 +161,8 @@ def vcycle(f: np.ndarray, ds: float, nu1: int = 2, nu2: int = 2, _lv=None, _cach
         for c in (0, 1):
             line_pass(u, f, ds, c)
     r = f - apply(u, ds)
-    e = vcycle(restrict(r), 2.0 * ds, nu1, nu2, _lv[1:], _cache)
+    coarse = 2.0 * ds if isinstance(ds, (int, float)) else ds.coarser(_lv[1][0])
+    e = vcycle(restrict(r), coarse, nu1, nu2, _lv[1:], _cache)
     u += prolong(e)
     for _ in range(nu2):
         for c in (1, 0):

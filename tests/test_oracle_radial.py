@@ -136,3 +136,33 @@ def test_multipole_shells_on_mapped_grid():
     G = 1.0 / (4 * math.pi)
     assert np.allclose(phi[:, :, -1], -G * q[0] / m.r[-1], rtol=1e-3)
     assert np.ptp(phi[:, :, 0]) < 1e-3 * abs(phi[0, 0, 0])
+
+
+def test_level_couplings_on_the_log_map():
+    """Multigrid level l of the plain log map has the s = ln r couplings of
+    spacing 2^l ds."""
+    m = RadialMap(64, 1e-3, 1.0)
+    for level, n in ((0, 64), (1, 32), (3, 8)):
+        cl, cr = m.level_couplings(level, n)
+        d = m.ds * 2 ** level
+        assert np.allclose(cl, 1 / d ** 2 - 1 / (2 * d), rtol=1e-12)
+        assert np.allclose(cr, 1 / d ** 2 + 1 / (2 * d), rtol=1e-12)
+    cl, cr = m.level_couplings(0, 64)
+    assert np.allclose(cl, m.cl, rtol=1e-14) and np.allclose(cr, m.cr, rtol=1e-14)
+
+
+def test_multigrid_preconditioner_cycle_on_padded_grid():
+    """One V(2,2) cycle of the spherical preconditioner on a padded grid
+    (levels rediscretised from the map) cuts the residual of a random right-
+    hand side about as much as on the log grid (0.42 against 0.35 on this
+    two-level grid)."""
+    from oracle import sph_mg as SM
+    nr, nth, nph = 32, 8, 16
+    m = RadialMap(nr, 0.5, 1.0, ext_in=5, ext_out=5, r_pad=0.3)
+    lv = SM.level0(m, nr)
+    f = np.random.default_rng(3).normal(size=(nph, nth, nr))
+    u = SM.vcycle(f, lv)
+    red = np.linalg.norm(f - SM.apply(u, lv)) / np.linalg.norm(f)
+    flog = SM.vcycle(f, m.ds)
+    red_log = np.linalg.norm(f - SM.apply(flog, m.ds)) / np.linalg.norm(f)
+    assert red < 0.6 and red < 1.5 * red_log, (red, red_log)
