@@ -68,24 +68,30 @@ struct SGeom {
   __host__ __device__ long long at(int i, int j, int k) const { return (long long)k * p1 + (long long)j * p0 + i; }
 };
 
-// One level of the FP32 multigrid preconditioner on the log-spherical grid:
+// One level of the FP32 multigrid preconditioner on the spherical grid:
 // nr x nth x nph unknowns in [phi][theta][r] layout with one zero radial
 // ghost on each side; level l pairs the nodes of level l-1 two by two along
-// each axis (spacings doubled, colatitudes (j + 1/2) pi / nth).
+// each axis (spacings doubled, colatitudes (j + 1/2) pi / nth).  The radial
+// couplings rcl[i], rcr[i] (to unknowns i-1, i+1; diagonal -(rcl + rcr))
+// are the radial map's operator rediscretised on the level: constant on the
+// log grid, varying with i where an inner pad bends the map.
 struct SLev {
   int nr, nth, nph, p0;  // unknowns, row pitch
   long long p1;          // plane pitch
-  float ids2, i2ds, idt2, idp2;
+  float idt2, idp2;
   float* u;
   float* f;
   float* r;
+  const float* rcl;    // per radial unknown i
+  const float* rcr;
   const float* cot2;   // cot(theta_j) / (2 dtheta)
   const float* isin2;  // 1 / sin^2(theta_j)
   // phi-line solver: each line splits into nseg segments of seg nodes; a
-  // block holds nl lines; per colatitude j the table at ltab + j * tstride
-  // holds the segment elimination factors m[seg], c'[seg], the responses
-  // v[seg], w[seg] to unit end loads and the 2nseg x 2nseg interface inverse
-  int seg, nseg, nl, tstride;
+  // block holds nl lines; the table of line (i, j) at ltab + (it nth + j)
+  // tstride (it = i when the radial couplings vary, tri = 1, else 0) holds
+  // the segment elimination factors m[seg], c'[seg], the responses v[seg],
+  // w[seg] to unit end loads and the 2nseg x 2nseg interface inverse
+  int seg, nseg, nl, tstride, tri;
   const float* ltab;
   __host__ __device__ long long at(int i, int j, int k) const { return (long long)k * p1 + (long long)j * p0 + i; }
   __host__ __device__ long long count() const { return p1 * nph; }

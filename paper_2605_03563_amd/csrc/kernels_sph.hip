@@ -273,12 +273,12 @@ __device__ inline float slev_off(const SLev& L, int i, int j, int k) {
   const float jp = (j + 1 < L.nth) ? u(a, j + 1, k) : u(a, L.nth - 1, (k + half) % L.nph);
   const float jm = (j > 0) ? u(a, j - 1, k) : u(a, 0, (k + half) % L.nph);
   const float kp = u(a, j, (k + 1) % L.nph), km = u(a, j, (k + L.nph - 1) % L.nph);
-  return (L.ids2 + L.i2ds) * u(a + 1, j, k) + (L.ids2 - L.i2ds) * u(a - 1, j, k) + (L.idt2 + L.cot2[j]) * jp +
+  return L.rcr[i] * u(a + 1, j, k) + L.rcl[i] * u(a - 1, j, k) + (L.idt2 + L.cot2[j]) * jp +
          (L.idt2 - L.cot2[j]) * jm + L.isin2[j] * L.idp2 * (kp + km);
 }
 
-__device__ inline float slev_diag(const SLev& L, int j) {
-  return -2.0f * L.ids2 - 2.0f * L.idt2 - 2.0f * L.isin2[j] * L.idp2;
+__device__ inline float slev_diag(const SLev& L, int i, int j) {
+  return -(L.rcl[i] + L.rcr[i]) - 2.0f * L.idt2 - 2.0f * L.isin2[j] * L.idp2;
 }
 
 // One zebra colour of phi-line Gauss-Seidel.  Block (x, j) takes nl lines
@@ -298,7 +298,8 @@ __global__ __launch_bounds__(1024) void k_sline(SLev L, int colour, int zero_gue
   const int SL = L.seg, P = L.nseg;
   float* Y = lds;
   float* E = lds + (size_t)SL * nt;
-  const float* tb = L.ltab + (size_t)j * L.tstride;
+  const int it = L.tri ? min(i, L.nr - 1) : 0;
+  const float* tb = L.ltab + ((size_t)it * L.nth + j) * L.tstride;
   const float* m = tb;
   const float* cp = tb + SL;
   const float* v = tb + 2 * SL;
@@ -309,7 +310,7 @@ __global__ __launch_bounds__(1024) void k_sline(SLev L, int colour, int zero_gue
   const int k0 = sgi * SL;
   if (act) {
     const int a = i + 1, half = L.nph >> 1;
-    const float cr = L.ids2 + L.i2ds, cl = L.ids2 - L.i2ds;
+    const float cr = L.rcr[i], cl = L.rcl[i];
     const float cjp = L.idt2 + L.cot2[j], cjm = L.idt2 - L.cot2[j];
     float d = 0.0f;
 #pragma unroll 8
@@ -358,7 +359,7 @@ __global__ __launch_bounds__(256) void k_sres32(SLev L) {
   const int k = blockIdx.z;
   if (i >= L.nr || j >= L.nth) return;
   const long long idx = L.at(i + 1, j, k);
-  L.r[idx] = L.f[idx] - (slev_off(L, i, j, k) + slev_diag(L, j) * L.u[idx]);
+  L.r[idx] = L.f[idx] - (slev_off(L, i, j, k) + slev_diag(L, i, j) * L.u[idx]);
 }
 
 // coarse f = mean of the 8 fine residuals it pairs

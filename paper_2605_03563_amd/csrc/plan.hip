@@ -111,30 +111,16 @@ bool line_split(int nph, int* seg, int* nseg, int* nl) {
   return true;
 }
 
-// Radial nodes of the spherical grid (Section 3.3).  Radial index a = 0 ..
+// Radial map of the spherical grid (Section 3.3).  Radial index a = 0 ..
 // nr+1 (a = 0 and nr+1 the ghosts) sits at map coordinate xi = a - 1 - p,
 // p = max(ext_in - 1, 0) inner pad unknowns; the log core r_in e^(xi ds)
 // covers xi = 0 .. nlog-1 and continues outward; with an inner pad, xi < 0
 // follows the quartic Q(xi) that matches the log map's value and first
-// three derivatives at xi = 0 and reaches r_pad at xi = -ext_in.  The
-// operator on the map coordinate is a u_xixi + b u_xi with a = (r/R')^2,
-// b = 2r/R' - r^2 R''/R'^3, i.e. couplings cl = a - b/2, cr = a + b/2; the
-// radial volume weight is r^2 R'.
-bool sph_radial_map(const poisson_grid_t& g, std::vector<double>& r, std::vector<double>& cl,
-                    std::vector<double>& cr, std::vector<double>& w, double& ds) {
-  const int nr = g.n[0];
-  const int ein = g.ext_in, eout = g.ext_out;
-  const int p = ein > 0 ? ein - 1 : 0, q = eout > 0 ? eout - 1 : 0;
-  const int nlog = nr - p - q;
-  if (nlog < 2 || ein < 0 || eout < 0) return false;
-  const double rin = g.lo[0];
-  ds = log(g.hi[0] / rin) / (nlog - 1);
-  double c4 = 0.0;
-  if (ein > 0) {
-    const double E = ein, x = ds * E;
-    c4 = (g.r_pad - rin * (1.0 - x + x * x / 2.0 - x * x * x / 6.0)) / (E * E * E * E);
-  }
-  auto eval = [&](double xi, double& R, double& R1, double& R2) {
+// three derivatives at xi = 0 and reaches r_pad at xi = -ext_in.
+struct RadialFn {
+  double rin = 0.0, ds = 0.0, c4 = 0.0;
+  int ein = 0, p = 0;
+  void eval(double xi, double& R, double& R1, double& R2) const {
     if (ein > 0 && xi < 0.0) {
       const double d = ds, x = d * xi;
       R = rin * (1.0 + x + x * x / 2.0 + x * x * x / 6.0) + c4 * xi * xi * xi * xi;
@@ -145,32 +131,80 @@ bool sph_radial_map(const poisson_grid_t& g, std::vector<double>& r, std::vector
       R1 = ds * R;
       R2 = ds * ds * R;
     }
-  };
+  }
+  // The operator on the map coordinate is a u_xixi + b u_xi with
+  // a = (r/R')^2, b = 2r/R' - r^2 R''/R'^3; central differences of spacing h
+  // give the couplings cl = a/h^2 - b/(2h) (to xi - h), cr = a/h^2 + b/(2h).
+  void couple(double xi, double h, double& cl, double& cr) const {
+    double R, R1, R2;
+    eval(xi, R, R1, R2);
+    const double q = R / (h * R1);
+    const double bb = 2.0 * q - R * R * R2 / (h * R1 * R1 * R1);
+    cl = q * q - 0.5 * bb;
+    cr = q * q + 0.5 * bb;
+  }
+};
+
+bool radial_fn(const poisson_grid_t& g, RadialFn& f) {
+  const int nr = g.n[0];
+  const int ein = g.ext_in, eout = g.ext_out;
+  const int p = ein > 0 ? ein - 1 : 0, q = eout > 0 ? eout - 1 : 0;
+  const int nlog = nr - p - q;
+  if (nlog < 2 || ein < 0 || eout < 0) return false;
+  f.rin = g.lo[0];
+  f.ein = ein;
+  f.p = p;
+  f.ds = log(g.hi[0] / f.rin) / (nlog - 1);
+  f.c4 = 0.0;
   if (ein > 0) {
+    const double E = ein, x = f.ds * E;
+    f.c4 = (g.r_pad - f.rin * (1.0 - x + x * x / 2.0 - x * x * x / 6.0)) / (E * E * E * E);
     // the pad must map monotonically (R' > 0 on [-ext_in, 0])
     for (int t = 0; t <= 2000; ++t) {
       double R, R1, R2;
-      eval(-ein + ein * (t / 2000.0), R, R1, R2);
+      f.eval(-ein + ein * (t / 2000.0), R, R1, R2);
       if (!(R1 > 0.0) || !(R > 0.0)) return false;
     }
   }
+  return true;
+}
+
+// Radii, couplings (spacing 1 in xi) and radial volume weights r^2 R' per
+// radial index of the finest grid.
+bool sph_radial_map(const poisson_grid_t& g, std::vector<double>& r, std::vector<double>& cl,
+                    std::vector<double>& cr, std::vector<double>& w, double& ds) {
+  RadialFn f;
+  if (!radial_fn(g, f)) return false;
+  const int nr = g.n[0];
+  ds = f.ds;
   r.assign(nr + 2, 0.0);
   cl.assign(nr + 2, 0.0);
   cr.assign(nr + 2, 0.0);
   w.assign(nr + 2, 0.0);
   for (int a = 0; a < nr + 2; ++a) {
+    const double xi = (double)(a - 1 - f.p);
     double R, R1, R2;
-    eval((double)(a - 1 - p), R, R1, R2);
+    f.eval(xi, R, R1, R2);
     r[a] = R;
     if (a >= 1 && a <= nr) {
-      const double aa = (R / R1) * (R / R1);
-      const double bb = 2.0 * R / R1 - R * R * R2 / (R1 * R1 * R1);
-      cl[a] = aa - 0.5 * bb;
-      cr[a] = aa + 0.5 * bb;
+      f.couple(xi, 1.0, cl[a], cr[a]);
       w[a] = R * R * R1;
     }
   }
   return true;
+}
+
+// Radial couplings of multigrid level `level` with n radial unknowns: level
+// unknown I pairs two nodes of the level below and sits at their mean,
+// xi = 2^level I + (2^level - 1)/2 - p, with spacing h = 2^level.
+void sph_level_couplings(const poisson_grid_t& g, int level, int n, std::vector<double>& cl,
+                         std::vector<double>& cr) {
+  RadialFn f;
+  radial_fn(g, f);
+  const double h = (double)(1 << level);
+  cl.assign(n, 0.0);
+  cr.assign(n, 0.0);
+  for (int I = 0; I < n; ++I) f.couple(h * I + 0.5 * (h - 1.0) - f.p, h, cl[I], cr[I]);
 }
 
 int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
@@ -253,10 +287,6 @@ int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
         set_error("radial pads leave fewer than two log-core unknowns or a non-monotone inner pad");
         return POISSON_EGRID;
       }
-    }
-    if ((g->ext_in > 0 || g->ext_out > 0) && o->method == POISSON_BICGSTAB_MG32) {
-      set_error("the FP32 multigrid preconditioner is built for the plain log grid (no radial pads)");
-      return POISSON_EINVAL;
     }
     if (g->pitch[0] < g->n[0] + 2 || g->pitch[1] < (int64_t)g->n[1] * g->pitch[0]) {
       set_error("pitch too small for the spherical grid");
@@ -408,8 +438,6 @@ void carve(poisson_plan_s* P, Carver& cv) {
     }
     P->slv.clear();
     if (o.method == POISSON_BICGSTAB_MG32) {
-      const double ds = log(g.hi[0] / g.lo[0]) / (g.n[0] - 1);
-      int lev = 0;
       for (const auto& d : sph_levels(g.n[0], g.n[1], g.n[2])) {
         SLev L{};
         L.nr = d[0];
@@ -417,23 +445,24 @@ void carve(poisson_plan_s* P, Carver& cv) {
         L.nph = d[2];
         L.p0 = L.nr + 2;
         L.p1 = (long long)L.nth * L.p0;
-        const double dsl = ds * (1 << lev), dth = M_PI / L.nth, dph = 2.0 * M_PI / L.nph;
-        L.ids2 = (float)(1.0 / (dsl * dsl));
-        L.i2ds = (float)(1.0 / (2.0 * dsl));
+        const double dth = M_PI / L.nth, dph = 2.0 * M_PI / L.nph;
         L.idt2 = (float)(1.0 / (dth * dth));
         L.idp2 = (float)(1.0 / (dph * dph));
         const size_t fb = sizeof(float) * (size_t)L.count();
         L.u = (float*)cv.take(fb);
         L.f = (float*)cv.take(fb);
         L.r = (float*)cv.take(fb);
+        L.rcl = (const float*)cv.take(sizeof(float) * L.nr);
+        L.rcr = (const float*)cv.take(sizeof(float) * L.nr);
         L.cot2 = (const float*)cv.take(sizeof(float) * L.nth);
         L.isin2 = (const float*)cv.take(sizeof(float) * L.nth);
+        L.tri = g.ext_in > 0 ? 1 : 0;
         if (line_split(L.nph, &L.seg, &L.nseg, &L.nl)) {
           L.tstride = 4 * L.seg + 4 * L.nseg * L.nseg;
-          L.ltab = (const float*)cv.take(sizeof(float) * (size_t)L.tstride * L.nth);
+          const size_t nlines = (size_t)L.nth * (L.tri ? L.nr : 1);
+          L.ltab = (const float*)cv.take(sizeof(float) * (size_t)L.tstride * nlines);
         }
         P->slv.push_back(L);
-        ++lev;
       }
       const SLev& C = P->slv.back();
       P->sncoarse = C.nr * C.nth * C.nph;
@@ -625,8 +654,10 @@ bool invert_general(int N, std::vector<double>& A, std::vector<double>& inv) {
 }
 
 // Dense operator of a spherical multigrid level (zero radial ghosts, pole
-// reflection, periodic phi), in the same coefficients as the level kernels.
-void sph_level_matrix(int nr, int nth, int nph, double ds, std::vector<double>& A) {
+// reflection, periodic phi), in the same coefficients as the level kernels;
+// cl, cr: radial couplings per radial unknown.
+void sph_level_matrix(int nr, int nth, int nph, const std::vector<double>& cl, const std::vector<double>& cr,
+                      std::vector<double>& A) {
   const int N = nr * nth * nph;
   A.assign((size_t)N * N, 0.0);
   const double dth = M_PI / nth, dph = 2.0 * M_PI / nph;
@@ -638,9 +669,9 @@ void sph_level_matrix(int nr, int nth, int nph, double ds, std::vector<double>& 
       const double cot2 = cos(th) / sin(th) / (2.0 * dth), is2 = 1.0 / (sin(th) * sin(th));
       for (int i = 0; i < nr; ++i) {
         double* row = &A[(size_t)id(i, j, k) * N];
-        row[id(i, j, k)] += -2.0 / (ds * ds) - 2.0 / (dth * dth) - 2.0 * is2 / (dph * dph);
-        if (i + 1 < nr) row[id(i + 1, j, k)] += 1.0 / (ds * ds) + 1.0 / (2.0 * ds);
-        if (i > 0) row[id(i - 1, j, k)] += 1.0 / (ds * ds) - 1.0 / (2.0 * ds);
+        row[id(i, j, k)] += -(cl[i] + cr[i]) - 2.0 / (dth * dth) - 2.0 * is2 / (dph * dph);
+        if (i + 1 < nr) row[id(i + 1, j, k)] += cr[i];
+        if (i > 0) row[id(i - 1, j, k)] += cl[i];
         row[(j + 1 < nth) ? id(i, j + 1, k) : id(i, nth - 1, (k + half) % nph)] += 1.0 / (dth * dth) + cot2;
         row[(j > 0) ? id(i, j - 1, k) : id(i, 0, (k + half) % nph)] += 1.0 / (dth * dth) - cot2;
         row[id(i, j, (k + 1) % nph)] += is2 / (dph * dph);
@@ -649,19 +680,24 @@ void sph_level_matrix(int nr, int nth, int nph, double ds, std::vector<double>& 
     }
 }
 
-// Tables of the phi-line smoother for one level (layout in SLev): per
-// colatitude j the line operator is the periodic tridiagonal system
-// a x[k-1] + b x[k] + a x[k+1] with a = 1 / (sin^2 theta_j dphi^2) and b the
-// level diagonal; computed in FP64, stored FP32.
-bool line_tables(const SLev& L, double ds, std::vector<float>& tab) {
+// Tables of the phi-line smoother for one level (layout in SLev): line
+// (i, j) is the periodic tridiagonal system a x[k-1] + b x[k] + a x[k+1]
+// with a = 1 / (sin^2 theta_j dphi^2) and b the level diagonal
+// -(cl_i + cr_i) - 2/dtheta^2 - 2a (one table per j when the radial
+// couplings are constant, per (i, j) otherwise); computed in FP64, stored
+// FP32.
+bool line_tables(const SLev& L, const std::vector<double>& cl, const std::vector<double>& cr,
+                 std::vector<float>& tab) {
   const int SL = L.seg, Pn = L.nseg;
-  tab.assign((size_t)L.tstride * L.nth, 0.0f);
+  const int ni = L.tri ? L.nr : 1;
+  tab.assign((size_t)L.tstride * L.nth * ni, 0.0f);
   const double dth = M_PI / L.nth, dph = 2.0 * M_PI / L.nph;
   std::vector<double> m(SL), cp(SL), v(SL), w(SL), K, G;
+  for (int it = 0; it < ni; ++it)
   for (int j = 0; j < L.nth; ++j) {
     const double th = (j + 0.5) * dth;
     const double a = 1.0 / (sin(th) * sin(th) * dph * dph);
-    const double b = -2.0 / (ds * ds) - 2.0 / (dth * dth) - 2.0 * a;
+    const double b = -(cl[it] + cr[it]) - 2.0 / (dth * dth) - 2.0 * a;
     m[0] = 1.0 / b;
     cp[0] = a / b;
     for (int q = 1; q < SL; ++q) {
@@ -692,7 +728,7 @@ bool line_tables(const SLev& L, double ds, std::vector<float>& tab) {
       K[(size_t)(2 * sgi + 1) * n2 + xr] += a * w[SL - 1];
     }
     if (!invert_general(n2, K, G)) return false;
-    float* t = &tab[(size_t)j * L.tstride];
+    float* t = &tab[((size_t)it * L.nth + j) * L.tstride];
     for (int q = 0; q < SL; ++q) {
       t[q] = (float)m[q];
       t[SL + q] = (float)cp[q];
@@ -1560,11 +1596,20 @@ int poisson_plan(poisson_plan_t* out, const poisson_grid_t* grid, const poisson_
       }
       P->srj_host = rj;
     }
+    std::vector<double> lcl, lcr;
     for (size_t l = 0; l < P->slv.size(); ++l) {
       const SLev& L = P->slv[l];
       std::vector<float> c2(L.nth), is2(L.nth), tab;
+      sph_level_couplings(g, (int)l, L.nr, lcl, lcr);
+      std::vector<float> fcl(lcl.begin(), lcl.end()), fcr(lcr.begin(), lcr.end());
+      if (hipMemcpyAsync((void*)L.rcl, fcl.data(), sizeof(float) * L.nr, hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipMemcpyAsync((void*)L.rcr, fcr.data(), sizeof(float) * L.nr, hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess) {
+        set_error("upload of preconditioner radial couplings failed");
+        return fail(POISSON_EHIP);
+      }
       if (L.ltab) {
-        if (!line_tables(L, S.ds * (1 << l), tab)) {
+        if (!line_tables(L, lcl, lcr, tab)) {
           set_error("phi-line interface system is singular");
           return fail(POISSON_ENUMERIC);
         }
@@ -1590,9 +1635,9 @@ int poisson_plan(poisson_plan_t* out, const poisson_grid_t* grid, const poisson_
     }
     if (!P->slv.empty()) {
       const SLev& C = P->slv.back();
-      const double dsc = S.ds * (1 << (P->slv.size() - 1));
       std::vector<double> A, inv;
-      sph_level_matrix(C.nr, C.nth, C.nph, dsc, A);
+      sph_level_couplings(g, (int)P->slv.size() - 1, C.nr, lcl, lcr);
+      sph_level_matrix(C.nr, C.nth, C.nph, lcl, lcr, A);
       if (!invert_general(P->sncoarse, A, inv)) {
         set_error("coarsest preconditioner level is singular");
         return fail(POISSON_ENUMERIC);

@@ -187,12 +187,19 @@ def test_spai_order_and_ghost_validation():
 def test_radial_pad_validation():
     """Pads belong to spherical grids; the inner pad needs 0 < r_pad < r_in and
     a monotone quartic; at least two log-core unknowns remain; the FP32
-    multigrid preconditioner takes plain log grids only."""
+    FP32 multigrid preconditioner keeps one line-smoother table per radius
+    and colatitude when an inner pad bends the map, one per colatitude
+    otherwise."""
     lib = L.load()
     ok = pg.sph_grid(60, 8, 16, 0.5, 1.0, ext_in=8, ext_out=6, r_pad=0.3)
     assert lib.poisson_workspace_bytes(C.byref(ok), C.byref(pg.options("bicgstab"))) > 0
     assert lib.poisson_workspace_bytes(C.byref(ok), C.byref(pg.options("sor"))) > 0
-    assert lib.poisson_workspace_bytes(C.byref(ok), C.byref(pg.options("bicgstab_mg32"))) == 0
+    padded = lib.poisson_workspace_bytes(C.byref(ok), C.byref(pg.options("bicgstab_mg32")))
+    outer = lib.poisson_workspace_bytes(C.byref(pg.sph_grid(60, 8, 16, 0.5, 1.0, ext_out=6)),
+                                        C.byref(pg.options("bicgstab_mg32")))
+    plain = lib.poisson_workspace_bytes(C.byref(pg.sph_grid(60, 8, 16, 0.5, 1.0)),
+                                        C.byref(pg.options("bicgstab_mg32")))
+    assert padded > outer == plain > 0
     bad_pad = pg.sph_grid(60, 8, 16, 0.5, 1.0, ext_in=8, r_pad=0.6)
     assert lib.poisson_workspace_bytes(C.byref(bad_pad), C.byref(pg.options("bicgstab"))) == 0
     assert b"r_pad" in lib.poisson_last_error()
