@@ -86,6 +86,12 @@ extern "C" {
 #define POISSON_MG_SPAI32      7  /* POISSON_MG_SPAI with every level below the finest stored in
                                      FP32 and all arithmetic in FP64 (the paper's mixed
                                      precision, Section 2.1.3) */
+#define POISSON_PCG            8  /* Cartesian CG preconditioned by one symmetric multi-colour
+                                     Gauss-Seidel step from a zero guess (Section 2.1.2: two
+                                     colours for order 2, four for the 19-point star): the
+                                     section's block lower triangle B applied forward over the
+                                     colours, then backward (B D^-1 B^T, symmetric positive
+                                     definite as CG needs) */
 
 #define POISSON_OMEGA_OPT       0 /* 2/(1+sqrt(1-rJ^2)), rJ from Eq. rjac */
 #define POISSON_OMEGA_OPT_A     1 /* 2/(1+pi/N) */

@@ -16,10 +16,10 @@ import torch
 
 from . import _lib as L
 from ._lib import (BICGSTAB, BICGSTAB_MG32, CARTESIAN, CG, MG, MG_IR32, MG_SPAI, MG_SPAI32, OMEGA_CHEBYSHEV, OMEGA_FIXED,
-                   OMEGA_OPT, OMEGA_OPT_A, SOR, SPHERICAL_LOG, WARN_MAXITER)
+                   OMEGA_OPT, OMEGA_OPT_A, PCG, SOR, SPHERICAL_LOG, WARN_MAXITER)
 
 METHODS = {"sor": SOR, "cg": CG, "bicgstab": BICGSTAB, "mg": MG, "mg_ir32": MG_IR32,
-           "bicgstab_mg32": BICGSTAB_MG32, "mg_spai": MG_SPAI, "mg_spai32": MG_SPAI32}
+           "bicgstab_mg32": BICGSTAB_MG32, "mg_spai": MG_SPAI, "mg_spai32": MG_SPAI32, "pcg": PCG}
 
 
 class PoissonError(RuntimeError):

@@ -11,7 +11,7 @@ OK, WARN_MAXITER = 0, 1
 EINVAL, EGRID, EWORKSPACE, EHIP, ENUMERIC, EADMIT = -1, -2, -3, -4, -5, -6
 
 CARTESIAN, SPHERICAL_LOG = 0, 1
-SOR, CG, BICGSTAB, MG, MG_IR32, BICGSTAB_MG32, MG_SPAI, MG_SPAI32 = 0, 1, 2, 3, 4, 5, 6, 7
+SOR, CG, BICGSTAB, MG, MG_IR32, BICGSTAB_MG32, MG_SPAI, MG_SPAI32, PCG = 0, 1, 2, 3, 4, 5, 6, 7, 8
 OMEGA_OPT, OMEGA_OPT_A, OMEGA_CHEBYSHEV, OMEGA_FIXED = 0, 1, 2, 3
 
 

@@ -163,9 +163,13 @@ void split_to_dense(const void* split, bool f32, double* dense, const Geom& G, h
 // into scal->v[dst + slot]
 void finish_sum(const double* partial, int nb, int nslots, Scalars* scal, int dst, hipStream_t st);
 
-// CG (A = -L, zero-ghost direction vectors, split layout, FP64)
+// CG (A = -L, zero-ghost direction vectors, split layout, FP64).  The
+// direction is p_new = sr r + beta p_old (sr = 1: CG on r; sr = -1: PCG on
+// the preconditioned residual z, which has the opposite sign).
 void cg_direction_apply(const double* r, const double* p_old, double* p_new, double* q, const Geom& G,
-                        int order, const Scalars* scal, double* partial, hipStream_t st);
+                        int order, const Scalars* scal, double* partial, hipStream_t st, double sr = 1.0);
+// partial sums of -(r . z) over the unknowns (the PCG inner product)
+void pcg_dot(const double* r, const double* z, const Geom& G, double* partial, hipStream_t st);
 void cg_update(double* x, double* r, const double* p, const double* q, const Geom& G, const Scalars* scal,
                double* partial, hipStream_t st);
 void cg_scalars(const double* partial, int nb, Scalars* scal, int stage, hipStream_t st);

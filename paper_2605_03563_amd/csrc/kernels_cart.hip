@@ -986,12 +986,13 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(const double* __restr
 }
 
 // ---------------------------------------------------------------- CG (A = -L)
-// p_new = r + beta p_old;  q = A p_new;  partial (p_new . q).
-// scal: v[0] = rr (current r.r), v[2] = beta, v[3] = alpha.
+// p_new = sr r + beta p_old;  q = A p_new;  partial (p_new . q).
+// scal: v[0] = rr (current r.r, or the PCG inner product), v[2] = beta,
+// v[3] = alpha.
 template <int ORDER>
 __global__ __launch_bounds__(256) void k_cg_dir(const double* __restrict__ R, const double* __restrict__ Pold,
                                                 double* __restrict__ Pnew, double* __restrict__ Q, Geom G,
-                                                double ih2, const Scalars* __restrict__ scal,
+                                                double ih2, double sr, const Scalars* __restrict__ scal,
                                                 double* __restrict__ partial) {
   int bx, by, bz;
   xcd_block(bx, by, bz);
@@ -1005,7 +1006,7 @@ __global__ __launch_bounds__(256) void k_cg_dir(const double* __restrict__ R, co
     const int k1 = min(G.g + bz * kz + kz - 1, last);
     auto pv = [&](int aa, int bb, int kk) -> double {
       const long long i = G.at(aa, bb, kk);
-      return R[i] + beta * Pold[i];  // ghosts of R and Pold are zero
+      return sr * R[i] + beta * Pold[i];  // ghosts of R and Pold are zero
     };
     for (int k = G.g + bz * kz; k <= k1; ++k)
       for (int r = 0; r < G.C; ++r) {
@@ -1064,6 +1065,31 @@ __global__ __launch_bounds__(256) void k_cg_upd(double* __restrict__ X, double* 
   }
   const double s = block_sum(acc);
   if (threadIdx.x == 0 && threadIdx.y == 0) partial[linear_block()] = s;
+}
+
+// partial sums of -(r . z): with the CG residual rho = -r and the
+// preconditioned residual zeta = z, the inner product rho . zeta.
+__global__ __launch_bounds__(256) void k_pcg_dot(const double* __restrict__ R, const double* __restrict__ Z, Geom G,
+                                                 double* __restrict__ partial) {
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int m = G.mlo() + bx * BX + (int)threadIdx.x;
+  const int b = G.g + by * BY + (int)threadIdx.y;
+  const int last = G.g + G.n - 2;
+  double acc = 0.0;
+  if (m <= G.mhi() && b <= last) {
+    const int kz = planes_per_block(G);
+    const int k1 = min(G.g + bz * kz + kz - 1, last);
+    for (int k = G.g + bz * kz; k <= k1; ++k)
+      for (int r = 0; r < G.C; ++r) {
+        const int a = (m << G.lc) + r;
+        if (!G.inner(a)) continue;
+        const long long i = G.at(a, b, k);
+        acc += R[i] * Z[i];
+      }
+  }
+  const double s = block_sum(acc);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partial[linear_block()] = -s;
 }
 
 // stage 0: v[4] = p.q (summed) -> alpha = rr / pq
@@ -1306,12 +1332,16 @@ void finish_sum(const double* partial, int nb, int nslots, Scalars* scal, int ds
 int cg_blocks(const Geom& G) { return (int)nblocks(col_grid(G)); }
 
 void cg_direction_apply(const double* r, const double* p_old, double* p_new, double* q, const Geom& G, int order,
-                        const Scalars* scal, double* partial, hipStream_t st) {
+                        const Scalars* scal, double* partial, hipStream_t st, double sr) {
   const double ih2 = 1.0 / (G.h * G.h);
   if (order == 2)
-    k_cg_dir<2><<<col_grid(G), dim3(BX, BY), 0, st>>>(r, p_old, p_new, q, G, ih2, scal, partial);
+    k_cg_dir<2><<<col_grid(G), dim3(BX, BY), 0, st>>>(r, p_old, p_new, q, G, ih2, sr, scal, partial);
   else
-    k_cg_dir<6><<<col_grid(G), dim3(BX, BY), 0, st>>>(r, p_old, p_new, q, G, ih2, scal, partial);
+    k_cg_dir<6><<<col_grid(G), dim3(BX, BY), 0, st>>>(r, p_old, p_new, q, G, ih2, sr, scal, partial);
+}
+
+void pcg_dot(const double* r, const double* z, const Geom& G, double* partial, hipStream_t st) {
+  k_pcg_dot<<<col_grid(G), dim3(BX, BY), 0, st>>>(r, z, G, partial);
 }
 
 void cg_update(double* x, double* r, const double* p, const double* q, const Geom& G, const Scalars* scal,

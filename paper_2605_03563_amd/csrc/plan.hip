@@ -370,6 +370,7 @@ int validate(const poisson_grid_t* g, const poisson_opts_t* o) {
       }
       break;
     case POISSON_CG:
+    case POISSON_PCG:
       break;
     case POISSON_MG:
     case POISSON_MG_IR32:
@@ -497,11 +498,12 @@ void carve(poisson_plan_s* P, Carver& cv) {
   P->phi64 = (double*)cv.take(b64);
   P->f64 = (double*)cv.take(b64);
   P->t64 = (double*)cv.take(b64);
-  if (o.method == POISSON_CG) {
+  if (o.method == POISSON_CG || o.method == POISSON_PCG) {
     P->cr = (double*)cv.take(b64);
     P->cp0 = (double*)cv.take(b64);
     P->cp1 = (double*)cv.take(b64);
     P->cq = (double*)cv.take(b64);
+    if (o.method == POISSON_PCG) P->cz = (double*)cv.take(b64);
   }
   if (o.method == POISSON_MG || o.method == POISSON_MG_IR32) {
     P->mg32 = o.method == POISSON_MG_IR32;
@@ -1040,6 +1042,21 @@ double rel_of(double r2, double bnorm) {
   return bnorm > 0.0 ? r / bnorm : r;
 }
 
+// One symmetric multi-colour Gauss-Seidel step for L z = r from z = 0 with
+// zero ghosts (Section 2.1.2): colours 0 .. C-1 forward, each reading only
+// the colours already updated (the later ones are still zero), then
+// C-2 .. 0 backward; the backward sweep's first colour would repeat the
+// forward sweep's last from unchanged neighbours and is left out.
+void pcg_precondition(poisson_plan_s* P, hipStream_t st) {
+  const Geom& G = P->G0;
+  const int C = P->order == 2 ? 2 : 4;
+  for (int c = 0; c < C; ++c) {
+    const int zmask = ((1 << C) - 1) & ~((2 << c) - 1);  // colours above c
+    colour_pass(P->cz, P->cr, false, G, P->order, c, 1.0, st, zmask);
+  }
+  for (int c = C - 2; c >= 0; --c) colour_pass(P->cz, P->cr, false, G, P->order, c, 1.0, st);
+}
+
 // ------------------------------------------------------------ Cartesian solve
 int cart_setup_impl(poisson_plan_s* P, const double* rho, double* phi) {
   const poisson_grid_t& g = P->grid;
@@ -1060,7 +1077,7 @@ int cart_setup_impl(poisson_plan_s* P, const double* rho, double* phi) {
   if (o.method == POISSON_MG_IR32) {
     rout = P->lv[0].f;
     rout32 = true;
-  } else if (o.method == POISSON_CG) {
+  } else if (o.method == POISSON_CG || o.method == POISSON_PCG) {
     rout = P->cr;
   }
   residual(P->phi64, P->f64, false, rout, rout32, G, P->order, false, P->partial, st);
@@ -1167,6 +1184,42 @@ int solve_cart(poisson_plan_s* P, const double* rho, double* phi, double tol, po
         T.push(rel);
         if (!isfinite(rel)) {
           set_error("SOR diverged (non-finite residual)");
+          return POISSON_ENUMERIC;
+        }
+        conv = rel <= tol;
+      }
+    }
+  } else if (o.method == POISSON_PCG) {
+    // z = M^-1 rho by one symmetric multi-colour Gauss-Seidel step on
+    // L z = r (r = -rho) from z = 0; the direction is built from -z so the
+    // CG kernels keep their signs (x -= alpha p, r -= alpha q); the inner
+    // product rho . zeta = -(r . z) sits in v[kRR], ||r||^2 in v[kRes2].
+    const int cb = cg_blocks(G);
+    pcg_precondition(P, st);
+    pcg_dot(P->cr, P->cz, G, P->partial, st);
+    finish_sum(P->partial, cb, 1, P->scal, kRR, st);
+    const double zero = 0.0;
+    HIPCHK(hipMemcpyAsync(&P->scal->v[2], &zero, sizeof(double), hipMemcpyHostToDevice, st));
+    fill_zero(P->cp0, false, G.total(), st);
+    double* pold = P->cp0;
+    double* pnew = P->cp1;
+    while (!conv && it < o.max_iter) {
+      cg_direction_apply(P->cz, pold, pnew, P->cq, G, P->order, P->scal, P->partial, st, -1.0);
+      cg_scalars(P->partial, cb, P->scal, 0, st);
+      cg_update(P->phi64, P->cr, pnew, P->cq, G, P->scal, P->partial, st);
+      finish_sum(P->partial, cb, 1, P->scal, kRes2, st);
+      pcg_precondition(P, st);
+      pcg_dot(P->cr, P->cz, G, P->partial, st);
+      cg_scalars(P->partial, cb, P->scal, 1, st);
+      std::swap(pold, pnew);
+      ++it;
+      if (it % o.check_every == 0 || it == o.max_iter) {
+        CHK(launch_check("PCG"));
+        CHK(read_scalars(P, kRes2, 1));
+        rel = rel_of(P->host[0], T.bnorm);
+        T.push(rel);
+        if (!isfinite(rel)) {
+          set_error("PCG breakdown (non-finite residual)");
           return POISSON_ENUMERIC;
         }
         conv = rel <= tol;

@@ -54,6 +54,7 @@ struct poisson_plan_s {
   std::vector<psn::NLevel> nlv;
   // CG
   double *cr = nullptr, *cp0 = nullptr, *cp1 = nullptr, *cq = nullptr;
+  double* cz = nullptr;  // PCG: preconditioned residual
   // spherical
   psn::SGeom S{};
   psn::SphCoef sc{};

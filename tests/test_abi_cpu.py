@@ -211,3 +211,16 @@ def test_radial_pad_validation():
     cart = pg.cart_grid(32)
     cart.ext_in = 2
     assert lib.poisson_workspace_bytes(C.byref(cart), C.byref(pg.options("mg"))) == 0
+
+
+def test_pcg_workspace_and_validation():
+    """PCG keeps one more FP64 array than CG (the preconditioned residual),
+    takes both Cartesian orders, and is not a spherical method."""
+    lib = L.load()
+    g = pg.cart_grid(64)
+    cg = lib.poisson_workspace_bytes(C.byref(g), C.byref(pg.options("cg")))
+    pcg = lib.poisson_workspace_bytes(C.byref(g), C.byref(pg.options("pcg")))
+    assert pcg > cg > 0
+    g3 = pg.cart_grid(64, ghost=3)
+    assert lib.poisson_workspace_bytes(C.byref(g3), C.byref(pg.options("pcg", order=6))) > 0
+    assert lib.poisson_workspace_bytes(C.byref(pg.sph_grid(16, 8, 16)), C.byref(pg.options("pcg"))) == 0
