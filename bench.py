@@ -88,8 +88,10 @@ def _time_solves(plan, rho, phi, tol, steps, warmup):
 def bench_c1(args):
     """32^3 cells, uniform sphere of radius 0.25 (rho = 1), multipole
     boundary with lmax 4, red-black SOR at omega_opt (and with the Chebyshev
-    sequence) and CG to 1e-10; errors against the analytic potential and the
-    oracle's exact discrete solution."""
+    sequence), CG and CG preconditioned by symmetric red-black Gauss-Seidel
+    to 1e-10; errors against the analytic potential and the oracle's exact
+    discrete solution.  Beside it, CG against PCG on the 255^3 clump field
+    (7-point) to 1e-8."""
     import torch
 
     import paper_2605_03563_amd as pg
@@ -111,7 +113,7 @@ def bench_c1(args):
     s = slice(1, n)
     rows = []
     for name, method, kw in (("sor_omega_opt", "sor", {}), ("sor_chebyshev", "sor", {"omega_mode": pg.OMEGA_CHEBYSHEV}),
-                             ("cg", "cg", {})):
+                             ("pcg_sgs", "pcg", {}), ("cg", "cg", {})):
         plan = pg.Plan(pg.cart_grid(n), pg.options(method, lmax=lmax, max_iter=100000, **kw), device=dev)
         phi = torch.zeros_like(rho)
         sec, res = _time_solves(plan, rho, phi, tol, args.steps, args.warmup)
@@ -123,13 +125,24 @@ def bench_c1(args):
                      "err_vs_analytic_rel_l2": float(np.linalg.norm(got[s, s, s] - ana) / np.linalg.norm(ana))})
         del plan
     cg = rows[-1]
+    # preconditioned against plain CG where the grid is large enough for the
+    # per-iteration cost to matter: 255^3 unknowns, C2's clump density
+    big = W.config_c2(n=256, device=dev)
+    study = []
+    for method in ("cg", "pcg"):
+        plan = pg.Plan(pg.cart_grid(256), pg.options(method, lmax=8, max_iter=20000, check_every=10), device=dev)
+        phi = torch.zeros_like(big.rho)
+        sec, res = _time_solves(plan, big.rho.contiguous(), phi, 1e-8, 1, 1)
+        study.append({"solver": method, "iterations": res.iterations, "converged": res.converged,
+                      "time_to_1e-8_ms": sec * 1e3, "ms_per_iteration": res.t_iter_ms / max(1, res.iterations)})
+        del plan, phi
     out = {
         "metric": "Gcell-updates/s", "value": (n - 1) ** 3 * cg["iterations"] / (cg["time_to_1e-10_ms"] * 1e-3) / 1e9,
         "unit": "Gcell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": cg["time_to_1e-10_ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "c1_uniform_sphere_32^3_lmax4_cg_and_sor_tol1e-10", "unknowns": (n - 1) ** 3},
-        "rows": rows,
+        "rows": rows, "cg_vs_pcg_255": study,
     }
     print(json.dumps(out), flush=True)
 
@@ -233,17 +246,23 @@ def c4(args):
     # the same core with the padding of Section 3.3: 20 inner cells along the
     # quartic down to r_min / 2 and 20 outer log cells, density zero in the
     # pads (the core's density copied in); BiCGSTAB with the Gauss-Seidel
-    # preconditioner (the FP32 multigrid preconditioner is log-grid only)
-    ext = 20
-    nr_pad = g.nr + 2 * (ext - 1)
-    gpad = pg.sph_grid(nr_pad, g.nth, g.nph, g.r_min, g.r_max, ext_in=ext, ext_out=ext, r_pad=g.r_min / 2)
-    rho_pad = torch.zeros((g.nph, g.nth, nr_pad + 2), dtype=torch.float64, device=dev)
-    rho_pad[:, :, ext:ext + g.nr] = rho[:, :, 1:g.nr + 1]
-    plan = pg.Plan(gpad, pg.options("bicgstab", lmax=8, point_mass=4 * math.pi * g.r_min, max_iter=20000,
-                                    check_every=10), device=dev)
-    phi = torch.zeros_like(rho_pad)
-    spad, rpad = _time_solves(plan, rho_pad, phi, args.tol, 1, 1)
-    del plan, phi, rho_pad
+    # preconditioner; then with the FP32 multigrid one, whose levels need a
+    # radial count that halves five times: 14 outer cells (288 unknowns)
+    def padded(method, ext_in, ext_out, check_every):
+        nr_pad = g.nr + (ext_in - 1) + (ext_out - 1)
+        gpad = pg.sph_grid(nr_pad, g.nth, g.nph, g.r_min, g.r_max, ext_in=ext_in, ext_out=ext_out,
+                           r_pad=g.r_min / 2)
+        rho_pad = torch.zeros((g.nph, g.nth, nr_pad + 2), dtype=torch.float64, device=dev)
+        rho_pad[:, :, ext_in:ext_in + g.nr] = rho[:, :, 1:g.nr + 1]
+        plan = pg.Plan(gpad, pg.options(method, lmax=8, point_mass=4 * math.pi * g.r_min, max_iter=20000,
+                                        check_every=check_every), device=dev)
+        phi = torch.zeros_like(rho_pad)
+        sp, rp = _time_solves(plan, rho_pad, phi, args.tol, 1, 1)
+        return {"radial_unknowns": nr_pad, "ext_in": ext_in, "ext_out": ext_out, "r_pad": g.r_min / 2,
+                "time_to_1e-8_ms": sp * 1e3, "iterations": rp.iterations, "converged": rp.converged,
+                "ms_per_iteration": rp.t_iter_ms / max(1, rp.iterations)}
+    pad_gs = padded("bicgstab", 20, 20, 10)
+    pad_mg = padded("bicgstab_mg32", 20, 14, 1)
     sec, res, steps = runs["bicgstab_mg32"]
     sgs, rgs, _ = runs["bicgstab"]
     gs_it_ms = rgs.t_iter_ms / max(1, rgs.iterations)
@@ -263,10 +282,8 @@ def c4(args):
         "sor_local_chebyshev": {"time_ms": ssor * 1e3, "converged": rsor.converged, "sweeps": rsor.iterations,
                                 "rel_residual": rsor.rel_residual,
                                 "ms_per_sweep": rsor.t_iter_ms / max(1, rsor.iterations)},
-        "padded_grid_gs_bicgstab": {"radial_unknowns": nr_pad, "ext_in": ext, "ext_out": ext,
-                                    "r_pad": g.r_min / 2, "time_to_1e-8_ms": spad * 1e3,
-                                    "iterations": rpad.iterations, "converged": rpad.converged,
-                                    "ms_per_iteration": rpad.t_iter_ms / max(1, rpad.iterations)},
+        "padded_grid_gs_bicgstab": pad_gs,
+        "padded_grid_fp32mg_bicgstab": pad_mg,
     }
     print(json.dumps(out), flush=True)
 
