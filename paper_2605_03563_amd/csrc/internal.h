@@ -137,20 +137,26 @@ void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, i
 
 // r = f - L phi on the unknowns (split in, split out or nullptr); partial sums
 // of r^2 go to partial[kReduceBlocks].  zero_unknowns_in treats the unknowns of
-// phi as 0 (norm of b).  out_f32 selects the output precision.
+// phi as 0 (norm of b).  out_f32 selects the output precision.  colour 0 / 1
+// (7-point only): only that colour's residual, the other one being known to
+// vanish (right after a Gauss-Seidel pass over it).
 void residual(const void* phi, const void* f, bool in_f32, void* r_out, bool out_f32, const Geom& G,
-              int order, bool zero_unknowns_in, double* partial, hipStream_t st);
+              int order, bool zero_unknowns_in, double* partial, hipStream_t st, int colour = -1);
 int residual_blocks(const Geom& G);   // partials written by residual()
 // f_coarse = R (f - L phi) for the 7-point operator without storing the fine
 // residual; resrestrict_ok tells whether the level's shape is supported
 // (two colours, one ghost layer, at most 256 intervals)
 bool resrestrict_ok(const Geom& Gf);
+// r0only: the colour-1 residuals vanish (a Gauss-Seidel pass over colour 1
+// came last) and only the colour-0 ones are formed.
 void resrestrict(const void* phi, const void* f, bool f32, const Geom& Gf, void* f_coarse, const Geom& Gc,
-                 hipStream_t st);
+                 hipStream_t st, bool r0only = false);
 void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom& Gc, bool f32,
                  hipStream_t st);
+// c0only (two-colour levels): correct colour-0 nodes only, when a
+// Gauss-Seidel pass over colour 1 follows and overwrites the others.
 void prolong_add(const void* e_coarse, const Geom& Gc, void* phi_fine, const Geom& Gf, bool f32,
-                 hipStream_t st);
+                 hipStream_t st, bool c0only = false);
 void coarse_solve(const double* inv, const void* f, void* phi, bool f32, const Geom& G, hipStream_t st);
 // phi64 (unknowns) += e (f32 or f64)
 void add_correction(double* phi, const void* e, bool e_f32, const Geom& G, hipStream_t st);

@@ -428,8 +428,11 @@ __global__ __launch_bounds__(512) void k_residual(const T* __restrict__ X, const
 // x-neighbour loads, four y-neighbour loads and the two right-hand sides.  As
 // in the colour pass, the loop is unrolled at compile time, load indices past
 // k1 are clamped into the array and only the stores and sums are predicated,
-// so the loads of all planes can be in flight together.
-template <typename T, typename TO, int KZP>
+// so the loads of all planes can be in flight together.  COL >= 0: only the
+// nodes of colour COL (the other colour's residual is known to vanish, e.g.
+// right after a Gauss-Seidel pass over it), with only their neighbour and
+// right-hand-side loads.
+template <typename T, typename TO, int KZP, int COL>
 __global__ __launch_bounds__(256) void k_residual7(const T* __restrict__ X, const T* __restrict__ F,
                                                    TO* __restrict__ R, Geom G, T ih2,
                                                    double* __restrict__ partial) {
@@ -468,14 +471,19 @@ __global__ __launch_bounds__(256) void k_residual7(const T* __restrict__ X, cons
         const long long o = (long long)k * plane;
         const long long sa = (long long)((b + k + G.off) & 1) * G.cs;  // colour of A = 2m
         const long long sb = G.cs - sa;                                 // colour of B = 2m+1
-        xl[t] = X[sb + q0 + o - 1];  // A's left neighbour (B's colour)
-        xr[t] = X[sa + q0 + o + 1];  // B's right neighbour (A's colour)
-        yb0[t] = X[sb + q0 + o - W];
-        yb1[t] = X[sb + q0 + o + W];
-        ya0[t] = X[sa + q0 + o - W];
-        ya1[t] = X[sa + q0 + o + W];
-        fa[t] = F[sa + q0 + o];
-        fb[t] = F[sb + q0 + o];
+        const bool doA = COL < 0 || ((b + k + G.off) & 1) == COL;
+        if (doA) {
+          xl[t] = X[sb + q0 + o - 1];  // A's left neighbour (B's colour)
+          yb0[t] = X[sb + q0 + o - W];
+          yb1[t] = X[sb + q0 + o + W];
+          fa[t] = F[sa + q0 + o];
+        }
+        if (COL < 0 || !doA) {
+          xr[t] = X[sa + q0 + o + 1];  // B's right neighbour (A's colour)
+          ya0[t] = X[sa + q0 + o - W];
+          ya1[t] = X[sa + q0 + o + W];
+          fb[t] = F[sb + q0 + o];
+        }
       }
 #pragma unroll
       for (int t = c0; t < c0 + CH; ++t) {
@@ -487,14 +495,14 @@ __global__ __launch_bounds__(256) void k_residual7(const T* __restrict__ X, cons
           // z-neighbours of A have B's colour and vice versa
           const T zbA = s ? z0[t] + z0[t + 2] : z1[t] + z1[t + 2];
           const T zbB = s ? z1[t] + z1[t + 2] : z0[t] + z0[t + 2];
-          if (inA) {
+          if (inA && (COL < 0 || s == COL)) {
             const T sx = xl[t] + uB;
             const T sy = yb0[t] + yb1[t] + zbA;
             const T res = fa[t] - ((sx + sy) - (T)6 * uA) * ih2;
             if (R) R[(long long)s * G.cs + q0 + o] = (TO)res;
             acc += (double)res * (double)res;
           }
-          if (inB) {
+          if (inB && (COL < 0 || s != COL)) {
             const T sx = uA + xr[t];
             const T sy = ya0[t] + ya1[t] + zbB;
             const T res = fb[t] - ((sx + sy) - (T)6 * uB) * ih2;
@@ -550,8 +558,11 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ Rf, Geom
 // and the z weights 1/4, 1/2, 1/4 accumulate in registers; a coarse plane is
 // written when its last fine plane is done.  The loads of the next fine plane
 // are issued before the current one's LDS stages, all loads are clamped into
-// the array, and rows or nodes outside the unknowns contribute zero.
-template <typename T, int BXR, int TYC, int KZC>
+// the array, and rows or nodes outside the unknowns contribute zero.  R0:
+// the colour-1 residuals are known to vanish (the level was just swept by a
+// Gauss-Seidel pass over colour 1), so only colour-0 residuals are formed and
+// only their neighbours and right-hand sides are loaded.
+template <typename T, int BXR, int TYC, int KZC, bool R0>
 __global__ __launch_bounds__(BXR*(2 * TYC + 1)) void k_resrestrict7(const T* __restrict__ X,
                                                                     const T* __restrict__ F, Geom Gf,
                                                                     T* __restrict__ Fc, Geom Gc, T ih2) {
@@ -584,21 +595,25 @@ __global__ __launch_bounds__(BXR*(2 * TYC + 1)) void k_resrestrict7(const T* __r
     T hi0, hi1, xl, xr, ya0, ya1, yb0, yb1, fa, fb;
   };
   auto load = [&](int k) {
-    Ld v;
+    Ld v{};
     const long long oz = (long long)min(k + 1, n) * plane;
     v.hi0 = x0[oz];
     v.hi1 = x1[oz];
     const long long o = (long long)k * plane;
     const long long sa = (long long)((bl + k + Gf.off) & 1) * Gf.cs;  // colour of node 2m
     const long long sb = Gf.cs - sa;
-    v.xl = X[sb + q0 + o - 1];
-    v.xr = X[sa + q0 + o + 1];
-    v.yb0 = X[sb + q0 + o - W];
-    v.yb1 = X[sb + q0 + o + W];
-    v.ya0 = X[sa + q0 + o - W];
-    v.ya1 = X[sa + q0 + o + W];
-    v.fa = F[sa + q0 + o];
-    v.fb = F[sb + q0 + o];
+    if (!R0 || sa == 0) {
+      v.xl = X[sb + q0 + o - 1];
+      v.yb0 = X[sb + q0 + o - W];
+      v.yb1 = X[sb + q0 + o + W];
+      v.fa = F[sa + q0 + o];
+    }
+    if (!R0 || sa != 0) {
+      v.xr = X[sa + q0 + o + 1];
+      v.ya0 = X[sa + q0 + o - W];
+      v.ya1 = X[sa + q0 + o + W];
+      v.fb = F[sb + q0 + o];
+    }
     return v;
   };
   T lo0 = x0[(long long)(kf0 - 1) * plane], lo1 = x1[(long long)(kf0 - 1) * plane];
@@ -613,12 +628,12 @@ __global__ __launch_bounds__(BXR*(2 * TYC + 1)) void k_resrestrict7(const T* __r
     const int s = (bl + k + Gf.off) & 1;
     const T uA = s ? cu1 : cu0, uB = s ? cu0 : cu1;
     T rA = (T)0, rB = (T)0;
-    if (inA) {
+    if (inA && (!R0 || s == 0)) {
       const T sx = cur.xl + uB;
       const T sy = cur.yb0 + cur.yb1 + (s ? lo0 + cur.hi0 : lo1 + cur.hi1);
       rA = cur.fa - ((sx + sy) - (T)6 * uA) * ih2;
     }
-    if (inB) {
+    if (inB && (!R0 || s != 0)) {
       const T sx = uA + cur.xr;
       const T sy = cur.ya0 + cur.ya1 + (s ? lo1 + cur.hi1 : lo0 + cur.hi0);
       rB = cur.fb - ((sx + sy) - (T)6 * uB) * ih2;
@@ -650,25 +665,30 @@ __global__ __launch_bounds__(BXR*(2 * TYC + 1)) void k_resrestrict7(const T* __r
 }
 
 template <typename T, int BXR, int TYC, int KZC>
-static void resrestrict7_go(const T* phi, const T* f, const Geom& Gf, T* fc, const Geom& Gc, hipStream_t st) {
+static void resrestrict7_go(const T* phi, const T* f, const Geom& Gf, T* fc, const Geom& Gc, bool r0,
+                            hipStream_t st) {
   const int nc = Gc.n;
   const T ih2 = (T)(1.0 / (Gf.h * Gf.h));
-  const dim3 grid(1, (nc - 1 + TYC - 1) / TYC, (nc - 1 + KZC - 1) / KZC);
-  k_resrestrict7<T, BXR, TYC, KZC><<<grid, dim3(BXR, 2 * TYC + 1), 0, st>>>(phi, f, Gf, fc, Gc, ih2);
+  const dim3 grid(1, (nc - 1 + TYC - 1) / TYC, (nc - 1 + KZC - 1) / KZC), blk(BXR, 2 * TYC + 1);
+  if (r0)
+    k_resrestrict7<T, BXR, TYC, KZC, true><<<grid, blk, 0, st>>>(phi, f, Gf, fc, Gc, ih2);
+  else
+    k_resrestrict7<T, BXR, TYC, KZC, false><<<grid, blk, 0, st>>>(phi, f, Gf, fc, Gc, ih2);
 }
 
 // Large levels: several coarse rows and planes per block (little recomputed
 // halo); small levels: one coarse row and plane per block (short dependent
 // chains, many blocks).
 template <typename T>
-static void resrestrict7_t(const T* phi, const T* f, const Geom& Gf, T* fc, const Geom& Gc, hipStream_t st) {
+static void resrestrict7_t(const T* phi, const T* f, const Geom& Gf, T* fc, const Geom& Gc, bool r0,
+                           hipStream_t st) {
   const int mc = Gf.mhi() + 1;
   if (mc <= 32)
-    resrestrict7_go<T, 64, 1, 1>(phi, f, Gf, fc, Gc, st);
+    resrestrict7_go<T, 64, 1, 1>(phi, f, Gf, fc, Gc, r0, st);
   else if (mc <= 64)
-    resrestrict7_go<T, 64, 1, 4>(phi, f, Gf, fc, Gc, st);
+    resrestrict7_go<T, 64, 1, 4>(phi, f, Gf, fc, Gc, r0, st);
   else
-    resrestrict7_go<T, 128, 2, 4>(phi, f, Gf, fc, Gc, st);
+    resrestrict7_go<T, 128, 2, 4>(phi, f, Gf, fc, Gc, r0, st);
 }
 
 // phi_fine += P e_coarse, P = 8 R^T (trilinear interpolation).  One thread
@@ -793,8 +813,10 @@ __global__ __launch_bounds__(256) void k_prolong4(const T* __restrict__ Ec, Geom
 // Two-colour (7-point hierarchy, one ghost layer) prolongation: the fine
 // nodes 2m and 2m+1 of a row need the coarse values at coarse columns m and
 // m+1 of one or two coarse rows on one or two coarse planes; the coarse plane
-// values are cached in registers while the thread marches fine planes.
-template <typename T>
+// values are cached in registers while the thread marches fine planes.  C0:
+// only colour-0 nodes are corrected (a Gauss-Seidel pass over colour 1,
+// which reads no colour-1 value, follows and overwrites the rest).
+template <typename T, bool C0>
 __global__ __launch_bounds__(256) void k_prolong2(const T* __restrict__ Ec, Geom Gc, T* __restrict__ Xf, Geom Gf) {
   int bx, by, bz;
   xcd_block(bx, by, bz);
@@ -854,8 +876,8 @@ __global__ __launch_bounds__(256) void k_prolong2(const T* __restrict__ Ec, Geom
     }
     const int s = (b + k + Gf.off) & 1;  // colour of fine node 2m
     const long long row = Gf.row(b, k);
-    if (inA) Xf[(long long)s * Gf.cs + row + m] += em;
-    if (inB) Xf[(long long)(s ^ 1) * Gf.cs + row + m] += half * (em + ep);
+    if (inA && (!C0 || s == 0)) Xf[(long long)s * Gf.cs + row + m] += em;
+    if (inB && (!C0 || s != 0)) Xf[(long long)(s ^ 1) * Gf.cs + row + m] += half * (em + ep);
   }
 }
 
@@ -1212,19 +1234,29 @@ void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, i
   }
 }
 
+template <typename T, typename TO, int COL>
+static void residual7_col(const T* phi, const T* f, TO* r, const Geom& G, T ih2, double* partial, hipStream_t st) {
+  const dim3 grid = col_grid(G), blk(BX, BY);
+  if (kz_for(G) == KZ)
+    k_residual7<T, TO, KZ, COL><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
+  else
+    k_residual7<T, TO, 1, COL><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
+}
+
 template <typename T, typename TO>
 static void residual_t(const T* phi, const T* f, TO* r, const Geom& G, int order, bool zu, double* partial,
-                       hipStream_t st) {
+                       int colour, hipStream_t st) {
   const dim3 grid = col_grid(G), blk(BX, BY);
   const T ih2 = (T)(1.0 / (G.h * G.h));
   if (order == 2) {
     if (zu)
       k_residual<T, TO, 2, true><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
+    else if (colour == 0)
+      residual7_col<T, TO, 0>(phi, f, r, G, ih2, partial, st);
+    else if (colour == 1)
+      residual7_col<T, TO, 1>(phi, f, r, G, ih2, partial, st);
     else
-      if (kz_for(G) == KZ)
-        k_residual7<T, TO, KZ><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
-      else
-        k_residual7<T, TO, 1><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
+      residual7_col<T, TO, -1>(phi, f, r, G, ih2, partial, st);
   } else {
     // both variants launch on the staged grid so that partial-sum counts agree
     const dim3 sg = staged_grid(G), sb(BX, TBY);
@@ -1238,25 +1270,26 @@ static void residual_t(const T* phi, const T* f, TO* r, const Geom& G, int order
 int residual_blocks(const Geom& G) { return (int)nblocks(G.C == 4 ? staged_grid(G) : col_grid(G)); }
 
 void residual(const void* phi, const void* f, bool in_f32, void* r_out, bool out_f32, const Geom& G, int order,
-              bool zu, double* partial, hipStream_t st) {
+              bool zu, double* partial, hipStream_t st, int colour) {
   if (in_f32) {
-    residual_t<float, float>((const float*)phi, (const float*)f, (float*)r_out, G, order, zu, partial, st);
+    residual_t<float, float>((const float*)phi, (const float*)f, (float*)r_out, G, order, zu, partial, colour, st);
   } else if (out_f32) {
-    residual_t<double, float>((const double*)phi, (const double*)f, (float*)r_out, G, order, zu, partial, st);
+    residual_t<double, float>((const double*)phi, (const double*)f, (float*)r_out, G, order, zu, partial, colour,
+                              st);
   } else {
     residual_t<double, double>((const double*)phi, (const double*)f, (double*)r_out, G, order, zu, partial,
-                               st);
+                               colour, st);
   }
 }
 
 bool resrestrict_ok(const Geom& Gf) { return Gf.C == 2 && Gf.g == 1 && Gf.n >= 4 && Gf.mhi() + 1 <= 128; }
 
 void resrestrict(const void* phi, const void* f, bool f32, const Geom& Gf, void* f_coarse, const Geom& Gc,
-                 hipStream_t st) {
+                 hipStream_t st, bool r0only) {
   if (f32)
-    resrestrict7_t<float>((const float*)phi, (const float*)f, Gf, (float*)f_coarse, Gc, st);
+    resrestrict7_t<float>((const float*)phi, (const float*)f, Gf, (float*)f_coarse, Gc, r0only, st);
   else
-    resrestrict7_t<double>((const double*)phi, (const double*)f, Gf, (double*)f_coarse, Gc, st);
+    resrestrict7_t<double>((const double*)phi, (const double*)f, Gf, (double*)f_coarse, Gc, r0only, st);
 }
 
 void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom& Gc, bool f32, hipStream_t st) {
@@ -1268,13 +1301,20 @@ void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom&
 }
 
 void prolong_add(const void* e_coarse, const Geom& Gc, void* phi_fine, const Geom& Gf, bool f32,
-                 hipStream_t st) {
+                 hipStream_t st, bool c0only) {
   const dim3 grid = col_grid(Gf), blk(BX, BY);
   if (Gf.C == 2 && Gf.g == 1) {
-    if (f32)
-      k_prolong2<float><<<grid, blk, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
-    else
-      k_prolong2<double><<<grid, blk, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
+    if (f32) {
+      if (c0only)
+        k_prolong2<float, true><<<grid, blk, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
+      else
+        k_prolong2<float, false><<<grid, blk, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
+    } else {
+      if (c0only)
+        k_prolong2<double, true><<<grid, blk, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
+      else
+        k_prolong2<double, false><<<grid, blk, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
+    }
     return;
   }
   if (Gf.C == 4) {

@@ -793,7 +793,11 @@ void w4_matrix(const W4& w, int n, std::vector<double>& A) {
 // One V(nu1, nu2) cycle from level l down.  zero_guess: the level's
 // unknowns start at zero (every coarse correction, and the FP32 correction of
 // a refinement step), so the first forward sweep reads colours it has not yet
-// updated as zero instead of clearing the array first.
+// updated as zero instead of clearing the array first.  On two-colour levels
+// a Gauss-Seidel pass leaves its colour's residual at zero: after the
+// pre-smoothing (last colour 1) only colour-0 residuals are restricted, and
+// the correction goes to colour-0 nodes only, since the first post-smoothing
+// pass (colour 1) reads no colour-1 value and overwrites them all.
 void vcycle(poisson_plan_s* P, int l, bool zero_guess, hipStream_t st) {
   Level& L = P->lv[l];
   const bool f32 = P->mg32;
@@ -812,13 +816,13 @@ void vcycle(poisson_plan_s* P, int l, bool zero_guess, hipStream_t st) {
     }
   Level& Lc = P->lv[l + 1];
   if (P->order == 2 && resrestrict_ok(L.G)) {
-    resrestrict(L.phi, L.f, f32, L.G, Lc.f, Lc.G, st);
+    resrestrict(L.phi, L.f, f32, L.G, Lc.f, Lc.G, st, o.nu1 > 0);
   } else {
     residual(L.phi, L.f, f32, L.tmp, f32, L.G, P->order, false, nullptr, st);
     restrict_fw(L.tmp, L.G, Lc.f, Lc.G, f32, st);
   }
   vcycle(P, l + 1, true, st);
-  prolong_add(Lc.phi, Lc.G, L.phi, L.G, f32, st);
+  prolong_add(Lc.phi, Lc.G, L.phi, L.G, f32, st, C == 2 && o.nu2 > 0);
   for (int s = 0; s < o.nu2; ++s)
     for (int c = C - 1; c >= 0; --c) colour_pass(L.phi, L.f, f32, L.G, P->order, c, 1.0, st);
 }
@@ -951,7 +955,10 @@ void mg_step(poisson_plan_s* P, hipStream_t st) {
     residual(P->phi64, P->f64, false, L0.f, true, P->G0, P->order, false, P->partial, st);
   } else {
     vcycle(P, 0, false, st);
-    residual(P->phi64, P->f64, false, nullptr, false, P->G0, P->order, false, P->partial, st);
+    // the cycle ends with a Gauss-Seidel pass over colour 0 on two-colour
+    // grids: only colour 1 carries a residual
+    const int col = (P->C == 2 && P->opts.nu2 > 0 && P->lv.size() > 1) ? 1 : -1;
+    residual(P->phi64, P->f64, false, nullptr, false, P->G0, P->order, false, P->partial, st, col);
   }
   finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
 }
