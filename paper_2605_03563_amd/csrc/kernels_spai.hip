@@ -88,19 +88,20 @@ __global__ __launch_bounds__(BX* BY) void k_n27(const T* __restrict__ src, const
 
 // One fused Richardson step out of place: out = u - M (f - A u) at the
 // unknowns (Eq. richardson), reading u and f once and writing out once.
-// A block owns a 64 x 8 output tile and a run of planes.  Per plane q it
+// A block owns a 64 x FY output tile and a run of planes.  Per plane q it
 // loads u on the tile plus a 2-node halo into LDS, every thread forms the
-// in-plane sums (c, f4, e4) of u for its points of the 66 x 10 residual tile
+// in-plane sums (c, f4, e4) of u for its points of the 66 x (FY+2) residual tile
 // (tile plus a 1-node halo) and keeps the last three planes of them in
 // registers, which gives r at plane q-1 (zero off the unknowns, so M acts on
 // r extended by zero); r goes to LDS, and the in-plane sums of r at the
 // thread's own column, again kept for three planes, give the output at plane
 // q-2.  Out of place because neighbouring tiles read the old u in their halos.
-constexpr int FX = 64, FY = 8;
-template <typename T>
+constexpr int FX = 64;
+template <typename T, int FY>
 __global__ __launch_bounds__(FX* FY) void k_nspai(const T* __restrict__ u, const T* __restrict__ f,
                                                   T* __restrict__ out, NGeom G, W4 A, W4 M) {
   constexpr int UX = FX + 4, UY = FY + 4, RX = FX + 2, RY = FY + 2, NT = FX * FY;
+  static_assert(RX * RY <= 2 * NT, "at most two residual-tile points per thread");
   __shared__ double Us[UY][UX];
   __shared__ double Rs[RY][RX];
   int bx, by, bz;
@@ -465,18 +466,33 @@ void n27_update(const void* r, void* u, bool f32, const NGeom& G, const W4& M, h
                                                                 nullptr);
 }
 
-inline dim3 fgrid(const NGeom& G) {
+// Tile rows FY and planes per block kz: on the 511^3 level 64 x 16 tiles
+// and runs of 128 planes (1024 blocks of 1024 threads) take 0.98 ms per
+// step against 1.11 ms with 64 x 8 tiles and 32 planes (less recomputed
+// halo, fewer pipeline start-ups); smaller levels keep 64 x 8 and shorter
+// runs so that they still spread over the compute units.
+template <int FY>
+inline dim3 fgrid(const NGeom& G, int kz) {
   const int e = G.n - 1;
-  const int kz = G.n >= 256 ? 32 : G.n >= 128 ? 16 : 4;
   return dim3((e + FX - 1) / FX, (e + FY - 1) / FY, (e + kz - 1) / kz);
+}
+
+template <typename T>
+static void spai_step_t(const T* u, const T* f, T* out, const NGeom& G, const W4& A, const W4& M, hipStream_t st) {
+  if (G.n >= 512) {
+    k_nspai<T, 16><<<fgrid<16>(G, 128), dim3(FX, 16), 0, st>>>(u, f, out, G, A, M);
+  } else {
+    const int kz = G.n >= 256 ? 32 : G.n >= 128 ? 16 : 4;
+    k_nspai<T, 8><<<fgrid<8>(G, kz), dim3(FX, 8), 0, st>>>(u, f, out, G, A, M);
+  }
 }
 
 void n_spai_step(const void* u, const void* f, void* out, bool f32, const NGeom& G, const W4& A, const W4& M,
                  hipStream_t st) {
   if (f32)
-    k_nspai<float><<<fgrid(G), dim3(FX, FY), 0, st>>>((const float*)u, (const float*)f, (float*)out, G, A, M);
+    spai_step_t<float>((const float*)u, (const float*)f, (float*)out, G, A, M, st);
   else
-    k_nspai<double><<<fgrid(G), dim3(FX, FY), 0, st>>>((const double*)u, (const double*)f, (double*)out, G, A, M);
+    spai_step_t<double>((const double*)u, (const double*)f, (double*)out, G, A, M, st);
 }
 
 void n_copy(const void* a, void* b, bool f32, const NGeom& G, hipStream_t st) {

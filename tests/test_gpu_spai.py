@@ -86,6 +86,40 @@ def test_richardson_steps(order):
     assert rel_max(_nodes(host(x), n, order), ref) < KERNEL_TOL
 
 
+def test_richardson_step_full_size_sampled():
+    """511^3 unknowns (the 64 x 16 tiles and 128-plane runs of the fine
+    step): one Richardson step from a random guess against the oracle's step
+    evaluated around sampled nodes (r = f - A u on the 27 nodes around the
+    sample, then u - omega M r there), including every tile and run seam
+    and the last rows and planes."""
+    n, order = 512, 2
+    say("SPAI Richardson step 511^3, sampled")
+    phi, rho = _random(n, 99, order)
+    plan = _plan(n, order, coarsest=4)
+    x = dev(phi)
+    plan.smooth(dev(rho), x, sweeps=1)
+    got = host(x)
+    del x
+    h = 1.0 / n
+    w = tuple(c / (h * h) for c in SP.WEIGHTS[order])
+    om, al, be, ga, de = SP.COEFFS[order][:5]
+    rng = np.random.default_rng(5)
+    pts = [tuple(rng.integers(2, n - 1, size=3)) for _ in range(150)]
+    seams = [2, 15, 16, 17, 63, 64, 65, 127, 128, 129, 130, 256, 257, 384, 385, 509, 510]
+    pts += [(a, b, c) for a in seams[::3] for b in seams[1::3] for c in seams[2::3]]
+    pts += [(k, j, i) for k in (128, 129, 257, 385, 510) for j in (16, 17, 510) for i in (64, 65, 510)]
+    errs, scale = [], 0.0
+    for (k, j, i) in pts:
+        U = phi[k - 2:k + 3, j - 2:j + 3, i - 2:i + 3]
+        F = rho[k - 1:k + 2, j - 1:j + 2, i - 1:i + 2]
+        r = F - SP.apply27(U, 4, w)
+        ref = U[2, 2, 2] - om * SP.apply27(r, 2, (al, be, ga, de), h * h)[0, 0, 0]
+        errs.append(abs(got[k, j, i] - ref))
+        scale = max(scale, abs(ref))
+    assert max(errs) < KERNEL_TOL * scale
+    assert np.array_equal(got[0], phi[0]) and np.array_equal(got[:, :, n], phi[:, :, n])
+
+
 @pytest.mark.parametrize("order,n,coarsest", [(2, 32, 8), (4, 32, 8), (6, 32, 8), (2, 48, 6), (6, 48, 6),
                                               (4, 128, 8), (6, 128, 8)])
 def test_one_vcycle_matches_oracle(order, n, coarsest):
