@@ -227,8 +227,11 @@ void sph_apply(const double* u, double* out, const SGeom& S, const SphCoef& c, h
 // relaxation factor omega[j (nr+2) + i] per colatitude and radial index, and
 // one step of the Chebyshev sequence omega <- 1 / (1 - rj^2 omega / 4) over
 // n entries
+// omega_out (with rj): also write the next Chebyshev term per (j, i) there
+// (nphi >= 4 and colour >= 2, the second pass of a half-sweep)
 void sph_sor_pass(double* u, const double* rho, const SGeom& S, const SphCoef& c, double four_pi_G,
-                  const double* omega, int colour, hipStream_t st);
+                  const double* omega, int colour, hipStream_t st, const double* rj = nullptr,
+                  double* omega_out = nullptr);
 void sph_omega_next(double* omega, const double* rj, int n, hipStream_t st);
 // right-preconditioned BiCGSTAB: p = r + beta (p - omega v), phat = B^-1 p;
 // s = r - alpha v, shat = B^-1 s (B: red-black block lower triangle);

@@ -88,7 +88,8 @@ __global__ __launch_bounds__(256) void k_sph_apply(const double* __restrict__ U,
 __global__ __launch_bounds__(256) void k_sph_sor(double* __restrict__ U, const double* __restrict__ rho, SGeom S,
                                                  Coef c, const double* __restrict__ cot2,
                                                  const double* __restrict__ isin2, const double* __restrict__ r2,
-                                                 double fpg, const double* __restrict__ omega, int colour) {
+                                                 double fpg, const double* __restrict__ omega, int colour,
+                                                 const double* __restrict__ rj, double* __restrict__ omega_out) {
   const int i = 1 + blockIdx.x * BX + threadIdx.x;
   const int j = blockIdx.y * BY + threadIdx.y;
   const int k = blockIdx.z + ((colour >> 1) ? (S.nph >> 1) : 0);
@@ -97,7 +98,13 @@ __global__ __launch_bounds__(256) void k_sph_sor(double* __restrict__ U, const d
   const long long idx = S.at(i, j, k);
   const double res = fpg * r2[i] * rho[idx] - sph_op(V, S, c, cot2, isin2, i, j, k);
   const double d = -(c.rcl[i] + c.rcr[i]) - 2.0 * c.idt2 - 2.0 * isin2[j] * c.idp2;
-  U[idx] += omega[(long long)j * (S.nr + 2) + i] * res / d;
+  const long long t = (long long)j * (S.nr + 2) + i;
+  const double w = omega[t];
+  U[idx] += w * res / d;
+  // next term of the sequence (Eq. omega_n), written by the one thread of
+  // (i, j) that is active in the first two planes of the half turn
+  if (omega_out && (int)blockIdx.z == ((colour + i + j + (S.nph >> 1)) & 1))
+    omega_out[t] = 1.0 / (1.0 - rj[t] * rj[t] * w / 4.0);
 }
 
 // next term of the relaxation sequence at every node of the table (Eq. omega_n)
@@ -517,9 +524,10 @@ void sph_cast_out(const SLev& L0, double* x, const SGeom& S, hipStream_t st) {
 }
 
 void sph_sor_pass(double* u, const double* rho, const SGeom& S, const SphCoef& c, double four_pi_G,
-                  const double* omega, int colour, hipStream_t st) {
+                  const double* omega, int colour, hipStream_t st, const double* rj, double* omega_out) {
   const dim3 g((S.nr + BX - 1) / BX, (S.nth + BY - 1) / BY, S.nph / 2);
-  k_sph_sor<<<g, dim3(BX, BY), 0, st>>>(u, rho, S, make_coef(S, c), c.cot, c.isin2, c.r2, four_pi_G, omega, colour);
+  k_sph_sor<<<g, dim3(BX, BY), 0, st>>>(u, rho, S, make_coef(S, c), c.cot, c.isin2, c.r2, four_pi_G, omega, colour,
+                                        rj, omega_out);
 }
 
 void sph_omega_next(double* omega, const double* rj, int n, hipStream_t st) {

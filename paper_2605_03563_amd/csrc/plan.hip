@@ -435,6 +435,7 @@ void carve(poisson_plan_s* P, Carver& cv) {
       // relaxation factors and local spectral radii per colatitude and radial index
       const size_t nrel = (size_t)g.n[1] * (g.n[0] + 2);
       P->somega = (double*)cv.take(sizeof(double) * nrel);
+      P->somega2 = (double*)cv.take(sizeof(double) * nrel);
       P->srj = (double*)cv.take(sizeof(double) * nrel);
     }
     P->slv.clear();
@@ -1311,13 +1312,23 @@ int sph_sor_init(poisson_plan_s* P) {
   return POISSON_OK;
 }
 
-// one SOR sweep: red half (colours 0, 2), then black (1, 3)
+// one SOR sweep: red half (colours 0, 2), then black (1, 3).  With the
+// Chebyshev sequence the second pass of each half also writes the next term
+// into the other table (one writer per colatitude and radius), and the
+// tables swap; with nphi = 2 that pass has no writer for every entry and a
+// separate kernel advances the table.
 void sph_sor_sweep(poisson_plan_s* P, const double* rho, double* phi, hipStream_t st) {
   const bool cheb = P->opts.omega_mode == POISSON_OMEGA_CHEBYSHEV;
+  const bool fused = cheb && P->S.nph >= 4;
   for (int half = 0; half < 2; ++half) {
     sph_sor_pass(phi, rho, P->S, P->sc, P->opts.four_pi_G, P->somega, half, st);
-    sph_sor_pass(phi, rho, P->S, P->sc, P->opts.four_pi_G, P->somega, half + 2, st);
-    if (cheb) sph_omega_next(P->somega, P->srj, P->S.nth * (P->S.nr + 2), st);
+    if (fused) {
+      sph_sor_pass(phi, rho, P->S, P->sc, P->opts.four_pi_G, P->somega, half + 2, st, P->srj, P->somega2);
+      std::swap(P->somega, P->somega2);
+    } else {
+      sph_sor_pass(phi, rho, P->S, P->sc, P->opts.four_pi_G, P->somega, half + 2, st);
+      if (cheb) sph_omega_next(P->somega, P->srj, P->S.nth * (P->S.nr + 2), st);
+    }
   }
 }
 

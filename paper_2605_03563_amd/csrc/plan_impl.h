@@ -61,6 +61,7 @@ struct poisson_plan_s {
   double *sr = nullptr, *srh = nullptr, *sp[2] = {nullptr, nullptr}, *sv[2] = {nullptr, nullptr};
   double *ss = nullptr, *stt = nullptr;
   double* somega = nullptr;            // SOR: relaxation factor per colatitude
+  double* somega2 = nullptr;           // SOR, Chebyshev sequence: the next term
   double* srj = nullptr;               // SOR: local Jacobi spectral radius per colatitude
   std::vector<double> srj_host;        // the same on the host
   std::vector<psn::SLev> slv;          // FP32 multigrid preconditioner levels (BICGSTAB_MG32)
