@@ -90,10 +90,13 @@ __global__ __launch_bounds__(256) void k_sph_sor(double* __restrict__ U, const d
                                                  const double* __restrict__ isin2, const double* __restrict__ r2,
                                                  double fpg, const double* __restrict__ omega, int colour,
                                                  const double* __restrict__ rj, double* __restrict__ omega_out) {
-  const int i = 1 + blockIdx.x * BX + threadIdx.x;
+  // thread t of the row takes the node of the pass's parity among radial
+  // indices 1 + 2t and 2 + 2t, so every lane has work
   const int j = blockIdx.y * BY + threadIdx.y;
   const int k = blockIdx.z + ((colour >> 1) ? (S.nph >> 1) : 0);
-  if (!active(S, i, j, k) || ((i + j + k) & 1) != (colour & 1)) return;
+  const int i0 = 1 + 2 * (int)(blockIdx.x * BX + threadIdx.x);
+  const int i = i0 + ((colour + i0 + j + k) & 1);
+  if (!active(S, i, j, k)) return;
   auto V = [&](int ii, int jj, int kk) -> double { return U[S.at(ii, jj, kk)]; };
   const long long idx = S.at(i, j, k);
   const double res = fpg * r2[i] * rho[idx] - sph_op(V, S, c, cot2, isin2, i, j, k);
@@ -525,7 +528,7 @@ void sph_cast_out(const SLev& L0, double* x, const SGeom& S, hipStream_t st) {
 
 void sph_sor_pass(double* u, const double* rho, const SGeom& S, const SphCoef& c, double four_pi_G,
                   const double* omega, int colour, hipStream_t st, const double* rj, double* omega_out) {
-  const dim3 g((S.nr + BX - 1) / BX, (S.nth + BY - 1) / BY, S.nph / 2);
+  const dim3 g((S.nr + 2 * BX - 1) / (2 * BX), (S.nth + BY - 1) / BY, S.nph / 2);
   k_sph_sor<<<g, dim3(BX, BY), 0, st>>>(u, rho, S, make_coef(S, c), c.cot, c.isin2, c.r2, four_pi_G, omega, colour,
                                         rj, omega_out);
 }
