@@ -38,6 +38,11 @@ __device__ inline double sph_op(const F& V, const SGeom& S, const Coef& c, const
          cot2[j] * (jp - jm) + (kp - 2.0 * u + km) * isin2[j] * c.idp2;
 }
 
+// one thread per pair of radial indices (the kernels that visit one colour)
+inline dim3 black_grid(const SGeom& S) {
+  return dim3((S.nr + 2 * BX - 1) / (2 * BX), (S.nth + BY - 1) / BY, S.nph);
+}
+
 __device__ inline bool active(const SGeom& S, int i, int j, int k) {
   return i >= 1 && i <= S.nr && j < S.nth && k < S.nph;
 }
@@ -165,10 +170,13 @@ __global__ __launch_bounds__(256) void k_pbicg_s(const double* __restrict__ R, c
 __global__ __launch_bounds__(256) void k_gs_black(const double* __restrict__ Y, double* __restrict__ Xh, SGeom S,
                                                   Coef c, const double* __restrict__ cot2,
                                                   const double* __restrict__ isin2) {
-  const int i = 1 + blockIdx.x * BX + threadIdx.x;
+  // thread t of the row takes the black node among radial indices 1 + 2t
+  // and 2 + 2t
   const int j = blockIdx.y * BY + threadIdx.y;
   const int k = blockIdx.z;
-  if (!active(S, i, j, k) || is_red(i, j, k)) return;
+  const int i0 = 1 + 2 * (int)(blockIdx.x * BX + threadIdx.x);
+  const int i = i0 + ((1 + i0 + j + k) & 1);
+  if (!active(S, i, j, k)) return;
   const int half = S.nph >> 1;
   // value of a neighbour if it is red, else 0 (radial ghosts of xhat are 0)
   auto red = [&](int ii, int jj, int kk) -> double { return is_red(ii, jj, kk) ? Xh[S.at(ii, jj, kk)] : 0.0; };
@@ -464,7 +472,7 @@ void pbicg_direction(const double* r, double* p, const double* v, double* phat, 
                      const Scalars* scal, hipStream_t st) {
   const Coef cf = make_coef(S, c);
   k_pbicg_p<<<sgrid(S), dim3(BX, BY), 0, st>>>(r, p, v, phat, S, cf, c.isin2, scal);
-  k_gs_black<<<sgrid(S), dim3(BX, BY), 0, st>>>(p, phat, S, cf, c.cot, c.isin2);
+  k_gs_black<<<black_grid(S), dim3(BX, BY), 0, st>>>(p, phat, S, cf, c.cot, c.isin2);
 }
 
 void pbicg_update_p(const double* r, double* p, const double* v, const SGeom& S, const SphCoef& c,
@@ -481,7 +489,7 @@ void pbicg_s(const double* r, const double* v, double* s, double* shat, const SG
              const Scalars* scal, hipStream_t st) {
   const Coef cf = make_coef(S, c);
   k_pbicg_s<<<sgrid(S), dim3(BX, BY), 0, st>>>(r, v, s, shat, S, cf, c.isin2, scal);
-  k_gs_black<<<sgrid(S), dim3(BX, BY), 0, st>>>(s, shat, S, cf, c.cot, c.isin2);
+  k_gs_black<<<black_grid(S), dim3(BX, BY), 0, st>>>(s, shat, S, cf, c.cot, c.isin2);
 }
 
 void pbicg_apply(const double* xhat, double* out, const double* w, int mode, const SGeom& S, const SphCoef& c,
