@@ -74,9 +74,13 @@ struct SGeom {
 // each axis (spacings doubled, colatitudes (j + 1/2) pi / nth).  The radial
 // couplings rcl[i], rcr[i] (to unknowns i-1, i+1; diagonal -(rcl + rcr))
 // are the radial map's operator rediscretised on the level: constant on the
-// log grid, varying with i where an inner pad bends the map.
+// log grid, varying with i where an inner pad bends the map.  A row holds
+// the even radial array indices a (ghost a = 0 included) in its first hp
+// entries and the odd ones in the next hp, so the lines of one zebra colour
+// at a colatitude are contiguous.
 struct SLev {
-  int nr, nth, nph, p0;  // unknowns, row pitch
+  int nr, nth, nph, p0;  // unknowns, row pitch (2 hp)
+  int hp;                // entries per parity half of a row
   long long p1;          // plane pitch
   float idt2, idp2;
   float* u;
@@ -93,7 +97,9 @@ struct SLev {
   // w[seg] to unit end loads and the 2nseg x 2nseg interface inverse
   int seg, nseg, nl, tstride, tri;
   const float* ltab;
-  __host__ __device__ long long at(int i, int j, int k) const { return (long long)k * p1 + (long long)j * p0 + i; }
+  __host__ __device__ long long at(int a, int j, int k) const {
+    return (long long)k * p1 + (long long)j * p0 + (long long)(a & 1) * hp + (a >> 1);
+  }
   __host__ __device__ long long count() const { return p1 * nph; }
 };
 

@@ -342,7 +342,7 @@ __global__ __launch_bounds__(1024) void k_sline(SLev L, int colour, int zero_gue
         const float pole = (zero_guess == 2) ? 0.0f : L.u[L.at(a, j, (k + half) % L.nph)];
         const float up = (j + 1 < L.nth) ? L.u[idx + L.p0] : pole;
         const float um = (j > 0) ? L.u[idx - L.p0] : pole;
-        rhs -= cr * L.u[idx + 1] + cl * L.u[idx - 1] + cjp * up + cjm * um;
+        rhs -= cr * L.u[L.at(a + 1, j, k)] + cl * L.u[L.at(a - 1, j, k)] + cjp * up + cjm * um;
       }
       d = (rhs - aphi * d) * m[q];
       Y[(size_t)q * nt + t] = d;

@@ -445,7 +445,8 @@ void carve(poisson_plan_s* P, Carver& cv) {
         L.nr = d[0];
         L.nth = d[1];
         L.nph = d[2];
-        L.p0 = L.nr + 2;
+        L.hp = (L.nr + 3) / 2;  // radial array indices 0 .. nr+1 split by parity
+        L.p0 = 2 * L.hp;
         L.p1 = (long long)L.nth * L.p0;
         const double dth = M_PI / L.nth, dph = 2.0 * M_PI / L.nph;
         L.idt2 = (float)(1.0 / (dth * dth));
