@@ -86,16 +86,19 @@ std::vector<std::array<int, 3>> sph_levels(int nr, int nth, int nph) {
   return out;
 }
 
-// Split of a phi line of nph nodes for the line smoother: eight segments
-// when nph is a multiple of 16 and at most 256 (short sequential
-// recurrences on the coarse levels, where the pass is latency bound), else
-// segments of the largest divisor of nph up to 32; nseg = nph / seg of them,
-// nl lines per block (a power of two, <= 64 lines, <= 1024 threads and the
-// LDS of Y plus the interface values within 64 KiB).  False if no split fits.
+// Split of a phi line of nph nodes for the line smoother: when nph is a
+// multiple of 16 and at most 256, sixteen segments (eight below 32 nodes),
+// since the pass is bound by the latency of its sequential recurrences
+// (at 256 x 128 x 256 sixteen segments of 16 nodes take the C4 solve from
+// 11.1 to 9.7 ms against eight of 32; 32 segments of 8 gain nothing more);
+// else segments of the largest divisor of nph up to 32; nseg = nph / seg of
+// them, nl lines per block (a power of two, <= 64 lines, <= 1024 threads
+// and the LDS of Y plus the interface values within 64 KiB).  False if no
+// split fits.
 bool line_split(int nph, int* seg, int* nseg, int* nl) {
   int L = 1;
   if (nph % 16 == 0 && nph <= 256) {
-    L = nph / 8;
+    L = nph >= 32 ? nph / 16 : nph / 8;
   } else {
     for (int d = 2; d <= 32 && d <= nph; ++d)
       if (nph % d == 0) L = d;
