@@ -1057,6 +1057,88 @@ __global__ __launch_bounds__(256) void k_cg_dir(const double* __restrict__ R, co
   if (threadIdx.x == 0 && threadIdx.y == 0) partial[linear_block()] = s;
 }
 
+// The same for the 7-point operator with a register window along z, as in
+// the residual kernel: the thread owns nodes A = 2m and B = 2m+1 of row
+// (b, k) for KZP planes, forms p = sr r + beta p_old at every position it
+// loads (both colours at compact m for the z-window, x- and y-neighbours per
+// plane; ghosts of r and p_old are zero), issues a chunk's loads before its
+// updates, then stores p_new and q = -L p and sums p . q.
+template <int KZP>
+__global__ __launch_bounds__(256) void k_cg_dir7(const double* __restrict__ Rr, const double* __restrict__ Pold,
+                                                 double* __restrict__ Pnew, double* __restrict__ Q, Geom G,
+                                                 double ih2, double sr, const Scalars* __restrict__ scal,
+                                                 double* __restrict__ partial) {
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int m = G.mlo() + bx * BX + (int)threadIdx.x;
+  const int b = G.g + by * BY + (int)threadIdx.y;
+  const int last = G.g + G.n - 2;
+  const double beta = scal->v[2];
+  double acc = 0.0;
+  if (m <= G.mhi() && b <= last) {
+    const int kz = planes_per_block(G);
+    const int k0 = G.g + bz * kz;
+    const int k1 = min(k0 + kz - 1, last);
+    const long long plane = (long long)G.M * G.W;
+    const long long W = G.W;
+    const long long q0 = G.row(b, 0) + m;
+    auto pv = [&](long long i) -> double { return sr * Rr[i] + beta * Pold[i]; };
+    constexpr int CH = KZP < 4 ? KZP : 4;
+    double z0[KZP + 2], z1[KZP + 2];
+    double xl[KZP], xr[KZP], ya0[KZP], ya1[KZP], yb0[KZP], yb1[KZP];
+    const bool inA = G.inner(2 * m), inB = G.inner(2 * m + 1);
+#pragma unroll
+    for (int c0 = 0; c0 < KZP; c0 += CH) {
+#pragma unroll
+      for (int t = (c0 == 0 ? 0 : c0 + 2); t < c0 + CH + 2; ++t) {
+        const long long o = (long long)min(k0 - 1 + t, k1 + 1) * plane;
+        z0[t] = pv(q0 + o);
+        z1[t] = pv(G.cs + q0 + o);
+      }
+#pragma unroll
+      for (int t = c0; t < c0 + CH; ++t) {
+        const int k = min(k0 + t, k1);
+        const long long o = (long long)k * plane;
+        const long long sa = (long long)((b + k + G.off) & 1) * G.cs;  // colour of A = 2m
+        const long long sb = G.cs - sa;                                 // colour of B = 2m+1
+        xl[t] = pv(sb + q0 + o - 1);
+        xr[t] = pv(sa + q0 + o + 1);
+        yb0[t] = pv(sb + q0 + o - W);
+        yb1[t] = pv(sb + q0 + o + W);
+        ya0[t] = pv(sa + q0 + o - W);
+        ya1[t] = pv(sa + q0 + o + W);
+      }
+#pragma unroll
+      for (int t = c0; t < c0 + CH; ++t) {
+        const int k = k0 + t;
+        if (k <= k1) {
+          const int s = (b + k + G.off) & 1;
+          const long long o = (long long)k * plane;
+          const double pA = s ? z1[t + 1] : z0[t + 1], pB = s ? z0[t + 1] : z1[t + 1];
+          const double zbA = s ? z0[t] + z0[t + 2] : z1[t] + z1[t + 2];
+          const double zbB = s ? z1[t] + z1[t + 2] : z0[t] + z0[t + 2];
+          if (inA) {
+            const double lap = ((xl[t] + pB) + (yb0[t] + yb1[t] + zbA) - 6.0 * pA) * ih2;
+            const long long i = (long long)s * G.cs + q0 + o;
+            Pnew[i] = pA;
+            Q[i] = -lap;
+            acc += pA * (-lap);
+          }
+          if (inB) {
+            const double lap = ((pA + xr[t]) + (ya0[t] + ya1[t] + zbB) - 6.0 * pB) * ih2;
+            const long long i = (long long)(s ^ 1) * G.cs + q0 + o;
+            Pnew[i] = pB;
+            Q[i] = -lap;
+            acc += pB * (-lap);
+          }
+        }
+      }
+    }
+  }
+  const double sum = block_sum(acc);
+  if (threadIdx.x == 0 && threadIdx.y == 0) partial[linear_block()] = sum;
+}
+
 // x -= alpha p; r -= alpha q; partial (r . r).  The vectors follow the
 // residual r = f - L x (the negative of the residual of the SPD system
 // -L x = -f), so the direction enters x with a minus sign.
@@ -1374,8 +1456,10 @@ int cg_blocks(const Geom& G) { return (int)nblocks(col_grid(G)); }
 void cg_direction_apply(const double* r, const double* p_old, double* p_new, double* q, const Geom& G, int order,
                         const Scalars* scal, double* partial, hipStream_t st, double sr) {
   const double ih2 = 1.0 / (G.h * G.h);
-  if (order == 2)
-    k_cg_dir<2><<<col_grid(G), dim3(BX, BY), 0, st>>>(r, p_old, p_new, q, G, ih2, sr, scal, partial);
+  if (order == 2 && kz_for(G) == KZ)
+    k_cg_dir7<KZ><<<col_grid(G), dim3(BX, BY), 0, st>>>(r, p_old, p_new, q, G, ih2, sr, scal, partial);
+  else if (order == 2)
+    k_cg_dir7<1><<<col_grid(G), dim3(BX, BY), 0, st>>>(r, p_old, p_new, q, G, ih2, sr, scal, partial);
   else
     k_cg_dir<6><<<col_grid(G), dim3(BX, BY), 0, st>>>(r, p_old, p_new, q, G, ih2, sr, scal, partial);
 }
