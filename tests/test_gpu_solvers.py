@@ -1,6 +1,7 @@
 """Converged parity of every solver path against the oracle's exact discrete
 solution (relative L2 error <= 1e-10 once the residual is driven to round-off
 level), error paths, and determinism."""
+import functools
 import math
 
 import numpy as np
@@ -145,16 +146,25 @@ def test_c4_multigrid_preconditioner_cuts_iterations():
     assert rel_l2(a[:, :, 1:-1], b[:, :, 1:-1]) < 1e-9
 
 
-def test_c2_full_size_multigrid():
-    """255^3 unknowns, the benchmark's launch configuration: converged MG
+@functools.lru_cache(maxsize=1)
+def _c2_full():
+    """C2's 256^3 density and the oracle's exact solution with its multipole
+    boundary (computed once for the full-size cases)."""
+    rho = W.config_c2(n=256).rho.numpy()
+    return rho, _oracle_cart(rho, 256, 1, 2, 8)
+
+
+@pytest.mark.parametrize("method", ["mg", "cg", "pcg"])
+def test_c2_full_size_multigrid(method):
+    """255^3 unknowns in the benchmarks' launch configurations (the C2
+    multigrid; CG and PCG as in the 255^3 preconditioning study): converged
     solution against the DST oracle."""
-    say("C2 full size 256^3 FP64 MG")
+    say(f"C2 full size 256^3 FP64 {method}")
     n = 256
-    wl = W.config_c2(n=n)
-    rho = wl.rho.numpy()
-    phi, res = _solve(n, 1, "mg", 2, rho, 8, 1e-12)
+    rho, ref = _c2_full()
+    phi, res = _solve(n, 1, method, 2, rho, 8, 1e-12, max_iter=20000)
+    say(f"  {res.iterations} iterations")
     assert res.converged, res
-    ref = _oracle_cart(rho, n, 1, 2, 8)
     s = slice(1, n)
     assert rel_l2(phi[s, s, s], ref[s, s, s]) < CONV_TOL
 
