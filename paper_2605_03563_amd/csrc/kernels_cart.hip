@@ -148,6 +148,7 @@ __global__ __launch_bounds__(256) void k_pass7(T* __restrict__ X, const T* __res
 // and needs no barrier.  The node at position q of a compact column in a row
 // with colour shift s has colour (q + s) mod 4.
 constexpr int TROWS = TBY + 6;
+static_assert(TBY >= 6, "the six halo rows of a plane tile are loaded by the first six thread rows");
 constexpr int TCOLS = BX + 2;
 
 // Four-colour pass without LDS or barriers: the register window along z
