@@ -1009,11 +1009,11 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(const double* __restr
 }
 
 // ---------------------------------------------------------------- CG (A = -L)
-// p_new = sr r + beta p_old;  q = A p_new;  partial (p_new . q).
+// p_new = sr r + beta p_old;  q = A p_new;  partial (p_new . q), for the
+// 19-point star (node by node, p formed at every stencil point).
 // scal: v[0] = rr (current r.r, or the PCG inner product), v[2] = beta,
 // v[3] = alpha.
-template <int ORDER>
-__global__ __launch_bounds__(256) void k_cg_dir(const double* __restrict__ R, const double* __restrict__ Pold,
+__global__ __launch_bounds__(256) void k_cg_dir19(const double* __restrict__ R, const double* __restrict__ Pold,
                                                 double* __restrict__ Pnew, double* __restrict__ Q, Geom G,
                                                 double ih2, double sr, const Scalars* __restrict__ scal,
                                                 double* __restrict__ partial) {
@@ -1036,18 +1036,11 @@ __global__ __launch_bounds__(256) void k_cg_dir(const double* __restrict__ R, co
         const int a = (m << G.lc) + r;
         if (!G.inner(a)) continue;
         const double pc = pv(a, b, k);
-        double lap;
-        if (ORDER == 2) {
-          const double s = pv(a - 1, b, k) + pv(a + 1, b, k) + pv(a, b - 1, k) + pv(a, b + 1, k) +
-                           pv(a, b, k - 1) + pv(a, b, k + 1);
-          lap = (s - 6.0 * pc) * ih2;
-        } else {
-          double s[3];
-          for (int d = 1; d <= 3; ++d)
-            s[d - 1] = pv(a - d, b, k) + pv(a + d, b, k) + pv(a, b - d, k) + pv(a, b + d, k) +
-                       pv(a, b, k - d) + pv(a, b, k + d);
-          lap = (3.0 * kC0 * pc + kC1 * s[0] + kC2 * s[1] + kC3 * s[2]) * ih2;
-        }
+        double s[3];
+        for (int d = 1; d <= 3; ++d)
+          s[d - 1] = pv(a - d, b, k) + pv(a + d, b, k) + pv(a, b - d, k) + pv(a, b + d, k) + pv(a, b, k - d) +
+                     pv(a, b, k + d);
+        const double lap = (3.0 * kC0 * pc + kC1 * s[0] + kC2 * s[1] + kC3 * s[2]) * ih2;
         const long long i = G.at(a, b, k);
         Pnew[i] = pc;
         Q[i] = -lap;
@@ -1058,7 +1051,7 @@ __global__ __launch_bounds__(256) void k_cg_dir(const double* __restrict__ R, co
   if (threadIdx.x == 0 && threadIdx.y == 0) partial[linear_block()] = s;
 }
 
-// The same for the 7-point operator with a register window along z, as in
+// The same for the 7-point operator, with a register window along z as in
 // the residual kernel: the thread owns nodes A = 2m and B = 2m+1 of row
 // (b, k) for KZP planes, forms p = sr r + beta p_old at every position it
 // loads (both colours at compact m for the z-window, x- and y-neighbours per
@@ -1462,7 +1455,7 @@ void cg_direction_apply(const double* r, const double* p_old, double* p_new, dou
   else if (order == 2)
     k_cg_dir7<1><<<col_grid(G), dim3(BX, BY), 0, st>>>(r, p_old, p_new, q, G, ih2, sr, scal, partial);
   else
-    k_cg_dir<6><<<col_grid(G), dim3(BX, BY), 0, st>>>(r, p_old, p_new, q, G, ih2, sr, scal, partial);
+    k_cg_dir19<<<col_grid(G), dim3(BX, BY), 0, st>>>(r, p_old, p_new, q, G, ih2, sr, scal, partial);
 }
 
 void pcg_dot(const double* r, const double* z, const Geom& G, double* partial, hipStream_t st) {

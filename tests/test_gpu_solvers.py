@@ -270,14 +270,17 @@ def test_c3_full_size_properties():
     del OS
 
 
+@pytest.mark.parametrize("dims", [(12, 8, 16), (13, 6, 6), (12, 8, 2)])
 @pytest.mark.parametrize("mode", ["chebyshev", "opt"])
-def test_spherical_sor_sweeps_match_oracle(mode):
-    """Three SOR sweeps on a random 12 x 8 x 16 state with the local
-    relaxation factors (Eq. local_rjac; Eq. omega_n advanced per half-sweep,
-    or the local omega_opt) against the oracle's colour passes."""
+def test_spherical_sor_sweeps_match_oracle(mode, dims):
+    """Three SOR sweeps on a random state with the local relaxation factors
+    (Eq. local_rjac; Eq. omega_n advanced per half-sweep, or the local
+    omega_opt) against the oracle's colour passes; an odd radial count and
+    an odd half turn (13 x 6 x 6), and nphi = 2, where the relaxation table
+    advances in its own kernel."""
     from oracle import sph_sor as SS
-    say(f"spherical SOR sweeps ({mode})")
-    nr, nth, nph = 12, 8, 16
+    say(f"spherical SOR sweeps ({mode}) {dims}")
+    nr, nth, nph = dims
     r, th, ph, ds = OM.sph_axes(nr, nth, nph)
     rng = np.random.default_rng(21)
     u = rng.standard_normal((nph, nth, nr + 2))
