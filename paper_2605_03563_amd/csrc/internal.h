@@ -92,10 +92,13 @@ struct SLev {
   const float* isin2;  // 1 / sin^2(theta_j)
   // phi-line solver: each line splits into nseg segments of seg nodes; a
   // block holds nl lines; the table of line (i, j) at ltab + (it nth + j)
-  // tstride (it = i when the radial couplings vary, tri = 1, else 0) holds
+  // tstride, it = min(i, ntab - 1): the radial couplings vary only on the
+  // unknowns inside an inner pad (the first ntab - 1), every other radius
+  // has the log map's and shares the last table (ntab = 1 on a log grid);
+  // it holds
   // the segment elimination factors m[seg], c'[seg], the responses v[seg],
   // w[seg] to unit end loads and the 2nseg x 2nseg interface inverse
-  int seg, nseg, nl, tstride, tri;
+  int seg, nseg, nl, tstride, ntab;
   const float* ltab;
   __host__ __device__ long long at(int a, int j, int k) const {
     return (long long)k * p1 + (long long)j * p0 + (long long)(a & 1) * hp + (a >> 1);

@@ -316,7 +316,7 @@ __global__ __launch_bounds__(1024) void k_sline(SLev L, int colour, int zero_gue
   const int SL = L.seg, P = L.nseg;
   float* Y = lds;
   float* E = lds + (size_t)SL * nt;
-  const int it = L.tri ? min(i, L.nr - 1) : 0;
+  const int it = min(i, L.ntab - 1);
   const float* tb = L.ltab + ((size_t)it * L.nth + j) * L.tstride;
   const float* m = tb;
   const float* cp = tb + SL;

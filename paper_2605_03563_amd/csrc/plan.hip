@@ -443,6 +443,7 @@ void carve(poisson_plan_s* P, Carver& cv) {
     }
     P->slv.clear();
     if (o.method == POISSON_BICGSTAB_MG32) {
+      int lev = 0;
       for (const auto& d : sph_levels(g.n[0], g.n[1], g.n[2])) {
         SLev L{};
         L.nr = d[0];
@@ -462,13 +463,22 @@ void carve(poisson_plan_s* P, Carver& cv) {
         L.rcr = (const float*)cv.take(sizeof(float) * L.nr);
         L.cot2 = (const float*)cv.take(sizeof(float) * L.nth);
         L.isin2 = (const float*)cv.take(sizeof(float) * L.nth);
-        L.tri = g.ext_in > 0 ? 1 : 0;
+        // unknown I of level `lev` sits at xi = 2^lev I + (2^lev - 1)/2 - p;
+        // from the first I with xi >= 0 on, the map is the log map and the
+        // couplings (so the line tables) are the same
+        {
+          const int p = g.ext_in > 0 ? g.ext_in - 1 : 0;
+          const double h = (double)(1 << lev);
+          const int i0 = (int)ceil((p - 0.5 * (h - 1.0)) / h);
+          L.ntab = 1 + std::min(std::max(i0, 0), L.nr - 1);
+        }
         if (line_split(L.nph, &L.seg, &L.nseg, &L.nl)) {
           L.tstride = 4 * L.seg + 4 * L.nseg * L.nseg;
-          const size_t nlines = (size_t)L.nth * (L.tri ? L.nr : 1);
+          const size_t nlines = (size_t)L.nth * L.ntab;
           L.ltab = (const float*)cv.take(sizeof(float) * (size_t)L.tstride * nlines);
         }
         P->slv.push_back(L);
+        ++lev;
       }
       const SLev& C = P->slv.back();
       P->sncoarse = C.nr * C.nth * C.nph;
@@ -696,7 +706,7 @@ void sph_level_matrix(int nr, int nth, int nph, const std::vector<double>& cl, c
 bool line_tables(const SLev& L, const std::vector<double>& cl, const std::vector<double>& cr,
                  std::vector<float>& tab) {
   const int SL = L.seg, Pn = L.nseg;
-  const int ni = L.tri ? L.nr : 1;
+  const int ni = L.ntab;
   tab.assign((size_t)L.tstride * L.nth * ni, 0.0f);
   const double dth = M_PI / L.nth, dph = 2.0 * M_PI / L.nph;
   std::vector<double> m(SL), cp(SL), v(SL), w(SL), K, G;
