@@ -188,8 +188,8 @@ def test_radial_pad_validation():
     """Pads belong to spherical grids; the inner pad needs 0 < r_pad < r_in and
     a monotone quartic; at least two log-core unknowns remain; the FP32
     FP32 multigrid preconditioner keeps one line-smoother table per radius
-    and colatitude when an inner pad bends the map, one per colatitude
-    otherwise."""
+    and colatitude inside an inner pad (where the map bends), one per
+    colatitude for the rest and on log grids."""
     lib = L.load()
     ok = pg.sph_grid(60, 8, 16, 0.5, 1.0, ext_in=8, ext_out=6, r_pad=0.3)
     assert lib.poisson_workspace_bytes(C.byref(ok), C.byref(pg.options("bicgstab"))) > 0
