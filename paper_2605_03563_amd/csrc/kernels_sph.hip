@@ -371,21 +371,26 @@ __global__ __launch_bounds__(1024) void k_sline(SLev L, int colour, int zero_gue
     L.u[L.at(a, j, k0 + q)] = Y[(size_t)q * nt + t] - (xl * v[q] + xr * w[q]);
 }
 
+// Thread x of a level row takes radial array index a in the row's storage
+// order (even a first, then odd), so a wavefront's accesses are contiguous;
+// returns the unknown index a - 1 (outside 0 .. nr-1 for ghosts and padding).
+__device__ inline int slev_unknown(const SLev& L, int x) { return (x < L.hp ? 2 * x : 2 * (x - L.hp) + 1) - 1; }
+
 __global__ __launch_bounds__(256) void k_sres32(SLev L) {
-  const int i = blockIdx.x * BX + threadIdx.x;
+  const int i = slev_unknown(L, blockIdx.x * BX + threadIdx.x);
   const int j = blockIdx.y * BY + threadIdx.y;
   const int k = blockIdx.z;
-  if (i >= L.nr || j >= L.nth) return;
+  if (i < 0 || i >= L.nr || j >= L.nth) return;
   const long long idx = L.at(i + 1, j, k);
   L.r[idx] = L.f[idx] - (slev_off(L, i, j, k) + slev_diag(L, i, j) * L.u[idx]);
 }
 
 // coarse f = mean of the 8 fine residuals it pairs
 __global__ __launch_bounds__(256) void k_srestrict(SLev Lf, SLev Lc) {
-  const int I = blockIdx.x * BX + threadIdx.x;
+  const int I = slev_unknown(Lc, blockIdx.x * BX + threadIdx.x);
   const int J = blockIdx.y * BY + threadIdx.y;
   const int K = blockIdx.z;
-  if (I >= Lc.nr || J >= Lc.nth) return;
+  if (I < 0 || I >= Lc.nr || J >= Lc.nth) return;
   float s = 0.0f;
   for (int c = 0; c < 2; ++c)
     for (int b = 0; b < 2; ++b)
@@ -394,10 +399,10 @@ __global__ __launch_bounds__(256) void k_srestrict(SLev Lf, SLev Lc) {
 }
 
 __global__ __launch_bounds__(256) void k_sprolong(SLev Lc, SLev Lf) {
-  const int i = blockIdx.x * BX + threadIdx.x;
+  const int i = slev_unknown(Lf, blockIdx.x * BX + threadIdx.x);
   const int j = blockIdx.y * BY + threadIdx.y;
   const int k = blockIdx.z;
-  if (i >= Lf.nr || j >= Lf.nth) return;
+  if (i < 0 || i >= Lf.nr || j >= Lf.nth) return;
   Lf.u[Lf.at(i + 1, j, k)] += Lc.u[Lc.at((i >> 1) + 1, j >> 1, k >> 1)];
 }
 
@@ -435,7 +440,9 @@ __global__ __launch_bounds__(256) void k_scast_out(SLev L, double* __restrict__ 
   x[S.at(i + 1, j, k)] = (double)L.u[L.at(i + 1, j, k)];
 }
 
-inline dim3 lgrid(const SLev& L) { return dim3((L.nr + BX - 1) / BX, (L.nth + BY - 1) / BY, L.nph); }
+// one thread per stored entry of a level row (p0 = 2 hp), for the kernels
+// indexed through slev_unknown
+inline dim3 lgrid_split(const SLev& L) { return dim3((L.p0 + BX - 1) / BX, (L.nth + BY - 1) / BY, L.nph); }
 
 Coef make_coef(const SGeom& S, const SphCoef& sc) {
   Coef c;
@@ -516,12 +523,12 @@ void sph_line_pass(const SLev& L, int colour, int zero_guess, hipStream_t st) {
   const int lines = (L.nr + 1) / 2;
   k_sline<<<dim3((lines + L.nl - 1) / L.nl, L.nth), nt, lds, st>>>(L, colour, zero_guess);
 }
-void sph_residual32(const SLev& L, hipStream_t st) { k_sres32<<<lgrid(L), dim3(BX, BY), 0, st>>>(L); }
+void sph_residual32(const SLev& L, hipStream_t st) { k_sres32<<<lgrid_split(L), dim3(BX, BY), 0, st>>>(L); }
 void sph_restrict32(const SLev& Lf, const SLev& Lc, hipStream_t st) {
-  k_srestrict<<<lgrid(Lc), dim3(BX, BY), 0, st>>>(Lf, Lc);
+  k_srestrict<<<lgrid_split(Lc), dim3(BX, BY), 0, st>>>(Lf, Lc);
 }
 void sph_prolong_add32(const SLev& Lc, const SLev& Lf, hipStream_t st) {
-  k_sprolong<<<lgrid(Lf), dim3(BX, BY), 0, st>>>(Lc, Lf);
+  k_sprolong<<<lgrid_split(Lf), dim3(BX, BY), 0, st>>>(Lc, Lf);
 }
 void sph_coarse32(const double* inv, const SLev& L, hipStream_t st) {
   const int N = L.nr * L.nth * L.nph;
