@@ -84,57 +84,70 @@ __device__ inline void store_stream(T* p, T v) { __builtin_nontemporal_store(v, 
 // time, plane indices past k1 are clamped to planes inside the array, and
 // only the stores are predicated, so a wavefront keeps all of its planes'
 // loads in flight at once.  ZG: zero initial guess -- the other colour is
-// taken as 0 (first pass of a cycle on a zeroed correction).
-template <typename T, bool SOR, bool ZG, int KZP>
+// taken as 0 (first pass of a cycle on a zeroed correction).  DOT: also the
+// block's partial sum of -(f . x_new) over the updated nodes (the PCG inner
+// product when F holds the CG residual and X the preconditioned one).
+template <typename T, bool SOR, bool ZG, int KZP, bool DOT>
 __global__ __launch_bounds__(256) void k_pass7(T* __restrict__ X, const T* __restrict__ F, Geom G, int c,
-                                               T omega, T h2) {
+                                               T omega, T h2, double* __restrict__ partial) {
   int bx, by, bz;
   xcd_block(bx, by, bz);
   const int m = G.mlo() + bx * BX + (int)threadIdx.x;
   const int b = G.g + by * BY + (int)threadIdx.y;
   const int last = G.g + G.n - 2;
-  if (m > G.mhi() || b > last) return;
-  const int kz = planes_per_block(G);
-  const int k0 = G.g + bz * kz;
-  const int k1 = min(k0 + kz - 1, last);
-  const long long plane = (long long)G.M * G.W;
-  const long long W = G.W;
-  const long long q0 = G.row(b, 0) + m;  // (m, b) on plane 0
-  T* __restrict__ xc = X + (long long)c * G.cs + q0;
-  const T* __restrict__ xo = X + (long long)(c ^ 1) * G.cs + q0;
-  const T* __restrict__ fc = F + (long long)c * G.cs + q0;
-  const T sixth = (T)(1.0 / 6.0);
-  T z[KZP + 2];
-#pragma unroll
-  for (int t = 0; t < KZP + 2; ++t) z[t] = ZG ? (T)0 : xo[(long long)min(k0 - 1 + t, k1 + 1) * plane];
-  T xs[KZP], ym[KZP], yp[KZP], fv[KZP], old[KZP];
-#pragma unroll
-  for (int t = 0; t < KZP; ++t) {
-    const int k = min(k0 + t, k1);
-    const long long o = (long long)k * plane;
-    const int r = (c - b - k - G.off) & 1;  // node a = 2m + r of plane k has colour c
-    if (!ZG) {
-      xs[t] = xo[o + 2 * r - 1];
-      ym[t] = xo[o - W];
-      yp[t] = xo[o + W];
-    }
-    fv[t] = fc[o];
-    if (SOR) old[t] = xc[o];
+  const bool live = m <= G.mhi() && b <= last;
+  if constexpr (!DOT) {
+    if (!live) return;
   }
+  double acc = 0.0;
+  if (live) {
+    const int kz = planes_per_block(G);
+    const int k0 = G.g + bz * kz;
+    const int k1 = min(k0 + kz - 1, last);
+    const long long plane = (long long)G.M * G.W;
+    const long long W = G.W;
+    const long long q0 = G.row(b, 0) + m;  // (m, b) on plane 0
+    T* __restrict__ xc = X + (long long)c * G.cs + q0;
+    const T* __restrict__ xo = X + (long long)(c ^ 1) * G.cs + q0;
+    const T* __restrict__ fc = F + (long long)c * G.cs + q0;
+    const T sixth = (T)(1.0 / 6.0);
+    T z[KZP + 2];
 #pragma unroll
-  for (int t = 0; t < KZP; ++t) {
-    const int k = k0 + t;
-    const int r = (c - b - k - G.off) & 1;
-    if (k <= k1 && G.inner(2 * m + r)) {
-      T s = (T)0;
-      if (!ZG) s = z[t + 1] + xs[t] + ym[t] + yp[t] + z[t] + z[t + 2];
-      const T gs = (s - h2 * fv[t]) * sixth;
-      T* __restrict__ dst = xc + (long long)k * plane;
-      if (SOR)
-        *dst = ((T)1 - omega) * old[t] + omega * gs;
-      else
-        store_stream(dst, gs);
+    for (int t = 0; t < KZP + 2; ++t) z[t] = ZG ? (T)0 : xo[(long long)min(k0 - 1 + t, k1 + 1) * plane];
+    T xs[KZP], ym[KZP], yp[KZP], fv[KZP], old[KZP];
+#pragma unroll
+    for (int t = 0; t < KZP; ++t) {
+      const int k = min(k0 + t, k1);
+      const long long o = (long long)k * plane;
+      const int r = (c - b - k - G.off) & 1;  // node a = 2m + r of plane k has colour c
+      if (!ZG) {
+        xs[t] = xo[o + 2 * r - 1];
+        ym[t] = xo[o - W];
+        yp[t] = xo[o + W];
+      }
+      fv[t] = fc[o];
+      if (SOR) old[t] = xc[o];
     }
+#pragma unroll
+    for (int t = 0; t < KZP; ++t) {
+      const int k = k0 + t;
+      const int r = (c - b - k - G.off) & 1;
+      if (k <= k1 && G.inner(2 * m + r)) {
+        T s = (T)0;
+        if (!ZG) s = z[t + 1] + xs[t] + ym[t] + yp[t] + z[t] + z[t + 2];
+        const T gs = (s - h2 * fv[t]) * sixth;
+        T* __restrict__ dst = xc + (long long)k * plane;
+        if (SOR)
+          *dst = ((T)1 - omega) * old[t] + omega * gs;
+        else
+          store_stream(dst, gs);
+        if constexpr (DOT) acc += (double)fv[t] * (double)gs;
+      }
+    }
+  }
+  if constexpr (DOT) {
+    const double sum = block_sum(acc);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partial[linear_block()] = -sum;
   }
 }
 
@@ -1273,9 +1286,9 @@ template <typename T, bool SOR, bool ZG>
 static void pass7_kz(T* x, const T* f, const Geom& G, int colour, T omega, T h2, dim3 grid, dim3 blk,
                      hipStream_t st) {
   if (kz_for(G) == KZ)
-    k_pass7<T, SOR, ZG, KZ><<<grid, blk, 0, st>>>(x, f, G, colour, omega, h2);
+    k_pass7<T, SOR, ZG, KZ, false><<<grid, blk, 0, st>>>(x, f, G, colour, omega, h2, nullptr);
   else
-    k_pass7<T, SOR, ZG, 1><<<grid, blk, 0, st>>>(x, f, G, colour, omega, h2);
+    k_pass7<T, SOR, ZG, 1, false><<<grid, blk, 0, st>>>(x, f, G, colour, omega, h2, nullptr);
 }
 
 template <typename T>
@@ -1308,6 +1321,15 @@ void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, i
     else
       k_pass19w<double><<<grid, blk, 0, st>>>((double*)phi, (const double*)f, G, colour, h2, zmask);
   }
+}
+
+void colour_pass_dot(double* phi, const double* f, const Geom& G, int colour, double* partial, hipStream_t st) {
+  const dim3 grid = col_grid(G), blk(BX, BY);
+  const double h2 = G.h * G.h;
+  if (kz_for(G) == KZ)
+    k_pass7<double, false, false, KZ, true><<<grid, blk, 0, st>>>(phi, f, G, colour, 1.0, h2, partial);
+  else
+    k_pass7<double, false, false, 1, true><<<grid, blk, 0, st>>>(phi, f, G, colour, 1.0, h2, partial);
 }
 
 template <typename T, typename TO, int COL>

@@ -1069,14 +1069,26 @@ double rel_of(double r2, double bnorm) {
 // the colours already updated (the later ones are still zero), then
 // C-2 .. 0 backward; the backward sweep's first colour would repeat the
 // forward sweep's last from unchanged neighbours and is left out.
-void pcg_precondition(poisson_plan_s* P, hipStream_t st) {
+// Then partial[0 .. nb) holds the partial sums of -(r . z), nb returned.
+// On two-colour grids the passes that finish colours 1 and 0 form them
+// (2 cg_blocks); on four-colour grids a separate inner-product kernel.
+int pcg_precondition(poisson_plan_s* P, hipStream_t st) {
   const Geom& G = P->G0;
-  const int C = P->order == 2 ? 2 : 4;
+  const int cb = cg_blocks(G);
+  if (P->order == 2) {
+    colour_pass(P->cz, P->cr, false, G, 2, 0, 1.0, st, 2);  // colour 1 still zero
+    colour_pass_dot(P->cz, P->cr, G, 1, P->partial, st);
+    colour_pass_dot(P->cz, P->cr, G, 0, P->partial + cb, st);
+    return 2 * cb;
+  }
+  const int C = 4;
   for (int c = 0; c < C; ++c) {
     const int zmask = ((1 << C) - 1) & ~((2 << c) - 1);  // colours above c
     colour_pass(P->cz, P->cr, false, G, P->order, c, 1.0, st, zmask);
   }
   for (int c = C - 2; c >= 0; --c) colour_pass(P->cz, P->cr, false, G, P->order, c, 1.0, st);
+  pcg_dot(P->cr, P->cz, G, P->partial, st);
+  return cb;
 }
 
 // ------------------------------------------------------------ Cartesian solve
@@ -1217,9 +1229,7 @@ int solve_cart(poisson_plan_s* P, const double* rho, double* phi, double tol, po
     // CG kernels keep their signs (x -= alpha p, r -= alpha q); the inner
     // product rho . zeta = -(r . z) sits in v[kRR], ||r||^2 in v[kRes2].
     const int cb = cg_blocks(G);
-    pcg_precondition(P, st);
-    pcg_dot(P->cr, P->cz, G, P->partial, st);
-    finish_sum(P->partial, cb, 1, P->scal, kRR, st);
+    finish_sum(P->partial, pcg_precondition(P, st), 1, P->scal, kRR, st);
     const double zero = 0.0;
     HIPCHK(hipMemcpyAsync(&P->scal->v[2], &zero, sizeof(double), hipMemcpyHostToDevice, st));
     fill_zero(P->cp0, false, G.total(), st);
@@ -1230,9 +1240,7 @@ int solve_cart(poisson_plan_s* P, const double* rho, double* phi, double tol, po
       cg_scalars(P->partial, cb, P->scal, 0, st);
       cg_update(P->phi64, P->cr, pnew, P->cq, G, P->scal, P->partial, st);
       finish_sum(P->partial, cb, 1, P->scal, kRes2, st);
-      pcg_precondition(P, st);
-      pcg_dot(P->cr, P->cz, G, P->partial, st);
-      cg_scalars(P->partial, cb, P->scal, 1, st);
+      cg_scalars(P->partial, pcg_precondition(P, st), P->scal, 1, st);
       std::swap(pold, pnew);
       ++it;
       if (it % o.check_every == 0 || it == o.max_iter) {
