@@ -53,6 +53,32 @@ def test_served_results_match_oracle():
         assert rel_l2(host(phi)[s, s, s], ref[s, s, s]) < 1e-7
 
 
+def test_served_results_at_the_benchmark_sizes():
+    """The serving benchmark's launch configuration (8 slots, mixed
+    precision, sizes 32^3 .. 256^3, warm-started streams): every request up
+    to 128^3 and the first 256^3 one against the oracle."""
+    say("server: bench sizes vs oracle")
+    reqs = _stream(8, (32, 64, 128, 256), 4, seed=10)
+    assert sorted({r.n for r in reqs}) == [32, 64, 128, 256]
+    rhos = [r.density(DEV) for r in reqs]
+    srv = pg.Server(64 * GB, max_slots=8, mixed=True, tol=1e-10)
+    outs, res = _run(srv, reqs, rhos)
+    srv.close()
+    seen256 = False
+    for r, rho, phi, (st, lat) in zip(reqs, rhos, outs, res):
+        assert st.status == 0 and st.rel_residual <= 1e-10, st
+        if r.n == 256:
+            if seen256:
+                continue
+            seen256 = True
+        say(f"  {r.n}^3 stream {r.stream_id}: {st.iterations} steps")
+        rh = host(rho)
+        ghost, _ = OM.cart_boundary(rh, r.n, 1, 8)
+        ref = OD.solve_cart(ghost, rh, r.n, 1.0 / r.n, 2, 1)
+        s = slice(1, r.n)
+        assert rel_l2(host(phi)[s, s, s], ref[s, s, s]) < 1e-7
+
+
 def test_same_result_alone_and_in_the_mix():
     say("server: alone vs mix")
     reqs = _stream(24, (32, 64, 128), 6, seed=12)
