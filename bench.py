@@ -711,6 +711,8 @@ def main():
         "smoother_pass_ms": pass_ms,
         "smoother_gcell_updates_per_s": unknowns / (2 * pass_ms * 1e-3) / 1e9,
         "copy_GBps": copy_gbps,
+        # counter-measured HBM bytes of the fine pass over its event-timed duration
+        "smoother_traffic_GBps": (traffic / (pass_ms * 1e-3) / 1e9) if traffic else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
