@@ -60,7 +60,7 @@ extern "C" {
 
 #define POISSON_SOR            0  /* red-black SOR (Section 2.1.1); on spherical grids four
                                      colours (parity, half turn) and relaxation factors per
-                                     colatitude from Eq. local_rjac: omega_mode OPT (local
+                                     colatitude and radius from Eq. local_rjac: omega_mode OPT (local
                                      omega_opt), CHEBYSHEV (local Eq. omega_n from n = 1) or
                                      FIXED */
 #define POISSON_CG             1  /* conjugate gradients (Section 2.1.2) */
@@ -129,7 +129,7 @@ typedef struct {
 } poisson_grid_t;
 
 typedef struct {
-    int32_t method;      /* POISSON_SOR .. POISSON_MG_SPAI32 */
+    int32_t method;      /* POISSON_SOR .. POISSON_PCG */
     int32_t order;       /* Cartesian: 2 (7-point) or 6 (19-point star); POISSON_MG_SPAI(32):
                             2, 4 or 6 (compact); spherical: 2 */
     int32_t lmax;        /* >= 0: multipole boundary of this order (<= 8);
@@ -232,9 +232,9 @@ int poisson_op_residual(poisson_plan_t plan, const double* d_rho, const double* 
    four colours with omega = 1 for order 6 (Section 2.1.2).  POISSON_MG_SPAI
    plans: `sweeps` steps of the SPAI Richardson smoother (Eq. richardson;
    forward and omega are ignored).  Spherical POISSON_SOR plans: `sweeps`
-   SOR sweeps (colours 0, 2 then 1, 3) with the plan's per-colatitude
-   relaxation factors from the start of their sequence (forward and omega are
-   ignored). */
+   SOR sweeps (colours 0, 2 then 1, 3) with the plan's relaxation factors
+   per colatitude and radius from the start of their sequence (forward and
+   omega are ignored). */
 int poisson_op_smooth(poisson_plan_t plan, const double* d_rho, double* d_phi, int32_t sweeps,
                       int32_t forward, double omega);
 
