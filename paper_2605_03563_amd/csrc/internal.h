@@ -162,8 +162,9 @@ void resrestrict(const void* phi, const void* f, bool f32, const Geom& Gf, void*
                  hipStream_t st, bool r0only = false);
 void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom& Gc, bool f32,
                  hipStream_t st);
-// c0only (two-colour levels): correct colour-0 nodes only, when a
-// Gauss-Seidel pass over colour 1 follows and overwrites the others.
+// c0only: leave the last colour (1 of two, 3 of four) uncorrected, when a
+// Gauss-Seidel pass over that colour follows, which reads no value of its
+// own colour and overwrites them all.
 void prolong_add(const void* e_coarse, const Geom& Gc, void* phi_fine, const Geom& Gf, bool f32,
                  hipStream_t st, bool c0only = false);
 void coarse_solve(const double* inv, const void* f, void* phi, bool f32, const Geom& G, hipStream_t st);

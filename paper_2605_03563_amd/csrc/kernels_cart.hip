@@ -763,7 +763,7 @@ __global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ Ec, G
 // coarse values it needs on a coarse plane (interpolated along x, and along
 // y when the fine row is odd) are formed once per coarse plane and kept for
 // the two or three fine planes that use them.
-template <typename T>
+template <typename T, bool SKIP3>
 __global__ __launch_bounds__(256) void k_prolong4(const T* __restrict__ Ec, Geom Gc, T* __restrict__ Xf, Geom Gf) {
   int bx, by, bz;
   xcd_block(bx, by, bz);
@@ -817,7 +817,7 @@ __global__ __launch_bounds__(256) void k_prolong4(const T* __restrict__ Ec, Geom
     const long long row = Gf.row(b, k);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (!in[q]) continue;
+      if (!in[q] || (SKIP3 && ((q + s) & 3) == 3)) continue;
       const T e = (l & 1) ? half * (cv[q] + nv[q]) : cv[q];
       Xf[(long long)((q + s) & 3) * Gf.cs + row + m] += e;
     }
@@ -1400,6 +1400,7 @@ void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom&
 
 void prolong_add(const void* e_coarse, const Geom& Gc, void* phi_fine, const Geom& Gf, bool f32,
                  hipStream_t st, bool c0only) {
+  // c0only: the last colour's correction is dead (see the declaration)
   const dim3 grid = col_grid(Gf), blk(BX, BY);
   if (Gf.C == 2 && Gf.g == 1) {
     if (f32) {
@@ -1416,10 +1417,17 @@ void prolong_add(const void* e_coarse, const Geom& Gc, void* phi_fine, const Geo
     return;
   }
   if (Gf.C == 4) {
-    if (f32)
-      k_prolong4<float><<<grid, blk, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
-    else
-      k_prolong4<double><<<grid, blk, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
+    if (f32) {
+      if (c0only)
+        k_prolong4<float, true><<<grid, blk, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
+      else
+        k_prolong4<float, false><<<grid, blk, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
+    } else {
+      if (c0only)
+        k_prolong4<double, true><<<grid, blk, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
+      else
+        k_prolong4<double, false><<<grid, blk, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
+    }
     return;
   }
   if (f32)

@@ -810,9 +810,10 @@ void w4_matrix(const W4& w, int n, std::vector<double>& A) {
 // a refinement step), so the first forward sweep reads colours it has not yet
 // updated as zero instead of clearing the array first.  On two-colour levels
 // a Gauss-Seidel pass leaves its colour's residual at zero: after the
-// pre-smoothing (last colour 1) only colour-0 residuals are restricted, and
-// the correction goes to colour-0 nodes only, since the first post-smoothing
-// pass (colour 1) reads no colour-1 value and overwrites them all.
+// pre-smoothing (last colour 1) only colour-0 residuals are restricted.  On
+// every level the correction skips the last colour, since the first
+// post-smoothing pass (that colour) reads none of its values and overwrites
+// them all.
 void vcycle(poisson_plan_s* P, int l, bool zero_guess, hipStream_t st) {
   Level& L = P->lv[l];
   const bool f32 = P->mg32;
@@ -837,7 +838,7 @@ void vcycle(poisson_plan_s* P, int l, bool zero_guess, hipStream_t st) {
     restrict_fw(L.tmp, L.G, Lc.f, Lc.G, f32, st);
   }
   vcycle(P, l + 1, true, st);
-  prolong_add(Lc.phi, Lc.G, L.phi, L.G, f32, st, C == 2 && o.nu2 > 0);
+  prolong_add(Lc.phi, Lc.G, L.phi, L.G, f32, st, o.nu2 > 0);
   for (int s = 0; s < o.nu2; ++s)
     for (int c = C - 1; c >= 0; --c) colour_pass(L.phi, L.f, f32, L.G, P->order, c, 1.0, st);
 }
