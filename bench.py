@@ -372,8 +372,8 @@ def spai(args):
         "time_to_1e-8_ms": sec * 1e3, "cycles": row["cycles"], "rows": rows, "coarse_rows": coarse_rows,
         "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_spai(args.cpu_budget_s),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "k_nspai<double> (fused fine-level SPAI step)",
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic_from_profiles("spai_step_f64_511"),
+                     "kernel": "k_nspai<double, 16> (fused fine-level SPAI step)",
                      "algorithmic_bytes_per_launch": bytes_per_step, "step_ms": step_ms},
     }
     print(json.dumps(out), flush=True)
@@ -470,9 +470,16 @@ def kernels_only(args):
     import workloads as W
 
     dev = "cuda:0"
-    wl = W.config_c2(n=args.n, device=dev)
-    rho = wl.rho.contiguous()
-    plan = pg.Plan(pg.cart_grid(args.n), pg.options("mg", lmax=8), device=dev)
+    if args.workload == "spai":
+        # the fused SPAI step at 511^3 (one V(1,1) cycle's solve, then resident steps)
+        wl = W.config_c3(n=512, device=dev, g=1)
+        rho = wl.rho.contiguous()
+        plan = pg.Plan(pg.cart_grid(512), pg.options("mg_spai", order=2, lmax=8, nu1=1, nu2=1, coarsest=4,
+                                                      max_iter=1), device=dev)
+    else:
+        wl = W.config_c2(n=args.n, device=dev)
+        rho = wl.rho.contiguous()
+        plan = pg.Plan(pg.cart_grid(args.n), pg.options("mg", lmax=8), device=dev)
     phi = torch.zeros_like(rho)
     plan.solve(rho, phi, tol=args.tol)
     pg.sweep_resident(plan, args.sweeps)
