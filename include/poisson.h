@@ -53,6 +53,7 @@ extern "C" {
 #define POISSON_EHIP         -4   /* a HIP runtime call failed */
 #define POISSON_ENUMERIC     -5   /* NaN/Inf residual or Krylov breakdown */
 #define POISSON_EADMIT       -6   /* serving: request larger than the whole memory budget */
+#define POISSON_ETIMEOUT     -7   /* serving: poisson_server_wait ran out of time (the request goes on) */
 
 /* ---- enumerations ---------------------------------------------------- */
 #define POISSON_CARTESIAN      0
@@ -178,6 +179,17 @@ size_t poisson_workspace_bytes(const poisson_grid_t* grid, const poisson_opts_t*
 int poisson_plan(poisson_plan_t* out, const poisson_grid_t* grid, const poisson_opts_t* opts,
                  void* d_workspace, size_t ws_bytes, void* stream);
 
+/* Multigrid plans (and the multigrid-preconditioned BiCGSTAB) launch each
+   iteration as one recorded HIP graph.  The graph is recorded on `stream`, a
+   caller-owned hipStream_t other than the NULL stream that must outlive the
+   plan and carry no other work while a poisson_* call of this plan runs;
+   nothing is executed on it.  Without a capture stream the graph is recorded
+   on the plan's own stream, and when that is the NULL stream (which cannot be
+   recorded) every iteration is launched kernel by kernel instead, with the
+   same results.  The library creates no stream.  POISSON_EINVAL for a NULL
+   plan or stream. */
+int poisson_plan_set_capture_stream(poisson_plan_t plan, void* stream);
+
 /* Section 2.2: compute the multipole moments of d_rho (sums over the
    unknown nodes with weight h^3, or r^3 ds sin(theta) dtheta dphi on the
    spherical grid; expansion origin at the box centre / r = 0) and overwrite
@@ -271,29 +283,43 @@ int poisson_op_precond(poisson_plan_t plan, const double* d_y, double* d_yhat);
    A persistent worker thread advances every admitted request by one
    multigrid iteration at a time on its own stream slot, so requests of
    different sizes overlap on the device; requests that arrive while others
-   run are admitted as slots and memory free up.  Device memory (plan
-   workspaces and one cached potential per stream id) is allocated by the
-   server within budget_bytes; idle plans and cached potentials are released
-   least-recently-used first.  Each stream id's last potential is the initial
-   guess of its next request (Section 2.1: the previous potential as initial
-   estimate).  A result depends only on its density and its stream's history,
-   not on what else is running. */
+   run are admitted as slots and memory free up.  The caller owns every
+   device resource: plan workspaces and one cached potential per stream id
+   are ranges of the caller's arena, handed out first fit and returned to a
+   free list (merged with free neighbours) when idle plans and cached
+   potentials are released, least recently used first; the slot streams are
+   the caller's.  The server allocates no device memory and creates no
+   stream.  Each stream id's last potential is the initial guess of its next
+   request (Section 2.1: the previous potential as initial estimate).  A
+   result depends only on its density and its stream's history, not on what
+   else is running. */
 typedef struct poisson_server_s* poisson_server_t;
 
-/* max_slots in 1..16 concurrent requests; mixed != 0: FP32 V-cycles inside
-   FP64 refinement (7-point), else FP64 V-cycles; lmax: multipole order of the
-   open boundary; nu: smoothing sweeps nu1 = nu2; tol: relative residual
-   target; warm_start: reuse each stream's previous potential; use_graphs:
-   launch each iteration as one captured graph.  Uses the current device. */
-int poisson_server_create(poisson_server_t* out, size_t budget_bytes, int32_t max_slots, int32_t mixed,
-                          int32_t lmax, int32_t nu, double tol, int32_t warm_start, int32_t use_graphs);
+/* d_arena: caller-owned device memory of arena_bytes (256-byte aligned) that
+   the server uses, and nothing else, until poisson_server_destroy returns;
+   arena_bytes is the memory budget.  slot_streams: max_slots (1..16)
+   caller-owned hipStream_t, none the NULL stream, that must outlive the
+   server; the server launches on them and records its graphs on them.
+   mixed != 0: FP32 V-cycles inside FP64 refinement (7-point), else FP64
+   V-cycles; lmax: multipole order of the open boundary; nu: smoothing sweeps
+   nu1 = nu2; tol: relative residual target; warm_start: reuse each stream's
+   previous potential; use_graphs: launch each iteration as one recorded
+   graph.  Uses the current device. */
+int poisson_server_create(poisson_server_t* out, void* d_arena, size_t arena_bytes, int32_t max_slots,
+                          void* const* slot_streams, int32_t mixed, int32_t lmax, int32_t nu, double tol,
+                          int32_t warm_start, int32_t use_graphs);
 /* Queue a solve on the unit box with n = 8 * 2^L intervals per axis.
    d_rho and d_phi are caller-owned device arrays in natural layout with
    pitch (n+1, (n+1)^2) elements; both must stay valid until the request is
-   done; the potential is written into d_phi.  Returns POISSON_EADMIT when the
-   request alone exceeds the budget, POISSON_EGRID for other sizes. */
+   done; the potential is written into d_phi.  The request reads d_rho and
+   writes d_phi only after the work queued on caller_stream (a hipStream_t;
+   NULL = the NULL stream) before this call: an event recorded on it here is
+   waited for on the request's slot.  Once poisson_server_poll reports the
+   request done, d_phi holds the result on the device; it is not ordered with
+   any stream.  Returns POISSON_EADMIT when the request alone exceeds the
+   arena, POISSON_EGRID for other sizes. */
 int poisson_server_submit(poisson_server_t srv, int32_t stream_id, int32_t n, const double* d_rho,
-                          double* d_phi, int64_t* ticket);
+                          double* d_phi, void* caller_stream, int64_t* ticket);
 /* *done = 1 once the request has finished; then returns its status
    (POISSON_OK, POISSON_WARN_MAXITER or an error) and fills stats (NULL
    allowed; t_iter_ms = start-to-finish time on the device) and the latency
@@ -301,17 +327,20 @@ int poisson_server_submit(poisson_server_t srv, int32_t stream_id, int32_t n, co
 int poisson_server_poll(poisson_server_t srv, int64_t ticket, int32_t* done, poisson_stats_t* stats,
                         double* latency_ms);
 /* Block up to timeout_ms for a ticket; returns its status, or
-   POISSON_WARN_MAXITER on timeout. */
+   POISSON_ETIMEOUT when the time ran out first (the request is not
+   cancelled). */
 int poisson_server_wait(poisson_server_t srv, int64_t ticket, double timeout_ms);
 /* Build `count` (<= 16) plans of size n with their captured graphs ahead of
    traffic, within the budget, so that no request pays for plan construction;
    blocks until done.  Returns POISSON_EADMIT if they do not fit. */
 int poisson_server_reserve(poisson_server_t srv, int32_t n, int32_t count);
-/* Device bytes one request of size n occupies (plan workspace + cached potential). */
+/* Arena bytes one request of size n occupies (plan workspace + cached
+   potential, each rounded up to 256 bytes). */
 int poisson_server_footprint(poisson_server_t srv, int32_t n, size_t* bytes);
-/* Current device bytes held, queued and running request counts (any may be NULL). */
+/* Arena bytes in use, queued and running request counts (any may be NULL). */
 int poisson_server_usage(poisson_server_t srv, size_t* used_bytes, int32_t* queued, int32_t* active);
-/* Waits for every queued and running request, then releases everything. */
+/* Waits for every queued and running request, then releases the server;
+   the arena and the slot streams return to the caller. */
 void poisson_server_destroy(poisson_server_t srv);
 
 #ifdef __cplusplus

@@ -15,8 +15,8 @@ from typing import Optional
 import torch
 
 from . import _lib as L
-from ._lib import (BICGSTAB, BICGSTAB_MG32, CARTESIAN, CG, MG, MG_IR32, MG_SPAI, MG_SPAI32, OMEGA_CHEBYSHEV, OMEGA_FIXED,
-                   OMEGA_OPT, OMEGA_OPT_A, PCG, SOR, SPHERICAL_LOG, WARN_MAXITER)
+from ._lib import (BICGSTAB, BICGSTAB_MG32, CARTESIAN, CG, ETIMEOUT, MG, MG_IR32, MG_SPAI, MG_SPAI32, OMEGA_CHEBYSHEV,
+                   OMEGA_FIXED, OMEGA_OPT, OMEGA_OPT_A, PCG, SOR, SPHERICAL_LOG, WARN_MAXITER)
 
 METHODS = {"sor": SOR, "cg": CG, "bicgstab": BICGSTAB, "mg": MG, "mg_ir32": MG_IR32,
            "bicgstab_mg32": BICGSTAB_MG32, "mg_spai": MG_SPAI, "mg_spai32": MG_SPAI32, "pcg": PCG}
@@ -128,7 +128,9 @@ class SolveResult:
 
 
 class Plan:
-    """A solver plan with its device workspace (a torch uint8 tensor)."""
+    """A solver plan with its device workspace (a torch uint8 tensor), run on
+    `stream` (default: torch's current stream); a second torch stream, on
+    which nothing runs, records the plan's graphs."""
 
     def __init__(self, grid, opts, device="cuda:0", stream: Optional[torch.cuda.Stream] = None):
         self.lib = L.load()
@@ -139,11 +141,14 @@ class Plan:
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) & ~255
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.capture_stream = torch.cuda.Stream(self.device)
         handle = C.c_void_p()
         _check(self.lib.poisson_plan(C.byref(handle), C.byref(grid), C.byref(opts),
                                      C.c_void_p(self._ws_ptr), nbytes, C.c_void_p(self.stream.cuda_stream)),
                "poisson_plan")
         self.handle = handle
+        _check(self.lib.poisson_plan_set_capture_stream(handle, C.c_void_p(self.capture_stream.cuda_stream)),
+               "poisson_plan_set_capture_stream")
 
     @property
     def node_elems(self) -> int:
@@ -225,21 +230,37 @@ class Plan:
 
 
 class Server:
-    """Continuous-batching solve server (a persistent loop in the library)."""
+    """Continuous-batching solve server (a persistent loop in the library).
+    Its device memory is one torch uint8 arena of budget_bytes and its slots
+    are max_slots torch streams; the library carves plans and cached
+    potentials from the arena and launches on those streams."""
 
     def __init__(self, budget_bytes: int, max_slots=8, mixed=True, lmax=8, nu=2, tol=1e-8, warm_start=True,
-                 use_graphs=True):
+                 use_graphs=True, device="cuda:0"):
         self.lib = L.load()
+        self.device = torch.device(device)
+        budget = int(budget_bytes)
+        self.arena = torch.empty(budget + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.arena.data_ptr() + 255) & ~255
+        self.streams = [torch.cuda.Stream(self.device) for _ in range(max_slots)]
+        handles = (C.c_void_p * max_slots)(*[s.cuda_stream for s in self.streams])
+        self._held = {}   # ticket -> (rho, phi): kept alive until the request is done
         h = C.c_void_p()
-        _check(self.lib.poisson_server_create(C.byref(h), int(budget_bytes), max_slots, int(mixed), lmax, nu, tol,
-                                              int(warm_start), int(use_graphs)), "poisson_server_create")
+        _check(self.lib.poisson_server_create(C.byref(h), C.c_void_p(ptr), budget, max_slots, handles, int(mixed),
+                                              lmax, nu, tol, int(warm_start), int(use_graphs)),
+               "poisson_server_create")
         self.handle = h
 
-    def submit(self, stream_id: int, n: int, rho: torch.Tensor, phi: torch.Tensor) -> int:
+    def submit(self, stream_id: int, n: int, rho: torch.Tensor, phi: torch.Tensor,
+               stream: Optional[torch.cuda.Stream] = None) -> int:
+        """Queue a solve; it starts after the work already queued on `stream`
+        (default: torch's current stream), which produced rho and phi."""
         t = C.c_int64()
         need = (n + 1) ** 3
+        st = stream if stream is not None else torch.cuda.current_stream(self.device)
         _check(self.lib.poisson_server_submit(self.handle, stream_id, n, _ptr(rho, need), _ptr(phi, need),
-                                              C.byref(t)), "poisson_server_submit")
+                                              C.c_void_p(st.cuda_stream), C.byref(t)), "poisson_server_submit")
+        self._held[t.value] = (rho, phi)
         return t.value
 
     def poll(self, ticket: int):
@@ -250,10 +271,13 @@ class Server:
         if not done.value:
             _check(status, "poisson_server_poll")
             return None
+        self._held.pop(ticket, None)
         return SolveResult(status, st.iterations, st.rel_residual, st.b_norm, st.rate, 0.0, st.t_iter_ms, []), \
             lat.value
 
     def wait(self, ticket: int, timeout_ms: float = 120000.0) -> int:
+        """The request's status once done, or ETIMEOUT (-7) if timeout_ms ran
+        out first."""
         return self.lib.poisson_server_wait(self.handle, ticket, timeout_ms)
 
     def reserve(self, n: int, count: int):
@@ -276,6 +300,7 @@ class Server:
         if getattr(self, "handle", None) is not None and self.handle.value:
             self.lib.poisson_server_destroy(self.handle)
             self.handle = None
+            self._held.clear()
 
     def __del__(self):
         try:

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpoisson_mi355x.so")
 
 OK, WARN_MAXITER = 0, 1
-EINVAL, EGRID, EWORKSPACE, EHIP, ENUMERIC, EADMIT = -1, -2, -3, -4, -5, -6
+EINVAL, EGRID, EWORKSPACE, EHIP, ENUMERIC, EADMIT, ETIMEOUT = -1, -2, -3, -4, -5, -6, -7
 
 CARTESIAN, SPHERICAL_LOG = 0, 1
 SOR, CG, BICGSTAB, MG, MG_IR32, BICGSTAB_MG32, MG_SPAI, MG_SPAI32, PCG = 0, 1, 2, 3, 4, 5, 6, 7, 8
@@ -47,6 +47,7 @@ SIGNATURES = {
                                      C.POINTER(C.c_double)]),
     "poisson_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Grid), C.c_double,
                                 C.POINTER(Stats)]),
+    "poisson_plan_set_capture_stream": (C.c_int, [C.c_void_p, C.c_void_p]),
     "poisson_plan_destroy": (None, [C.c_void_p]),
     "poisson_strerror": (C.c_char_p, [C.c_int]),
     "poisson_last_error": (C.c_char_p, []),
@@ -60,9 +61,10 @@ SIGNATURES = {
     "poisson_op_vcycle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "poisson_op_sweep_resident": (C.c_int, [C.c_void_p, C.c_int32]),
     "poisson_op_precond": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
-    "poisson_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_size_t, C.c_int32, C.c_int32, C.c_int32,
-                                        C.c_int32, C.c_double, C.c_int32, C.c_int32]),
-    "poisson_server_submit": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+    "poisson_server_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t, C.c_int32,
+                                        C.POINTER(C.c_void_p), C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                        C.c_int32, C.c_int32]),
+    "poisson_server_submit": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                         C.POINTER(C.c_int64)]),
     "poisson_server_poll": (C.c_int, [C.c_void_p, C.c_int64, C.POINTER(C.c_int32), C.POINTER(Stats),
                                       C.POINTER(C.c_double)]),

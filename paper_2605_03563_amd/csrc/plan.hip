@@ -892,6 +892,11 @@ void sph_mg_iteration(poisson_plan_s* P, double* phi, hipStream_t st) {
   bicg_scalars(P->partial, nb, P->scal, 2, st);
 }
 
+// Stream on which the plan's graphs are recorded: the caller's capture
+// stream when one was given, else the plan's own stream; the NULL stream
+// cannot be captured, so with neither the steps run kernel by kernel.
+hipStream_t capture_stream(const poisson_plan_s* P) { return P->cap ? P->cap : P->st; }
+
 int capture_sph_iteration(poisson_plan_s* P, double* phi) {
   if (P->iter_exec && P->iter_phi == phi) return POISSON_OK;
   if (P->iter_exec) {
@@ -899,9 +904,10 @@ int capture_sph_iteration(poisson_plan_s* P, double* phi) {
     P->iter_exec = nullptr;
   }
   hipGraph_t graph = nullptr;
-  HIPCHK(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
-  sph_mg_iteration(P, phi, P->cap);
-  hipError_t e = hipStreamEndCapture(P->cap, &graph);
+  hipStream_t cs = capture_stream(P);
+  HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  sph_mg_iteration(P, phi, cs);
+  hipError_t e = hipStreamEndCapture(cs, &graph);
   if (e != hipSuccess) {
     set_error("graph capture failed: %s", hipGetErrorString(e));
     return POISSON_EHIP;
@@ -982,12 +988,13 @@ void mg_step(poisson_plan_s* P, hipStream_t st) {
 int capture_step(poisson_plan_s* P) {
   if (P->step_exec) return POISSON_OK;
   hipGraph_t graph = nullptr;
-  HIPCHK(hipStreamBeginCapture(P->cap, hipStreamCaptureModeThreadLocal));
+  hipStream_t cs = capture_stream(P);
+  HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
   if (!P->nlv.empty())
-    spai_step(P, P->cap);
+    spai_step(P, cs);
   else
-    mg_step(P, P->cap);
-  hipError_t e = hipStreamEndCapture(P->cap, &graph);
+    mg_step(P, cs);
+  hipError_t e = hipStreamEndCapture(cs, &graph);
   if (e != hipSuccess) {
     set_error("graph capture failed: %s", hipGetErrorString(e));
     return POISSON_EHIP;
@@ -999,6 +1006,21 @@ int capture_step(poisson_plan_s* P) {
     set_error("graph instantiation failed: %s", hipGetErrorString(e));
     return POISSON_EHIP;
   }
+  return POISSON_OK;
+}
+
+// One multigrid iteration on the plan's stream: the captured graph when the
+// plan has a stream to record it on, else its kernels one by one.
+int launch_step(poisson_plan_s* P) {
+  if (!capture_stream(P)) {
+    if (!P->nlv.empty())
+      spai_step(P, P->st);
+    else
+      mg_step(P, P->st);
+    return launch_check("multigrid step");
+  }
+  CHK(capture_step(P));
+  HIPCHK(hipGraphLaunch(P->step_exec, P->st));
   return POISSON_OK;
 }
 
@@ -1150,9 +1172,8 @@ int solve_spai(poisson_plan_s* P, const double* rho, double* phi, double tol, po
   }
   int it = 0;
   bool conv = rel <= tol;
-  CHK(capture_step(P));
   while (!conv && it < o.max_iter) {
-    HIPCHK(hipGraphLaunch(P->step_exec, st));
+    CHK(launch_step(P));
     ++it;
     if (it % o.check_every == 0 || it == o.max_iter) {
       CHK(read_scalars(P, kRes2, 1));
@@ -1285,9 +1306,8 @@ int solve_cart(poisson_plan_s* P, const double* rho, double* phi, double tol, po
       }
     }
   } else {  // multigrid
-    CHK(capture_step(P));
     while (!conv && it < o.max_iter) {
-      HIPCHK(hipGraphLaunch(P->step_exec, st));
+      CHK(launch_step(P));
       ++it;
       if (it % o.check_every == 0 || it == o.max_iter) {
         CHK(read_scalars(P, kRes2, 1));
@@ -1437,10 +1457,13 @@ int solve_sph(poisson_plan_s* P, const double* rho, double* phi, double tol, poi
   double* v = P->sv[0];
   double* shat = P->sv[1];
   const bool mg = o.method == POISSON_BICGSTAB_MG32;
-  if (mg) CHK(capture_sph_iteration(P, phi));
+  const bool mg_graph = mg && capture_stream(P) != nullptr;
+  if (mg_graph) CHK(capture_sph_iteration(P, phi));
   while (!conv && it < o.max_iter) {
-    if (mg) {
+    if (mg_graph) {
       HIPCHK(hipGraphLaunch(P->iter_exec, st));
+    } else if (mg) {
+      sph_mg_iteration(P, phi, st);
     } else {
       pbicg_direction(P->sr, p, v, phat, S, P->sc, P->scal, st);
       pbicg_apply(phat, v, P->srh, 0, S, P->sc, P->partial, st);
@@ -1500,11 +1523,7 @@ int psn::cart_step(poisson_plan_s* P, bool use_graph) {
     set_error("multigrid plan expected");
     return POISSON_EINVAL;
   }
-  if (use_graph) {
-    CHK(capture_step(P));
-    HIPCHK(hipGraphLaunch(P->step_exec, P->st));
-    return POISSON_OK;
-  }
+  if (use_graph) return launch_step(P);
   mg_step(P, P->st);
   return launch_check("multigrid step");
 }
@@ -1514,7 +1533,7 @@ int psn::cart_prepare_graph(poisson_plan_s* P) {
     set_error("multigrid plan expected");
     return POISSON_EINVAL;
   }
-  return capture_step(P);
+  return capture_stream(P) ? capture_step(P) : POISSON_OK;
 }
 
 int psn::cart_finish(poisson_plan_s* P, double* phi) {
@@ -1596,11 +1615,6 @@ int poisson_plan(poisson_plan_t* out, const poisson_grid_t* grid, const poisson_
       set_error("event creation failed");
       return fail(POISSON_EHIP);
     }
-  if (hipStreamCreateWithFlags(&P->cap, hipStreamNonBlocking) != hipSuccess) {
-    set_error("stream creation failed");
-    P->cap = nullptr;
-    return fail(POISSON_EHIP);
-  }
   hipStream_t st = P->st;
   // zero the whole workspace once: ghosts of correction and direction
   // vectors must stay zero and are never written afterwards
@@ -1808,9 +1822,19 @@ void poisson_plan_destroy(poisson_plan_t P) {
   if (P->iter_exec) hipGraphExecDestroy(P->iter_exec);
   for (int i = 0; i < 3; ++i)
     if (P->ev[i]) hipEventDestroy(P->ev[i]);
-  if (P->cap) hipStreamDestroy(P->cap);
   if (P->host) hipHostFree(P->host);
   delete P;
+}
+
+int poisson_plan_set_capture_stream(poisson_plan_t P, void* stream) {
+  if (!P || !stream) {
+    set_error("a plan and a non-NULL capture stream are needed");
+    return POISSON_EINVAL;
+  }
+  // graphs recorded before stay valid: a graph does not depend on the stream
+  // it was recorded on
+  P->cap = (hipStream_t)stream;
+  return POISSON_OK;
 }
 
 int multipole_boundary(poisson_plan_t P, const double* d_rho, double* d_phi, int32_t lmax, double* h_q) {
@@ -1856,6 +1880,7 @@ const char* poisson_strerror(int s) {
     case POISSON_EHIP: return "HIP runtime error";
     case POISSON_ENUMERIC: return "non-finite residual or breakdown";
     case POISSON_EADMIT: return "request exceeds the memory budget";
+    case POISSON_ETIMEOUT: return "timed out waiting for a request";
     default: return "unknown status";
   }
 }

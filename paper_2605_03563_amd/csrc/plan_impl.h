@@ -36,7 +36,7 @@ struct poisson_plan_s {
   poisson_grid_t grid{};
   poisson_opts_t opts{};
   hipStream_t st = nullptr;
-  hipStream_t cap = nullptr;  // private stream used only to capture graphs
+  hipStream_t cap = nullptr;  // caller's stream for recording graphs (nullptr: the plan's stream)
   bool sph = false;
   int order = 2;
   int C = 2;

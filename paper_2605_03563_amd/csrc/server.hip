@@ -1,19 +1,23 @@
 // Serving loop: continuous batching of independent Poisson solves.
 //
-// A persistent worker thread owns up to 16 HIP streams ("slots", default
-// priority).  Requests (stream id, grid size, density, output array) queue in
+// A persistent worker thread drives up to 16 caller-owned HIP streams
+// ("slots").  Requests (stream id, grid size, density, output array) queue in
 // arrival order and are admitted while a slot is free and their device
 // footprint -- plan workspace plus the stream's cached potential -- fits the
-// memory budget (least recently used idle plans and cached potentials are
-// released to make room).  Each admitted request is advanced one multigrid
-// iteration at a time on its slot stream (a graph launch of the plan's
-// captured step), so requests of different sizes overlap on the device; the
-// worker polls one event per slot and never blocks on the device.  When a
-// request converges its potential is written to the caller's array and kept
-// on the device as the next initial guess of the same stream id (Section 2.1:
-// the previous potential as initial estimate).  Results do not depend on the
-// mix: every plan of a size computes identically and all reductions run in a
-// fixed order.
+// caller's device arena (least recently used idle plans and cached potentials
+// are released to make room).  Plan workspaces and cached potentials are
+// ranges of that one arena, handed out first-fit from a free list whose
+// released ranges merge with their neighbours; the server itself allocates no
+// device memory and creates no stream.  Each admitted request first waits on
+// its slot for the work the caller had queued on its own stream before
+// submitting, then advances one multigrid iteration at a time (a graph launch
+// of the plan's captured step), so requests of different sizes overlap on the
+// device; the worker polls one event per slot and never blocks on the device.
+// When a request converges its potential is written to the caller's array
+// and kept in the arena as the next initial guess of the same stream id
+// (Section 2.1: the previous potential as initial estimate).  Results do not
+// depend on the mix: every plan of a size computes identically and all
+// reductions run in a fixed order.
 #include <math.h>
 #include <string.h>
 
@@ -23,6 +27,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
@@ -36,6 +41,74 @@ using namespace psn;
 namespace {
 
 constexpr int kMaxSlots = 16;
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
+
+// First-fit ranges of the caller's device arena.  free_ maps the offset of
+// every free range to its size; adjacent free ranges are always merged.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  std::atomic<size_t> used{0};
+  std::map<size_t, size_t> free_;
+
+  void init(void* b, size_t bytes) {
+    base = (char*)b;
+    cap = bytes & ~(kAlign - 1);
+    free_.clear();
+    if (cap) free_[0] = cap;
+    used = 0;
+  }
+  void* take(size_t bytes) {
+    bytes = round_up(bytes);
+    for (auto it = free_.begin(); it != free_.end(); ++it)
+      if (it->second >= bytes) {
+        const size_t off = it->first, rest = it->second - bytes;
+        free_.erase(it);
+        if (rest) free_[off + bytes] = rest;
+        used += bytes;
+        return base + off;
+      }
+    return nullptr;
+  }
+  void give(void* p, size_t bytes) {
+    if (!p) return;
+    bytes = round_up(bytes);
+    size_t off = (size_t)((char*)p - base);
+    used -= bytes;
+    auto nx = free_.lower_bound(off);
+    if (nx != free_.end() && off + bytes == nx->first) {  // merge with the next range
+      bytes += nx->second;
+      nx = free_.erase(nx);
+    }
+    if (nx != free_.begin()) {
+      auto pv = std::prev(nx);
+      if (pv->first + pv->second == off) {  // and with the previous one
+        pv->second += bytes;
+        return;
+      }
+    }
+    free_[off] = bytes;
+  }
+  // would first-fit placement of every size, in order, succeed now?
+  bool fits(const std::vector<size_t>& sizes) const {
+    std::vector<size_t> room;
+    for (auto& kv : free_) room.push_back(kv.second);
+    for (size_t b : sizes) {
+      b = round_up(b);
+      bool ok = false;
+      for (size_t& r : room)
+        if (r >= b) {
+          r -= b;
+          ok = true;
+          break;
+        }
+      if (!ok) return false;
+    }
+    return true;
+  }
+};
 
 double now_ms() {
   using namespace std::chrono;
@@ -76,6 +149,7 @@ struct Request {
   double bnorm = 0.0, rel = 0.0;
   int slot = -1;
   PlanEntry* plan = nullptr;
+  hipEvent_t ready = nullptr;  // recorded on the caller's stream at submission
 };
 
 }  // namespace
@@ -87,14 +161,14 @@ struct poisson_server_s {
   int lmax = 8, nu = 2, max_iter = 100;
   double tol = 1e-8;
   int device = 0;
-  hipStream_t streams[kMaxSlots] = {};
+  Arena arena;                          // the caller's device memory
+  hipStream_t streams[kMaxSlots] = {};  // the caller's slot streams
   hipEvent_t events[kMaxSlots] = {};
   Request* slot_req[kMaxSlots] = {};
   double* pinned = nullptr;  // 2 doubles per slot
   std::vector<PlanEntry*> plans;
   std::unordered_map<int, CacheEntry> cache;
   std::unordered_map<int, int> running;  // stream id -> running requests (0 or 1)
-  size_t used = 0;
   uint64_t clock = 0;
   std::mutex mu;
   std::condition_variable cv;
@@ -142,25 +216,26 @@ size_t plan_bytes(const poisson_server_s* S, int n) {
 
 size_t phi_bytes(int n) { return sizeof(double) * (size_t)(n + 1) * (n + 1) * (n + 1); }
 
-// Device bytes a request still needs allocated to start now.
-size_t need_bytes(poisson_server_s* S, const Request* r) {
-  size_t need = 0;
+// Arena ranges a request still needs to start now.
+std::vector<size_t> need_ranges(poisson_server_s* S, const Request* r) {
+  std::vector<size_t> need;
   bool have_plan = false;
   for (PlanEntry* p : S->plans)
     if (!p->busy && p->n == r->n) have_plan = true;
-  if (!have_plan) need += plan_bytes(S, r->n);
+  if (!have_plan) need.push_back(plan_bytes(S, r->n));
   if (S->warm) {
     auto it = S->cache.find(r->stream_id);
-    if (it == S->cache.end() || it->second.n != r->n) need += phi_bytes(r->n);
+    if (it == S->cache.end() || it->second.n != r->n) need.push_back(phi_bytes(r->n));
   }
   return need;
 }
 
 // Release idle plans and cached potentials (least recently used first) until
-// `need` more bytes fit the budget, sparing plans of size keep_n (about to be
-// reused) and the cached potential of keep_stream.  Returns true when they fit.
-bool make_room(poisson_server_s* S, size_t need, int keep_stream, int keep_n) {
-  while (S->used + need > S->budget) {
+// ranges of the sizes in `need` can be taken from the arena, sparing plans of
+// size keep_n (about to be reused) and the cached potential of keep_stream.
+// Returns true when they fit.
+bool make_room(poisson_server_s* S, const std::vector<size_t>& need, int keep_stream, int keep_n) {
+  while (!S->arena.fits(need)) {
     uint64_t best = UINT64_MAX;
     int kind = -1;
     size_t pi = 0;
@@ -174,8 +249,9 @@ bool make_room(poisson_server_s* S, size_t need, int keep_stream, int keep_n) {
         kind = 0;
         pi = i;
       }
+    // a stream's cached potential of another size is replaced anyway
     for (auto& kv : S->cache)
-      if (!kv.second.in_use && kv.first != keep_stream && kv.second.last_use < best) {
+      if (!kv.second.in_use && (kv.first != keep_stream || kv.second.n != keep_n) && kv.second.last_use < best) {
         best = kv.second.last_use;
         kind = 1;
         ck = kv.first;
@@ -184,14 +260,12 @@ bool make_room(poisson_server_s* S, size_t need, int keep_stream, int keep_n) {
     if (kind == 0) {
       PlanEntry* p = S->plans[pi];
       poisson_plan_destroy(p->plan);
-      (void)hipFree(p->ws);
-      S->used -= p->bytes;
+      S->arena.give(p->ws, p->bytes);
       delete p;
       S->plans.erase(S->plans.begin() + pi);
     } else {
       CacheEntry& c = S->cache[ck];
-      (void)hipFree(c.phi);
-      S->used -= c.bytes;
+      S->arena.give(c.phi, c.bytes);
       S->cache.erase(ck);
     }
   }
@@ -209,28 +283,29 @@ PlanEntry* take_plan(poisson_server_s* S, int n, int slot, int* status, bool for
     pe = new PlanEntry();
     pe->n = n;
     pe->bytes = plan_bytes(S, n);
-    if (hipMalloc(&pe->ws, pe->bytes) != hipSuccess) {
+    pe->ws = S->arena.take(pe->bytes);
+    if (!pe->ws) {
+      set_error("no arena range of %zu bytes for a plan", pe->bytes);
       delete pe;
-      *status = POISSON_EHIP;
+      *status = POISSON_EADMIT;
       return nullptr;
     }
     poisson_grid_t g = grid_for(n);
     poisson_opts_t o = opts_for(S);
     int s = poisson_plan(&pe->plan, &g, &o, pe->ws, pe->bytes, S->streams[slot]);
     if (s != POISSON_OK) {
-      (void)hipFree(pe->ws);
+      S->arena.give(pe->ws, pe->bytes);
       delete pe;
       *status = s;
       return nullptr;
     }
     if (S->graphs && cart_prepare_graph(pe->plan) != POISSON_OK) {
       poisson_plan_destroy(pe->plan);
-      (void)hipFree(pe->ws);
+      S->arena.give(pe->ws, pe->bytes);
       delete pe;
       *status = POISSON_EHIP;
       return nullptr;
     }
-    S->used += pe->bytes;
     S->plans.push_back(pe);
   }
   pe->busy = true;
@@ -248,6 +323,10 @@ void complete(poisson_server_s* S, Request* r, int status) {
   auto it = S->cache.find(r->stream_id);
   if (it != S->cache.end()) it->second.in_use = false;
   S->running.erase(r->stream_id);
+  if (r->ready) {
+    (void)hipEventDestroy(r->ready);
+    r->ready = nullptr;
+  }
   std::lock_guard<std::mutex> lk(S->mu);
   r->status = status;
   r->t_done = now_ms();
@@ -275,23 +354,28 @@ void start(poisson_server_s* S, Request* r, int slot) {
     complete(S, r, status);
     return;
   }
+  // the caller's work on rho and phi queued before submission comes first
+  if (r->ready && hipStreamWaitEvent(st, r->ready, 0) != hipSuccess) {
+    fail_hip(S, r);
+    return;
+  }
   const size_t pb = phi_bytes(r->n);
   r->warm = false;
   if (S->warm) {
     CacheEntry& c = S->cache[r->stream_id];
     if (c.phi && c.n != r->n) {
-      (void)hipFree(c.phi);
-      S->used -= c.bytes;
+      S->arena.give(c.phi, c.bytes);
       c = CacheEntry();
     }
     if (!c.phi) {
-      if (hipMalloc((void**)&c.phi, pb) != hipSuccess) {
-        fail_hip(S, r);
+      c.phi = (double*)S->arena.take(pb);
+      if (!c.phi) {
+        set_error("no arena range of %zu bytes for a cached potential", pb);
+        complete(S, r, POISSON_EADMIT);
         return;
       }
       c.bytes = pb;
       c.n = r->n;
-      S->used += pb;
     }
     c.in_use = true;
     c.last_use = ++S->clock;
@@ -367,8 +451,7 @@ void do_reserve(poisson_server_s* S, int n, int count) {
     if (p->n == n) ++have;
   int status = POISSON_OK;
   for (; have < count && status == POISSON_OK; ++have) {
-    const size_t need = plan_bytes(S, n);
-    if (!make_room(S, need, -1, n)) {
+    if (!make_room(S, {plan_bytes(S, n)}, -1, n)) {
       status = POISSON_EADMIT;
       break;
     }
@@ -418,11 +501,14 @@ void worker_loop(poisson_server_s* S) {
           }
         if (!r) break;
       }
-      const size_t need = need_bytes(S, r);
-      if (!make_room(S, need, r->stream_id, r->n)) {
+      if (!make_room(S, need_ranges(S, r), r->stream_id, r->n)) {
         if (S->active == 0) {  // nothing will free up: the request can never fit
           std::lock_guard<std::mutex> lk(S->mu);
           S->queue.erase(S->queue.begin() + qi);
+          if (r->ready) {
+            (void)hipEventDestroy(r->ready);
+            r->ready = nullptr;
+          }
           r->phase = kDone;
           r->status = POISSON_EADMIT;
           r->t_done = now_ms();
@@ -467,14 +553,26 @@ void worker_loop(poisson_server_s* S) {
 
 extern "C" {
 
-int poisson_server_create(poisson_server_t* out, size_t budget_bytes, int32_t max_slots, int32_t mixed, int32_t lmax,
-                          int32_t nu, double tol, int32_t warm_start, int32_t use_graphs) {
-  if (!out || max_slots < 1 || max_slots > kMaxSlots || lmax < -1 || lmax > kLmaxMax || nu < 1 || !(tol > 0.0)) {
+int poisson_server_create(poisson_server_t* out, void* d_arena, size_t arena_bytes, int32_t max_slots,
+                          void* const* slot_streams, int32_t mixed, int32_t lmax, int32_t nu, double tol,
+                          int32_t warm_start, int32_t use_graphs) {
+  if (!out || !d_arena || !slot_streams || max_slots < 1 || max_slots > kMaxSlots || lmax < -1 ||
+      lmax > kLmaxMax || nu < 1 || !(tol > 0.0)) {
     set_error("invalid server option");
     return POISSON_EINVAL;
   }
+  if (((uintptr_t)d_arena & (kAlign - 1)) != 0) {
+    set_error("the arena must be %zu-byte aligned", kAlign);
+    return POISSON_EWORKSPACE;
+  }
+  for (int i = 0; i < max_slots; ++i)
+    if (!slot_streams[i]) {
+      set_error("slot stream %d is the NULL stream", i);
+      return POISSON_EINVAL;
+    }
   poisson_server_s* S = new poisson_server_s();
-  S->budget = budget_bytes;
+  S->budget = arena_bytes & ~(kAlign - 1);
+  S->arena.init(d_arena, arena_bytes);
   S->max_slots = max_slots;
   S->mixed = mixed != 0;
   S->lmax = lmax;
@@ -489,9 +587,9 @@ int poisson_server_create(poisson_server_t* out, size_t budget_bytes, int32_t ma
     return POISSON_EHIP;
   }
   for (int i = 0; i < max_slots; ++i) {
-    if (hipStreamCreateWithFlags(&S->streams[i], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&S->events[i], hipEventDisableTiming) != hipSuccess) {
-      set_error("server stream creation failed");
+    S->streams[i] = (hipStream_t)slot_streams[i];
+    if (hipEventCreateWithFlags(&S->events[i], hipEventDisableTiming) != hipSuccess) {
+      set_error("server event creation failed");
       poisson_server_destroy(S);
       return POISSON_EHIP;
     }
@@ -502,7 +600,7 @@ int poisson_server_create(poisson_server_t* out, size_t budget_bytes, int32_t ma
 }
 
 int poisson_server_submit(poisson_server_t S, int32_t stream_id, int32_t n, const double* d_rho, double* d_phi,
-                          int64_t* ticket) {
+                          void* caller_stream, int64_t* ticket) {
   if (!S || !d_rho || !d_phi || !ticket) {
     set_error("null argument");
     return POISSON_EINVAL;
@@ -511,16 +609,25 @@ int poisson_server_submit(poisson_server_t S, int32_t stream_id, int32_t n, cons
     set_error("serving grids need n = 8 * 2^L intervals (got %d)", n);
     return POISSON_EGRID;
   }
-  const size_t alone = plan_bytes(S, n) + (S->warm ? phi_bytes(n) : 0);
+  const size_t alone = round_up(plan_bytes(S, n)) + (S->warm ? round_up(phi_bytes(n)) : 0);
   if (alone > S->budget) {
-    set_error("request of %zu bytes exceeds the budget of %zu", alone, S->budget);
+    set_error("request of %zu bytes exceeds the arena of %zu", alone, S->budget);
     return POISSON_EADMIT;
+  }
+  // order the request after the caller's pending work on rho and phi
+  hipEvent_t ready = nullptr;
+  if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ready, (hipStream_t)caller_stream) != hipSuccess) {
+    if (ready) (void)hipEventDestroy(ready);
+    set_error("could not record the caller's stream");
+    return POISSON_EHIP;
   }
   Request* r = new Request();
   r->stream_id = stream_id;
   r->n = n;
   r->rho = d_rho;
   r->phi = d_phi;
+  r->ready = ready;
   r->t_submit = now_ms();
   std::lock_guard<std::mutex> lk(S->mu);
   r->ticket = S->next_ticket++;
@@ -576,7 +683,7 @@ int poisson_server_wait(poisson_server_t S, int64_t ticket, double timeout_ms) {
   while (r->phase != kDone)
     if (S->cv.wait_until(lk, deadline) == std::cv_status::timeout && r->phase != kDone) {
       set_error("timed out waiting for ticket %lld", (long long)ticket);
-      return POISSON_WARN_MAXITER;
+      return POISSON_ETIMEOUT;
     }
   return r->status;
 }
@@ -604,7 +711,7 @@ int poisson_server_footprint(poisson_server_t S, int32_t n, size_t* bytes) {
     set_error("null argument");
     return POISSON_EINVAL;
   }
-  *bytes = plan_bytes(S, n) + (S->warm ? phi_bytes(n) : 0);
+  *bytes = round_up(plan_bytes(S, n)) + (S->warm ? round_up(phi_bytes(n)) : 0);
   return POISSON_OK;
 }
 
@@ -614,7 +721,7 @@ int poisson_server_usage(poisson_server_t S, size_t* used_bytes, int32_t* queued
     return POISSON_EINVAL;
   }
   std::lock_guard<std::mutex> lk(S->mu);
-  if (used_bytes) *used_bytes = S->used;
+  if (used_bytes) *used_bytes = S->arena.used.load();
   if (queued) *queued = (int32_t)S->queue.size();
   if (active) *active = S->active;
   return POISSON_OK;
@@ -633,19 +740,15 @@ void poisson_server_destroy(poisson_server_t S) {
     S->worker.join();
   }
   for (int i = 0; i < kMaxSlots; ++i) {
-    if (S->streams[i]) {
-      (void)hipStreamSynchronize(S->streams[i]);
-      (void)hipStreamDestroy(S->streams[i]);
-    }
+    if (S->streams[i]) (void)hipStreamSynchronize(S->streams[i]);  // the caller's streams stay
     if (S->events[i]) (void)hipEventDestroy(S->events[i]);
   }
   for (PlanEntry* p : S->plans) {
     poisson_plan_destroy(p->plan);
-    (void)hipFree(p->ws);
     delete p;
   }
-  for (auto& kv : S->cache)
-    if (kv.second.phi) (void)hipFree(kv.second.phi);
+  for (auto& kv : S->reqs)
+    if (kv.second->ready) (void)hipEventDestroy(kv.second->ready);
   for (auto& kv : S->reqs) delete kv.second;
   if (S->pinned) (void)hipHostFree(S->pinned);
   delete S;

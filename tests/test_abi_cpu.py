@@ -224,3 +224,24 @@ def test_pcg_workspace_and_validation():
     g3 = pg.cart_grid(64, ghost=3)
     assert lib.poisson_workspace_bytes(C.byref(g3), C.byref(pg.options("pcg", order=6))) > 0
     assert lib.poisson_workspace_bytes(C.byref(pg.sph_grid(16, 8, 16)), C.byref(pg.options("pcg"))) == 0
+
+
+def test_server_and_capture_stream_validation_before_any_device_call():
+    """The serving loop takes the caller's arena and streams: a missing arena,
+    a misaligned one or a NULL slot stream is refused on the host, and so is
+    a NULL capture stream; a wait that runs out of time has its own status."""
+    lib = L.load()
+    h = C.c_void_p()
+    streams = (C.c_void_p * 2)(C.c_void_p(0x1000), C.c_void_p(0x2000))
+    assert lib.poisson_server_create(C.byref(h), None, 1 << 20, 2, streams, 1, 8, 2, 1e-8, 1, 1) == L.EINVAL
+    assert lib.poisson_server_create(C.byref(h), C.c_void_p(0x10080), 1 << 20, 2, streams, 1, 8, 2, 1e-8, 1,
+                                     1) == L.EWORKSPACE
+    nulls = (C.c_void_p * 2)(C.c_void_p(0x1000), None)
+    assert lib.poisson_server_create(C.byref(h), C.c_void_p(0x10000), 1 << 20, 2, nulls, 1, 8, 2, 1e-8, 1,
+                                     1) == L.EINVAL
+    assert b"NULL stream" in lib.poisson_last_error()
+    assert lib.poisson_server_create(C.byref(h), C.c_void_p(0x10000), 1 << 20, 17, streams, 1, 8, 2, 1e-8, 1,
+                                     1) == L.EINVAL
+    assert lib.poisson_plan_set_capture_stream(None, C.c_void_p(0x1000)) == L.EINVAL
+    assert lib.poisson_strerror(L.ETIMEOUT) != lib.poisson_strerror(L.WARN_MAXITER)
+    assert b"timed out" in lib.poisson_strerror(L.ETIMEOUT)
