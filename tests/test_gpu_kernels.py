@@ -23,7 +23,7 @@ def _plan(n, order=2, method="cg", **kw):
     return pg.Plan(pg.cart_grid(n, ghost=g), pg.options(method, order=order, lmax=-1, **kw)), g
 
 
-@pytest.mark.parametrize("n,order", [(16, 2), (21, 2), (70, 2), (16, 6), (23, 6)])
+@pytest.mark.parametrize("n,order", [(16, 2), (21, 2), (70, 2), (16, 6), (23, 6), (131, 6)])
 def test_apply(n, order):
     say(f"apply n={n} order={order}")
     plan, g = _plan(n, order)
@@ -37,8 +37,11 @@ def test_apply(n, order):
     assert rel_max(host(out)[s, s, s], ref) < KTOL
 
 
-@pytest.mark.parametrize("n,order", [(33, 2), (24, 6)])
+@pytest.mark.parametrize("n,order", [(33, 2), (24, 6), (128, 6), (131, 6), (130, 2)])
 def test_residual_and_norm(n, order):
+    """n >= 128 takes the large-level launch shapes (eight planes per thread,
+    the 19-point residual's register window); 131 and 130 end in partial
+    tiles and partial plane runs."""
     say(f"residual n={n} order={order}")
     plan, g = _plan(n, order)
     phi, rho = random_cart(n, g, 3)
@@ -66,8 +69,9 @@ def test_red_black_sweep(n, omega, forward):
     assert rel_max(host(t), ref) < KTOL
 
 
-@pytest.mark.parametrize("n,forward", [(16, True), (19, False), (40, True)])
+@pytest.mark.parametrize("n,forward", [(16, True), (19, False), (40, True), (128, True), (131, False)])
 def test_four_colour_sweep(n, forward):
+    """n >= 128: eight planes per thread, as on the large multigrid levels."""
     say(f"4-colour sweep n={n} forward={forward}")
     plan, g = _plan(n, 6)
     phi, rho = random_cart(n, g, 11)
@@ -92,11 +96,13 @@ def test_restrict_and_prolong(n):
     assert rel_max(host(tf), fine + OS.prolong(ec)) < KTOL
 
 
-@pytest.mark.parametrize("order,n", [(2, 32), (2, 64), (2, 96), (2, 128), (2, 256), (6, 32)])
+@pytest.mark.parametrize("order,n", [(2, 32), (2, 64), (2, 96), (2, 128), (2, 256), (6, 32), (6, 128),
+                                     (6, 256)])
 def test_one_vcycle_matches_reference_cycle(order, n):
     """One V(2,2) cycle against the oracle's cycle; n = 96 has ragged tiles,
     n = 128 and 256 take the large-level shapes of the fused residual and
-    restriction."""
+    restriction (7-point) and of the four-colour passes and residual
+    (19-point star, Section 2.1.2)."""
     say(f"one V(2,2) cycle order={order} n={n}")
     g = 1 if order == 2 else 3
     coarsest = 6 if n == 96 else 8

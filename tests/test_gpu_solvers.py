@@ -154,11 +154,12 @@ def _c2_full():
     return rho, _oracle_cart(rho, 256, 1, 2, 8)
 
 
-@pytest.mark.parametrize("method", ["mg", "cg", "pcg"])
+@pytest.mark.parametrize("method", ["mg", "mg_ir32", "cg", "pcg"])
 def test_c2_full_size_multigrid(method):
     """255^3 unknowns in the benchmarks' launch configurations (the C2
-    multigrid; CG and PCG as in the 255^3 preconditioning study): converged
-    solution against the DST oracle."""
+    multigrid in FP64 and as FP32 cycles inside FP64 refinement; CG and PCG as
+    in the 255^3 preconditioning study): converged solution against the DST
+    oracle."""
     say(f"C2 full size 256^3 FP64 {method}")
     n = 256
     rho, ref = _c2_full()
@@ -167,6 +168,37 @@ def test_c2_full_size_multigrid(method):
     assert res.converged, res
     s = slice(1, n)
     assert rel_l2(phi[s, s, s], ref[s, s, s]) < CONV_TOL
+
+
+@functools.lru_cache(maxsize=1)
+def _c3_256():
+    """The 512^3 workload's recipe (64 clumps + turbulent floor, three ghost
+    layers) at 256 intervals, its oracle ghost values (lmax 8) and the
+    oracle's exact 19-point solution (about a minute of CPU)."""
+    n, g = 256, 3
+    rho = W.config_c3(n=n).rho.numpy()
+    ghost, _ = OM.cart_boundary(rho, n, g, 8)
+    return rho, ghost, OD.solve_cart(ghost, rho, n, 1.0 / n, 6, g)
+
+
+@pytest.mark.parametrize("method", ["mg", "mg_ir32"])
+def test_c3_star19_full_size_paths(method):
+    """19-point star (sixth order, four colours, Section 2.1.2) at 256
+    intervals with three ghost layers: the large-level shapes of the
+    four-colour pass and the residual on the two finest levels.  FP64
+    multigrid and FP32 cycles inside FP64 refinement, both driven to 1e-12,
+    against the oracle's exact solution on the oracle's own multipole ghosts:
+    <= 1e-10 relative L2 on the unknowns, every ghost node within 1e-12."""
+    say(f"C3 recipe 256^3 19-point {method}")
+    n, g = 256, 3
+    rho, ghost, ref = _c3_256()
+    phi, res = _solve(n, g, method, 6, rho, 8, 1e-12)
+    say(f"  {res.iterations} iterations, rel residual {res.rel_residual:.2e}")
+    assert res.converged, res
+    s = slice(g, g + n - 1)
+    assert rel_l2(phi[s, s, s], ref[s, s, s]) < CONV_TOL
+    mask = OM.cart_ghost_mask(n, g)
+    assert np.max(np.abs(phi[mask] - ghost[mask])) <= 1e-12 * np.max(np.abs(ghost[mask]))
 
 
 def test_warm_start_and_determinism():
