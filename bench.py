@@ -1,18 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the self-gravity Poisson hot path on one MI355X.
 
-Workload (default): 256^3 intervals on the unit box (255^3 unknowns), density
-of 16 seeded Gaussian clumps (centres U[0.2,0.8]^3, widths U[0.02,0.08],
-masses lognormal(0, 0.5)), open boundary from the multipole expansion with
-lmax = 8, FP64 geometric multigrid V(2,2) with red-black Gauss-Seidel,
-full-weighting restriction, trilinear prolongation and an exact 7^3 coarsest
-solve.  One step = one whole poisson_solve from a cold start (phi = 0):
-multipole boundary + V-cycles until the relative residual is <= 1e-8.
+Default line (the largest single-GPU workload): 512^3 intervals on the unit
+box (511^3 unknowns), density of 64 seeded Gaussian clumps plus a 5%
+lognormal |k|^-2 turbulent floor, 19-point sixth-order star with three ghost
+layers, open boundary from the multipole expansion with lmax = 8, all-FP64
+geometric multigrid V(2,2) with four-colour Gauss-Seidel, full weighting,
+trilinear prolongation and an exact 7^3 coarsest solve.  One step = one whole
+poisson_solve from a cold start (phi = 0): multipole boundary + V-cycles until
+the relative residual is <= 1e-8.  value = unknowns x V-cycles / wall time per
+step (Gcell-updates/s of the whole job, multipole included).
 
-Printed: one JSON line.  value = unknowns x V-cycles / wall time per step
-(Gcell-updates/s of the whole job, multipole included).  The roofline entry
-times the dominant kernel (the fine-level red-black colour pass) with HIP
-events on the plan's stream in its solver launch configuration.
+Beside it on the same line: the FP32 multigrid inside FP64 iterative
+refinement on the same input (time and speedup), the event-timed 7-point FP64
+colour pass at 511^3, the 255^3 clump workload (FP64 and mixed) and the
+19-point workload at 255^3 with their errors against the CPU oracle's exact
+discrete solution, a short serving leg (p50 / p99 latency and solves/s), and
+the oracle timed on the host cores.  The roofline entry times the dominant
+kernel (the fine-level four-colour pass) with HIP events on the plan's stream
+in its solver launch configuration.
 """
 from __future__ import annotations
 
@@ -38,7 +44,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--n", type=int, default=0, help="intervals per axis (default: 512 for c3, 256 for c2)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=12.0,
                     help="seconds of oracle V-cycles for the CPU baseline (at least one cycle)")
@@ -50,9 +56,13 @@ def parse():
                          "--sweeps resident smoother sweeps and one 1 GiB reference copy; "
                          "prints no bench line")
     ap.add_argument("--sweeps", type=int, default=10)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "serving", "spai"],
-                    help="c2: the 255^3 FP64 multigrid solve (default bench line); serving: the "
-                         "continuous-batching request stream (its own JSON line)")
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "serving", "spai"],
+                    help="c3: the 511^3 19-point FP64 multigrid solve (default bench line); c2: the 255^3 "
+                         "7-point one; serving: the continuous-batching request stream (its own JSON line)")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="requests of the serving leg on the default line")
+    ap.add_argument("--no-oracle-errors", action="store_true",
+                    help="skip the oracle's exact solves (errors of the 255^3 solves)")
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--load", type=float, default=0.7, help="offered load relative to saturation")
@@ -147,61 +157,318 @@ def bench_c1(args):
     print(json.dumps(out), flush=True)
 
 
-def c3(args):
-    """512^3 intervals (511^3 unknowns), 19-point 6th-order star, 64 Gaussian
-    clumps + 5% lognormal |k|^-2 floor, lmax 8: FP32 four-colour V(2,2) cycles
-    inside FP64 iterative refinement against the all-FP64 19-point multigrid."""
+def progress(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def host_description() -> dict:
+    """Host cores and CPU model of the machine the oracle runs on."""
+    model = None
+    try:
+        import subprocess
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.lower().startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except Exception:
+        model = None
+    if model is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.lower().startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return {"os_cpu_count": os.cpu_count(), "usable_cpus": affinity, "cpu_model": model}
+
+
+def _timed_solves(plan, rho, phi, tol, steps, warmup):
+    """warmup untimed cold-start solves, then `steps` timed ones bracketed by
+    device synchronisation; per-solve wall latencies (each solve ends with the
+    library's own convergence read-back, so they add up to the total)."""
+    import torch
+    res = None
+    for _ in range(warmup):
+        phi.zero_()
+        res = plan.solve(rho, phi, tol=tol)
+    torch.cuda.synchronize()
+    lats, its, tmp, tit = [], [], [], []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t1 = time.perf_counter()
+        phi.zero_()
+        res = plan.solve(rho, phi, tol=tol)
+        torch.cuda.synchronize()
+        lats.append(time.perf_counter() - t1)
+        if not res.converged:
+            raise RuntimeError(f"solve did not converge: {res}")
+        its.append(res.iterations)
+        tmp.append(res.t_multipole_ms)
+        tit.append(res.t_iter_ms)
+    sec = (time.perf_counter() - t0) / steps
+    return sec, res, {"lat_ms": [x * 1e3 for x in lats], "iterations": its, "t_multipole_ms": tmp,
+                      "t_iter_ms": tit}
+
+
+def _pass_ms(plan, passes_per_sweep: int, sweeps: int = 20) -> float:
+    """Average duration of one fine-level colour pass, HIP events on the
+    plan's stream around `sweeps` resident sweeps."""
+    import torch
+
+    import paper_2605_03563_amd as pg
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pg.sweep_resident(plan, 2)
+    ev0.record(plan.stream)
+    pg.sweep_resident(plan, sweeps)
+    ev1.record(plan.stream)
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / (passes_per_sweep * sweeps)
+
+
+def _rel_l2(a, b) -> float:
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _oracle_errors(label, n, g, order, rho_dev, runs):
+    """Errors of GPU solves against the oracle's exact discrete solution of
+    the same input (its own multipole ghosts, FP64 on the host).  runs:
+    {name: phi tensor}; returns {name: rel L2 error over the unknowns}."""
+    from oracle import direct as OD
+    from oracle import multipole as OM
+    progress(f"{label}: oracle multipole boundary and exact solve at {n - 1}^3")
+    t0 = time.perf_counter()
+    rho = rho_dev.cpu().numpy()
+    ghost, _ = OM.cart_boundary(rho, n, g, 8)
+    exact = OD.solve_cart(ghost, rho, n, 1.0 / n, order, g)
+    s = slice(g, g + n - 1)
+    ref = exact[s, s, s]
+    out = {name: _rel_l2(phi.cpu().numpy()[s, s, s], ref) for name, phi in runs.items()}
+    out["oracle_seconds"] = time.perf_counter() - t0
+    return out
+
+
+def _accuracy_leg(label, n, g, order, rho, oracle, tol):
+    """FP64 and mixed multigrid on one input, stopped at tol and driven to
+    1e-12, each compared with the oracle."""
+    import torch
+
+    import paper_2605_03563_amd as pg
+    grid = pg.cart_grid(n, ghost=g)
+    runs, info = {}, {}
+    for method in ("mg", "mg_ir32"):
+        plan = pg.Plan(grid, pg.options(method, order=order, lmax=8), device="cuda:0")
+        for t in (tol, 1e-12):
+            phi = torch.zeros_like(rho)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = plan.solve(rho, phi, tol=t)
+            torch.cuda.synchronize()
+            key = f"{method}_tol{t:g}"
+            runs[key] = phi
+            info[key] = {"iterations": r.iterations, "rel_residual": r.rel_residual, "converged": r.converged,
+                         "ms": (time.perf_counter() - t0) * 1e3}
+        del plan
+    if oracle:
+        errs = _oracle_errors(label, n, g, order, rho, runs)
+        for k in runs:
+            info[k]["err_vs_oracle_rel_l2"] = errs[k]
+        info["oracle_seconds"] = errs["oracle_seconds"]
+    return info
+
+
+def _serving_leg(n_requests: int):
+    """A short request stream (sizes 32^3..256^3, warm starts): saturation
+    throughput of the full server and of the FIFO FP64 cold-start baseline,
+    then both at 0.7x the baseline's own saturation, where it can keep up,
+    with p50 / p99 latency from arrival to completion."""
+    import torch
+
+    import paper_2605_03563_amd as pg
+    import workloads as W
+    dev = "cuda:0"
+    reqs = W.serving_stream(n_requests=n_requests, rate=1.0, seed=5)
+    rhos = [r.density(dev) for r in reqs]
+    torch.cuda.synchronize()
+    budget = 64 << 30
+
+    def run(cfg, rate):
+        phis = [torch.zeros_like(x) for x in rhos]
+        srv = pg.Server(budget, **cfg)
+        seen = {}
+        for r, x in zip(reqs, rhos):
+            if r.n not in seen:
+                seen[r.n] = (x, torch.zeros_like(x))
+        for i, (n, (x, y)) in enumerate(seen.items()):
+            st = srv.wait(srv.submit(-1 - i, n, x, y))
+            if st != 0:
+                raise RuntimeError(f"warm-up request failed with status {st}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets = []
+        for r, x, y in zip(reqs, rhos, phis):
+            if rate is not None:
+                target = t0 + r.arrival / rate
+                while True:
+                    dt = target - time.perf_counter()
+                    if dt <= 0:
+                        break
+                    time.sleep(min(dt, 0.0005) if dt > 0.0002 else 0)
+            tickets.append(srv.submit(r.stream_id, r.n, x, y))
+        stats = []
+        for t in tickets:
+            st = srv.wait(t, 600000.0)
+            if st != 0:
+                raise RuntimeError(f"request failed with status {st}")
+            stats.append(srv.poll(t))
+        wall = time.perf_counter() - t0
+        srv.close()
+        lat = [l for _, l in stats]
+        return {"solves_per_s": len(reqs) / wall, "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
+                "mean_steps": statistics.mean(s.iterations for s, _ in stats)}
+
+    full = dict(max_slots=8, mixed=True, warm_start=True, use_graphs=True)
+    fifo = dict(max_slots=1, mixed=False, warm_start=False, use_graphs=False)
+    sat_full = run(full, None)
+    sat_fifo = run(fifo, None)
+    rate = 0.7 * sat_fifo["solves_per_s"]
+    at_full = run(full, rate)
+    at_fifo = run(fifo, rate)
+    return {"requests": n_requests, "sizes": "32^3-256^3 (weights 0.4/0.3/0.2/0.1)",
+            "offered_rate_per_s": rate, "offered_load": "0.7x the FIFO FP64 baseline's saturation",
+            "full": at_full, "fifo_fp64_cold": at_fifo,
+            "speedup_p50_vs_fifo_fp64": at_fifo["p50_ms"] / at_full["p50_ms"],
+            "speedup_p99_vs_fifo_fp64": at_fifo["p99_ms"] / at_full["p99_ms"],
+            "saturation_solves_per_s": {"full": sat_full["solves_per_s"], "fifo_fp64_cold": sat_fifo["solves_per_s"]}}
+
+
+def bench_c3(args):
+    """Default line: 512^3 intervals (511^3 unknowns), 19-point 6th-order star,
+    64 Gaussian clumps + 5% lognormal |k|^-2 floor, lmax 8: all-FP64 four-colour
+    multigrid V(2,2) to 1e-8 from a cold start, beside the FP32 multigrid in
+    FP64 iterative refinement on the same input."""
     import torch
 
     import paper_2605_03563_amd as pg
     import workloads as W
 
     dev = "cuda:0"
-    n = 512
+    n = args.n or 512
+    unknowns = (n - 1) ** 3
+    progress(f"c3 density at {n}^3 intervals")
     wl = W.config_c3(n=n, device=dev)
     rho = wl.rho.contiguous()
     del wl
-    unknowns = (n - 1) ** 3
     grid = pg.cart_grid(n, ghost=3)
-    p32 = pg.Plan(grid, pg.options("mg_ir32", order=6, lmax=8), device=dev)
-    phi32 = torch.zeros_like(rho)
-    sec32, r32 = _time_solves(p32, rho, phi32, args.tol, args.steps, args.warmup)
-    # dominant kernel: the fine-level FP32 four-colour pass
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    pg.sweep_resident(p32, 1)
-    ev0.record(p32.stream)
-    pg.sweep_resident(p32, 5)
-    ev1.record(p32.stream)
-    torch.cuda.synchronize()
-    pass_ms = ev0.elapsed_time(ev1) / 20
-    bytes_per_pass = 5.0 * unknowns   # FP32: 3 other colours + f_c read, colour c written
-    achieved = bytes_per_pass / (pass_ms * 1e-3) / 1e9
-    del p32
+
+    progress("FP64 19-point multigrid")
     p64 = pg.Plan(grid, pg.options("mg", order=6, lmax=8), device=dev)
-    phi64 = torch.zeros_like(rho)
-    sec64, r64 = _time_solves(p64, rho, phi64, args.tol, max(1, args.steps // 2), 1)
-    # reference: FP64 multigrid driven to round-off
-    ref = torch.zeros_like(rho)
-    rref = p64.solve(rho, ref, tol=1e-12)
-    s = slice(3, 3 + n - 1)
-    err32 = float(torch.linalg.vector_norm(phi32[s, s, s] - ref[s, s, s]) / torch.linalg.vector_norm(ref[s, s, s]))
-    err64 = float(torch.linalg.vector_norm(phi64[s, s, s] - ref[s, s, s]) / torch.linalg.vector_norm(ref[s, s, s]))
+    phi = torch.zeros_like(rho)
+    sec, r64, rec = _timed_solves(p64, rho, phi, args.tol, args.steps, args.warmup)
+    cycles = statistics.mean(rec["iterations"])
+    value = unknowns * cycles / sec / 1e9
+    pass_ms = _pass_ms(p64, 4)
+    bytes_per_pass = 10.0 * unknowns   # FP64: three other colours and f_c read, colour c written
+    achieved = bytes_per_pass / (pass_ms * 1e-3) / 1e9
+    traffic = traffic_from_profiles("pass19w_f64_c3_511")
+    del p64
+
+    mixed = None
+    if not args.no_mixed:
+        progress("FP32 19-point multigrid in FP64 refinement")
+        p32 = pg.Plan(grid, pg.options("mg_ir32", order=6, lmax=8), device=dev)
+        sec32, r32, rec32 = _timed_solves(p32, rho, phi, args.tol, args.steps, args.warmup)
+        pass32_ms = _pass_ms(p32, 4)
+        mixed = {"time_to_1e-8_ms": sec32 * 1e3, "refinement_steps": statistics.mean(rec32["iterations"]),
+                 "speedup_vs_fp64_mg": sec / sec32, "rel_residual": r32.rel_residual,
+                 "p50_ms": _pct(rec32["lat_ms"], 50), "p99_ms": _pct(rec32["lat_ms"], 99),
+                 "fine_pass_fp32_ms": pass32_ms,
+                 "fine_pass_fp32_GBps": 5.0 * unknowns / (pass32_ms * 1e-3) / 1e9}
+        del p32
+    del phi, rho
+
+    progress("7-point FP64 colour pass at 511^3")
+    w7 = W.config_c2(n=512, device=dev)
+    rho7 = w7.rho.contiguous()
+    del w7
+    p7 = pg.Plan(pg.cart_grid(512), pg.options("mg", lmax=8), device=dev)
+    phi7 = torch.zeros_like(rho7)
+    r7 = p7.solve(rho7, phi7, tol=args.tol)
+    pass7_ms = _pass_ms(p7, 2)
+    pass7 = {"pass_ms": pass7_ms, "algorithmic_bytes_per_launch": 12.0 * unknowns,
+             "GBps": 12.0 * unknowns / (pass7_ms * 1e-3) / 1e9,
+             "frac": 12.0 * unknowns / (pass7_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+             "gcell_updates_per_s": unknowns / (2 * pass7_ms * 1e-3) / 1e9,
+             "traffic": traffic_from_profiles("rb_pass7_f64_c2_511"),
+             "kernel": "k_pass7<double> (fine-level red-black GS colour pass)",
+             "solve": {"v_cycles": r7.iterations, "ms": r7.t_multipole_ms + r7.t_iter_ms}}
+    del p7, phi7, rho7
+
+    # plain copy bandwidth on the same device for context
+    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(10):
+        b.copy_(a)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 2 * a.numel() * 4 * 10 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del a, b
+
+    oracle = not args.no_oracle_errors
+    progress("255^3 clump workload (7-point), FP64 and mixed, against the oracle")
+    w2 = W.config_c2(n=256, device=dev)
+    acc_c2 = _accuracy_leg("c2", 256, 1, 2, w2.rho.contiguous(), oracle, args.tol)
+    del w2
+    progress("19-point workload at 255^3, FP64 and mixed, against the oracle")
+    w3 = W.config_c3(n=256, device=dev)
+    acc_c3 = _accuracy_leg("c3@256", 256, 3, 6, w3.rho.contiguous(), oracle, args.tol)
+    del w3
+
+    serving = None
+    if args.serve_requests > 0:
+        progress(f"serving leg, {args.serve_requests} requests")
+        serving = _serving_leg(args.serve_requests)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        progress("CPU oracle baseline")
+        cpu = cpu_baseline_c3(args.cpu_budget_s)
+
     out = {
-        "metric": "Gcell-updates/s", "value": unknowns * r32.iterations / sec32 / 1e9, "unit": "Gcell-updates/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec32 * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": "c3_clumps64_floor_512^3_star19_fp32mg_in_fp64ir_lmax8", "unknowns": unknowns},
-        "time_to_1e-8_ms": sec32 * 1e3, "refinement_steps": r32.iterations,
-        "fp64_mg_time_to_1e-8_ms": sec64 * 1e3, "fp64_mg_cycles": r64.iterations,
-        "speedup_mixed_vs_fp64": sec64 / sec32,
-        "err_vs_converged_fp64_mixed": err32, "err_vs_converged_fp64_fp64mg": err64,
-        "converged_reference_rel_residual": rref.rel_residual,
-        "t_multipole_ms": r32.t_multipole_ms,
-        "cpu_baseline": None if args.no_cpu_baseline else cpu_baseline_c3(args.cpu_budget_s),
+        "metric": "Gcell-updates/s", "value": value, "unit": "Gcell-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"c3_clumps64_floor_{n}^3_star19_fp64_mg_v22_4colour_gs_lmax8_tol{args.tol:g}",
+                   "unknowns": unknowns, "solver": "MG V(2,2) four-colour GS on the 19-point star, FW "
+                   "restriction, trilinear prolongation, 7^3 exact coarsest", "parallelism": "single-gpu"},
+        "time_to_1e-8_ms": sec * 1e3,
+        "time_to_1e-8_p50_ms": _pct(rec["lat_ms"], 50), "time_to_1e-8_p99_ms": _pct(rec["lat_ms"], 99),
+        "time_to_1e-8_median_device_ms": statistics.median(a + b for a, b in zip(rec["t_multipole_ms"],
+                                                                                 rec["t_iter_ms"])),
+        "v_cycles": cycles, "rate": r64.rate, "rel_residual": r64.rel_residual,
+        "t_multipole_ms": statistics.mean(rec["t_multipole_ms"]), "t_iter_ms": statistics.mean(rec["t_iter_ms"]),
+        "s_s_gzups": unknowns / (statistics.mean(rec["t_iter_ms"]) / cycles * 1e-3) / 1e9,
+        "s_t_gzups": unknowns / sec / 1e9,
+        "fine_pass_ms": pass_ms,
+        "fine_pass_gcell_updates_per_s": unknowns / (4 * pass_ms * 1e-3) / 1e9,
+        "copy_GBps": copy_gbps,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
-                     "kernel": "k_pass19w<float> (fine-level four-colour GS pass)",
-                     "algorithmic_bytes_per_launch": bytes_per_pass, "pass_ms": pass_ms},
+                     "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
+                     "kernel": "k_pass19w<double> (fine-level four-colour GS pass)",
+                     "algorithmic_bytes_per_launch": bytes_per_pass},
+        "mixed_fp32_mg_in_fp64_ir": mixed,
+        "rb_pass7_f64_511": pass7,
+        "accuracy_vs_oracle_255": {"c2_clumps16_7pt": acc_c2, "c3_recipe_19pt": acc_c3},
+        "serving": serving,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
 
@@ -422,7 +689,7 @@ def serving(args):
         stats = []
         for t in tickets:
             st = srv.wait(t, 600000.0)
-            if st not in (0, 1):
+            if st != 0:
                 raise RuntimeError(f"request failed with status {st}")
             stats.append(srv.poll(t))
         wall = time.perf_counter() - t0
@@ -463,7 +730,10 @@ def serving(args):
 
 def kernels_only(args):
     """Dispatch the dominant kernel and a copy kernel of known size so that
-    rocprofv3 counters (FETCH_SIZE, WRITE_SIZE) can be read per dispatch."""
+    rocprofv3 counters (FETCH_SIZE, WRITE_SIZE) can be read per dispatch:
+    c3: the FP64 four-colour pass at 511^3 (19-point star); c2: the FP64
+    red-black pass (7-point, --n intervals, default 512); spai: the fused SPAI
+    step at 511^3."""
     import torch
 
     import paper_2605_03563_amd as pg
@@ -476,10 +746,20 @@ def kernels_only(args):
         rho = wl.rho.contiguous()
         plan = pg.Plan(pg.cart_grid(512), pg.options("mg_spai", order=2, lmax=8, nu1=1, nu2=1, coarsest=4,
                                                       max_iter=1), device=dev)
-    else:
-        wl = W.config_c2(n=args.n, device=dev)
+        what = "fused SPAI steps"
+    elif args.workload == "c3":
+        n = args.n or 512
+        wl = W.config_c3(n=n, device=dev)
         rho = wl.rho.contiguous()
-        plan = pg.Plan(pg.cart_grid(args.n), pg.options("mg", lmax=8), device=dev)
+        plan = pg.Plan(pg.cart_grid(n, ghost=3), pg.options("mg", order=6, lmax=8, max_iter=1), device=dev)
+        what = "four-colour sweeps"
+    else:
+        n = args.n or 512
+        wl = W.config_c2(n=n, device=dev)
+        rho = wl.rho.contiguous()
+        plan = pg.Plan(pg.cart_grid(n), pg.options("mg", lmax=8, max_iter=1), device=dev)
+        what = "red-black sweeps"
+    del wl
     phi = torch.zeros_like(rho)
     plan.solve(rho, phi, tol=args.tol)
     pg.sweep_resident(plan, args.sweeps)
@@ -487,8 +767,7 @@ def kernels_only(args):
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
-    print(f"kernels-only: {args.sweeps} sweeps = {2 * args.sweeps} colour passes, "
-          f"copy of {a.numel() * 8} bytes", flush=True)
+    print(f"kernels-only ({args.workload}): {args.sweeps} {what}, copy of {a.numel() * 8} bytes", flush=True)
 
 
 def traffic_from_profiles(kernel_tag: str):
@@ -538,7 +817,7 @@ def cpu_baseline(rho_host, n, budget_s, with_multipole):
     if t_mp is not None:
         sample += f"; oracle multipole boundary (lmax 8) took {t_mp:.1f} s (not in value)"
     return {"value": unknowns * cycles / el / 1e9, "unit": "Gcell-updates/s", "cores": 1,
-            "kind": "oracle", "sample": sample}
+            "kind": "oracle", "sample": sample, "host": host_description()}
 
 
 def _cpu_repeat(fn, budget_s):
@@ -570,7 +849,7 @@ def cpu_baseline_c3(budget_s):
     calls, el = _cpu_repeat(lambda: OS.vcycle(u, rho, n, 1.0 / n, 6, g, _cache=cache), budget_s)
     return {"value": (n - 1) ** 3 * calls / el / 1e9, "unit": "Gcell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{calls} oracle 19-point V(2,2) cycle(s) (FP64 NumPy) on the same recipe at 128^3 "
-                      f"(127^3 unknowns), single thread, {el:.1f} s"}
+                      f"(127^3 unknowns), single thread, {el:.1f} s", "host": host_description()}
 
 
 def cpu_baseline_c4(rho_host, g, budget_s):
@@ -584,7 +863,7 @@ def cpu_baseline_c4(rho_host, g, budget_s):
     return {"value": g.unknowns * calls / el / 1e9, "unit": "Gcell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{calls} oracle residual evaluation(s) of the r^2-scaled spherical operator on the full "
                       f"{g.nr}x{g.nth}x{g.nph} input, single thread, {el:.1f} s (the oracle solves C4 directly; "
-                      f"this is its per-sweep building block)"}
+                      f"this is its per-sweep building block)", "host": host_description()}
 
 
 def cpu_baseline_spai(budget_s):
@@ -602,7 +881,7 @@ def cpu_baseline_spai(budget_s):
     calls, el = _cpu_repeat(lambda: SP.vcycle(u, f, n, ops, SP.COEFFS[2], 3, 3, _cache=cache), budget_s)
     return {"value": (n - 1) ** 3 * calls / el / 1e9, "unit": "Gcell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"{calls} oracle SPAI V(3,3) cycle(s) (order 2, Galerkin coarse levels to 4 intervals) on "
-                      f"the same recipe at 128^3, single thread, {el:.1f} s"}
+                      f"the same recipe at 128^3, single thread, {el:.1f} s", "host": host_description()}
 
 
 def main():
@@ -617,16 +896,21 @@ def main():
         kernels_only(args)
         return
     if args.workload != "c2":
-        {"serving": serving, "c1": bench_c1, "c3": c3, "c4": c4, "spai": spai}[args.workload](args)
+        {"serving": serving, "c1": bench_c1, "c3": bench_c3, "c4": c4, "spai": spai}[args.workload](args)
         return
+    bench_c2(args)
 
+
+def bench_c2(args):
+    """256^3 intervals (255^3 unknowns), 16 Gaussian clumps, 7-point operator,
+    lmax 8: FP64 multigrid V(2,2) with red-black Gauss-Seidel to 1e-8."""
     import torch
 
     import paper_2605_03563_amd as pg
     import workloads as W
 
     dev = "cuda:0"
-    n = args.n
+    n = args.n or 256
     unknowns = (n - 1) ** 3
     wl = W.config_c2(n=n, device=dev)
     rho = wl.rho.contiguous()
