@@ -347,6 +347,32 @@ def _serving_leg(n_requests: int):
             "saturation_solves_per_s": {"full": sat_full["solves_per_s"], "fifo_fp64_cold": sat_fifo["solves_per_s"]}}
 
 
+def hbm_ceiling(gib: float = 2.0, reps: int = 10) -> dict:
+    """Plain streams on the same device, on arrays of `gib` GiB each (beyond
+    the 256 MB Infinity Cache): a read-only sum, a copy and a triad
+    c = a + s b (two reads, one write: a colour pass's stream mix), timed
+    with events; torch's own kernels, for context beside the roofline."""
+    import torch
+    n = int(gib * (1 << 30)) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.ones_like(a)
+    c = torch.empty_like(a)
+    out = {"array_GiB": gib}
+    for name, fn, nbytes in (("read_GBps", lambda: a.sum(), 8 * n),
+                             ("copy_GBps", lambda: c.copy_(a), 16 * n),
+                             ("triad_GBps", lambda: torch.add(a, b, alpha=0.5, out=c), 24 * n)):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b, c
+    return out
+
+
 def bench_c3(args):
     """Default line: 512^3 intervals (511^3 unknowns), 19-point 6th-order star,
     64 Gaussian clumps + 5% lognormal |k|^-2 floor, lmax 8: all-FP64 four-colour
@@ -409,18 +435,7 @@ def bench_c3(args):
              "solve": {"v_cycles": r7.iterations, "ms": r7.t_multipole_ms + r7.t_iter_ms}}
     del p7, phi7, rho7
 
-    # plain copy bandwidth on the same device for context
-    a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-    b = torch.empty_like(a)
-    b.copy_(a)
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    c0.record()
-    for _ in range(10):
-        b.copy_(a)
-    c1.record()
-    torch.cuda.synchronize()
-    copy_gbps = 2 * a.numel() * 4 * 10 / (c0.elapsed_time(c1) * 1e-3) / 1e9
-    del a, b
+    ceiling = hbm_ceiling()
 
     oracle = not args.no_oracle_errors
     progress("255^3 clump workload (7-point), FP64 and mixed, against the oracle")
@@ -459,7 +474,8 @@ def bench_c3(args):
         "s_t_gzups": unknowns / sec / 1e9,
         "fine_pass_ms": pass_ms,
         "fine_pass_gcell_updates_per_s": unknowns / (4 * pass_ms * 1e-3) / 1e9,
-        "copy_GBps": copy_gbps,
+        "copy_GBps": ceiling["copy_GBps"],
+        "hbm_ceiling": ceiling,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
                      "kernel": "k_pass19w<double> (fine-level four-colour GS pass)",
