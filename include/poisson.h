@@ -204,6 +204,29 @@ int poisson_plan_set_capture_stream(poisson_plan_t plan, void* stream);
 int multipole_boundary(poisson_plan_t plan, const double* d_rho, double* d_phi, int32_t lmax,
                        double* h_q);
 
+/* Allocation-free multipole boundary, for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving loops,
+   harnesses that forbid hipMalloc): the Cartesian case of
+   multipole_boundary without a plan.  The moment sums, the monomial tables
+   and q_lm live in a fixed device array of POISSON_NOALLOC_SCRATCH_BYTES that
+   the library holds on each GPU it runs on until the process ends (enough for
+   n <= 512 at any lmax <= 8); nothing is allocated or freed per call, and the
+   first call on a device uploads the tables into that device's array with
+   hipMemcpy.  grid: Cartesian, ghost 1..3, pitches as for poisson_plan;
+   d_rho is read at the unknowns, every ghost node of d_phi is overwritten
+   (the unknowns are left untouched); four_pi_G > 0; point_mass is added to
+   q_00; h_q as for multipole_boundary (NULL to skip; synchronises).  Work is
+   queued on `stream` (a hipStream_t, NULL = default stream).  Every call on
+   one GPU shares that GPU's array, so calls that overlap on one GPU (other
+   threads or streams) race; calls queued on one stream are ordered.
+   POISSON_EINVAL for a spherical grid, bad arguments, or an n whose scratch
+   exceeds the array; POISSON_EHIP when the array's address cannot be
+   obtained. */
+#define POISSON_NOALLOC_SCRATCH_BYTES (80u * 1024u * 1024u)
+int multipole_boundary_noalloc(const poisson_grid_t* grid, const double* d_rho, double* d_phi,
+                               int32_t lmax, double four_pi_G, double point_mass, double* h_q,
+                               void* stream);
+
 /* Solve lap Phi = 4 pi G rho (Cartesian) or r^2 lap Phi = r^2 4 pi G rho
    (spherical, Eq. 2 in s = ln r) for the unknowns of d_phi.  On entry the
    unknowns are the initial guess (warm start, Section 2.1); with

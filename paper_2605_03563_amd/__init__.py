@@ -309,6 +309,23 @@ class Server:
             pass
 
 
+NOALLOC_SCRATCH_BYTES = 80 * 1024 * 1024
+
+
+def multipole_boundary_noalloc(grid, rho: torch.Tensor, phi: torch.Tensor, lmax: int, four_pi_G: float = 1.0,
+                               point_mass: float = 0.0, stream: Optional[torch.cuda.Stream] = None):
+    """Cartesian multipole boundary without a plan or any device allocation
+    (the library's fixed per-device scratch array); returns q_lm."""
+    lib = L.load()
+    p, r, _ = array_shape(grid)
+    ne = int(p * grid.pitch[1])
+    q = (C.c_double * ((lmax + 1) ** 2))()
+    st = stream if stream is not None else torch.cuda.current_stream(rho.device)
+    _check(lib.multipole_boundary_noalloc(C.byref(grid), _ptr(rho, ne), _ptr(phi, ne), lmax, four_pi_G, point_mass,
+                                          q, C.c_void_p(st.cuda_stream)), "multipole_boundary_noalloc")
+    return [q[i] for i in range(len(q))]
+
+
 def sweep_resident(plan: "Plan", sweeps: int):
     _check(plan.lib.poisson_op_sweep_resident(plan.handle, sweeps), "poisson_op_sweep_resident")
 

@@ -45,6 +45,8 @@ SIGNATURES = {
                                C.c_size_t, C.c_void_p]),
     "multipole_boundary": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                      C.POINTER(C.c_double)]),
+    "multipole_boundary_noalloc": (C.c_int, [C.POINTER(Grid), C.c_void_p, C.c_void_p, C.c_int32, C.c_double,
+                                             C.c_double, C.POINTER(C.c_double), C.c_void_p]),
     "poisson_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Grid), C.c_double,
                                 C.POINTER(Stats)]),
     "poisson_plan_set_capture_stream": (C.c_int, [C.c_void_p, C.c_void_p]),

@@ -245,3 +245,26 @@ def test_server_and_capture_stream_validation_before_any_device_call():
     assert lib.poisson_plan_set_capture_stream(None, C.c_void_p(0x1000)) == L.EINVAL
     assert lib.poisson_strerror(L.ETIMEOUT) != lib.poisson_strerror(L.WARN_MAXITER)
     assert b"timed out" in lib.poisson_strerror(L.ETIMEOUT)
+
+
+def test_noalloc_multipole_validation_before_any_device_call():
+    """The allocation-free multipole boundary rejects, on the host, grids its
+    fixed scratch array cannot hold and everything but Cartesian grids."""
+    lib = L.load()
+    fake = C.c_void_p(1 << 20)   # never dereferenced: validation fails first
+
+    def call(grid, lmax=8, four_pi_g=1.0, rho=fake):
+        return lib.multipole_boundary_noalloc(C.byref(grid), rho, fake, lmax, four_pi_g, 0.0, None, None)
+
+    assert call(pg.cart_grid(1024)) == L.EINVAL
+    assert b"scratch" in lib.poisson_last_error()
+    assert call(pg.sph_grid(16, 8, 8)) == L.EINVAL
+    assert call(pg.cart_grid(32), lmax=9) == L.EINVAL
+    assert call(pg.cart_grid(32), lmax=-1) == L.EINVAL
+    assert call(pg.cart_grid(32), four_pi_g=0.0) == L.EINVAL
+    assert call(pg.cart_grid(32), rho=None) == L.EINVAL
+    assert call(pg.cart_grid(32, pitch_x=20)) == L.EINVAL
+    g = pg.cart_grid(32)
+    g.ghost = 4
+    assert call(g) == L.EGRID
+    assert pg.NOALLOC_SCRATCH_BYTES == 80 * 1024 * 1024
