@@ -401,7 +401,7 @@ def bench_c3(args):
     pass_ms = _pass_ms(p64, 4)
     bytes_per_pass = 10.0 * unknowns   # FP64: three other colours and f_c read, colour c written
     achieved = bytes_per_pass / (pass_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles("pass19w_f64_c3_511")
+    traffic = traffic_from_profiles("pass19v_f64_c3_511")
     del p64
 
     mixed = None
@@ -478,7 +478,7 @@ def bench_c3(args):
         "hbm_ceiling": ceiling,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS, "traffic": traffic,
-                     "kernel": "k_pass19w<double> (fine-level four-colour GS pass)",
+                     "kernel": "k_pass19v<double, 2> (fine-level four-colour GS pass)",
                      "algorithmic_bytes_per_launch": bytes_per_pass},
         "mixed_fp32_mg_in_fp64_ir": mixed,
         "rb_pass7_f64_511": pass7,

@@ -160,8 +160,10 @@ bool resrestrict_ok(const Geom& Gf);
 // came last) and only the colour-0 ones are formed.
 void resrestrict(const void* phi, const void* f, bool f32, const Geom& Gf, void* f_coarse, const Geom& Gc,
                  hipStream_t st, bool r0only = false);
+// last_zero (four colours): the residuals of colour 3 vanish (a Gauss-Seidel
+// pass over it came last) and are not read
 void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom& Gc, bool f32,
-                 hipStream_t st);
+                 hipStream_t st, bool last_zero = false);
 // c0only: leave the last colour (1 of two, 3 of four) uncorrected, when a
 // Gauss-Seidel pass over that colour follows, which reads no value of its
 // own colour and overwrites them all.

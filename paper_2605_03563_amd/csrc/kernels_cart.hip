@@ -153,90 +153,130 @@ __global__ __launch_bounds__(256) void k_pass7(T* __restrict__ X, const T* __res
 
 // ---------------------------------------------------------------- 19-point star
 // Both kernels keep a register window along z: the values at the thread's own
-// compact column of rows b for planes k-3..k+3, so each plane costs one new
+// compact columns of row b for planes k-3..k+3, so each plane costs one new
 // load per colour.  The residual kernel stages the window's centre plane, three
 // halo rows above and below and one halo column on each side in an LDS tile
 // (64 x TBY threads march planes in lock step) and reads x- and y-neighbours
-// from it; the pass kernel takes x-neighbours from the adjacent lanes instead
-// and needs no barrier.  The node at position q of a compact column in a row
-// with colour shift s has colour (q + s) mod 4.
+// from it; the pass kernel takes x-neighbours from its own vector or the
+// adjacent lanes and needs no barrier.
 constexpr int TROWS = TBY + 6;
 static_assert(TBY >= 6, "the six halo rows of a plane tile are loaded by the first six thread rows");
 constexpr int TCOLS = BX + 2;
 
-// Four-colour pass without LDS or barriers: the register window along z
-// holds the three other colours at the thread's compact column for planes
-// k-3..k+3; x-neighbours in the adjacent compact columns come from the
-// neighbouring lanes of the wavefront (one wavefront = 64 consecutive columns
-// of one row), the wavefront's edge lanes load theirs; y-neighbours are loaded.
-template <typename T>
-__global__ __launch_bounds__(256) void k_pass19w(T* __restrict__ X, const T* __restrict__ F, Geom G, int c, T h2,
+// Four-colour pass without LDS or barriers.  A lane owns CPL consecutive
+// compact columns m0 .. m0+CPL-1 of one row (16-byte vector loads: two FP64
+// or four FP32 columns) and marches the planes of its run; lanes are numbered
+// over (column group, row) pairs of the level, so every lane of a wavefront
+// has work whatever the row length.  The register window along z holds the
+// three other colours at the lane's columns for planes k-3..k+3 (one new
+// vector load per colour and plane); x-neighbours in the adjacent compact
+// columns come from the lane's own vector or from the neighbouring lanes,
+// which hold the adjacent column group of the same row (lanes at a wavefront
+// or row edge load theirs); y-neighbours are loaded.  ZM: colours whose bit
+// is set in zmask are read as zero (the first sweep on a zero initial guess).
+// The node at position q of a compact column in a row with colour shift s has
+// colour (q + s) mod 4.
+template <typename T, int N> struct VecOf;
+template <> struct VecOf<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
+
+// column groups of CPL compact columns covering the columns 0 .. mhi (the
+// four-colour levels have mlo = 0); loads of a group stay below the row pitch
+// because W is a multiple of 32 and W >= mhi + 1
+template <int CPL>
+__host__ __device__ inline int col_groups(const Geom& G) { return (G.mhi() + CPL) / CPL; }
+
+template <typename T, int CPL, bool ZM>
+__global__ __launch_bounds__(256) void k_pass19v(T* __restrict__ X, const T* __restrict__ F, Geom G, int c, T h2,
                                                  int zmask) {
+  typedef typename VecOf<T, CPL>::type V;
   int bx, by, bz;
   xcd_block(bx, by, bz);
-  const int tx = threadIdx.x;
-  const int m = G.mlo() + bx * BX + tx;
-  const int b = G.g + by * BY + (int)threadIdx.y;
+  const int ngr = col_groups<CPL>(G);
+  const int E = G.n - 1;
+  const int lane = threadIdx.x & 63;
+  const int fi = bx * 256 + (int)threadIdx.x;
+  const bool live = fi < ngr * E;
+  const int fl = live ? fi : ngr * E - 1;  // idle lanes mirror the last pair (loads stay in the array)
+  const int gp = fl % ngr;
+  const int m0 = gp * CPL;
+  const int b = G.g + fl / ngr;
   const int last = G.g + G.n - 2;
   const int kz = planes_per_block(G);
   const int k0 = G.g + bz * kz;
   const int k1 = min(k0 + kz - 1, last);
-  const bool rowok = b <= last;
-  const bool colok = m < G.W;
+  const bool needl = (lane == 0 || gp == 0) && m0 >= 1;
+  const bool needr = (lane == 63 || gp == ngr - 1) && m0 + CPL < G.W;
   const T* P[3];
   bool zero[3];
 #pragma unroll
   for (int e = 0; e < 3; ++e) {
     const int col = (c + e + 1) & 3;
     P[e] = X + (long long)col * G.cs;
-    zero[e] = (zmask >> col) & 1;
+    zero[e] = ZM && ((zmask >> col) & 1);
   }
   const long long plane = (long long)G.M * G.W;
-  const long long cb = (long long)b * G.W + m;
-  const bool live = rowok && colok;
-  T win[7][3];
+  const long long cb = (long long)b * G.W + m0;
+  auto ldv = [&](int e, long long off) -> V {
+    if (ZM && zero[e]) return V{};
+    return *reinterpret_cast<const V*>(P[e] + off);
+  };
+  V win[7][3];
 #pragma unroll
   for (int d = -3; d <= 2; ++d)
 #pragma unroll
-    for (int e = 0; e < 3; ++e) win[d + 3][e] = (live && !zero[e]) ? P[e][(k0 + d) * plane + cb] : (T)0;
+    for (int e = 0; e < 3; ++e) win[d + 3][e] = ldv(e, (k0 + d) * plane + cb);
   T* __restrict__ Xc = X + (long long)c * G.cs;
   const T* __restrict__ Fc = F + (long long)c * G.cs;
   const T inv = (T)(1.0 / (3.0 * kC0));
   for (int k = k0; k <= k1; ++k) {
+    const long long row = k * plane + cb;
 #pragma unroll
-    for (int e = 0; e < 3; ++e) win[6][e] = (live && !zero[e]) ? P[e][(k + 3) * plane + cb] : (T)0;
-    // neighbouring compact columns from the adjacent lanes
+    for (int e = 0; e < 3; ++e) win[6][e] = ldv(e, row + 3 * plane);
+    // y-neighbours: colour c+d (slot d-1) at row b+d, colour c-d (slot 3-d) at row b-d
+    V yv[6];
+    yv[0] = ldv(0, row + G.W);
+    yv[1] = ldv(2, row - G.W);
+    yv[2] = ldv(1, row + 2 * (long long)G.W);
+    yv[3] = ldv(1, row - 2 * (long long)G.W);
+    yv[4] = ldv(2, row + 3 * (long long)G.W);
+    yv[5] = ldv(0, row - 3 * (long long)G.W);
+    const V fv = *reinterpret_cast<const V*>(Fc + row);
     T lft[3], rgt[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-      lft[e] = __shfl_up(win[3][e], 1, 64);
-      rgt[e] = __shfl_down(win[3][e], 1, 64);
+      lft[e] = __shfl_up(win[3][e][CPL - 1], 1, 64);
+      rgt[e] = __shfl_down(win[3][e][0], 1, 64);
+      if (needl) lft[e] = (ZM && zero[e]) ? (T)0 : P[e][row - 1];
+      if (needr) rgt[e] = (ZM && zero[e]) ? (T)0 : P[e][row + CPL];
     }
-    const long long row = k * plane + (long long)b * G.W;
-    if (tx == 0 && live && m >= 1) {
+    const int q = (c - b - k - G.off) & 3;  // position of the colour-c node in each compact column
+    T out[CPL];
+    bool ok[CPL];
+    bool all = live;
 #pragma unroll
-      for (int e = 0; e < 3; ++e) lft[e] = zero[e] ? (T)0 : P[e][row + m - 1];
+    for (int i = 0; i < CPL; ++i) {
+      const int a = 4 * (m0 + i) + q;
+      ok[i] = live && G.inner(a);
+      all = all && ok[i];
+      // slot e at compact column m0 + j (j = -1 .. CPL)
+      auto colv = [&](int j, int e) -> T { return j < 0 ? lft[e] : (j >= CPL ? rgt[e] : win[3][e][j]); };
+      auto xval = [&](int d, int e) -> T { return colv(((a + d) >> 2) - m0, e); };
+      const T s1 = xval(1, 0) + xval(-1, 2) + yv[0][i] + yv[1][i] + win[4][0][i] + win[2][2][i];
+      const T s2 = xval(2, 1) + xval(-2, 1) + yv[2][i] + yv[3][i] + win[5][1][i] + win[1][1][i];
+      const T s3 = xval(3, 2) + xval(-3, 0) + yv[4][i] + yv[5][i] + win[6][2][i] + win[0][0][i];
+      const T sum = (T)kC1 * s1 + (T)kC2 * s2 + (T)kC3 * s3;
+      out[i] = (h2 * fv[i] - sum) * inv;
     }
-    if (tx == BX - 1 && live && m + 1 < G.W) {
+    if (all) {
+      V o;
 #pragma unroll
-      for (int e = 0; e < 3; ++e) rgt[e] = zero[e] ? (T)0 : P[e][row + m + 1];
-    }
-    if (live && m <= G.mhi()) {
-      const int q = (c - b - k - G.off) & 3;  // position of the colour-c node in the column
-      const int a = 4 * m + q;
-      if (G.inner(a)) {
-        // colour c+d (e = d-1 for d = 1..3, colour c-d = c+4-d: e = 3-d) at compact (a+-d)>>2
-        auto xval = [&](int d, int e) -> T {
-          const int mm = (a + d) >> 2;
-          return mm < m ? lft[e] : (mm > m ? rgt[e] : win[3][e]);
-        };
-        auto yv = [&](int d, int e) -> T { return zero[e] ? (T)0 : P[e][row + (long long)d * G.W + m]; };
-        const T s1 = xval(1, 0) + xval(-1, 2) + yv(1, 0) + yv(-1, 2) + win[4][0] + win[2][2];
-        const T s2 = xval(2, 1) + xval(-2, 1) + yv(2, 1) + yv(-2, 1) + win[5][1] + win[1][1];
-        const T s3 = xval(3, 2) + xval(-3, 0) + yv(3, 2) + yv(-3, 0) + win[6][2] + win[0][0];
-        const T sum = (T)kC1 * s1 + (T)kC2 * s2 + (T)kC3 * s3;
-        store_stream(Xc + row + m, (h2 * Fc[row + m] - sum) * inv);
-      }
+      for (int i = 0; i < CPL; ++i) o[i] = out[i];
+      __builtin_nontemporal_store(o, reinterpret_cast<V*>(Xc + row));
+    } else {
+#pragma unroll
+      for (int i = 0; i < CPL; ++i)
+        if (ok[i]) store_stream(Xc + row + i, out[i]);
     }
 #pragma unroll
     for (int d = 0; d < 6; ++d)
@@ -553,6 +593,84 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ Rf, Geom
       for (int da = -1; da <= 1; ++da)
         s += w[dk + 1] * w[db + 1] * w[da + 1] * Rf[Gf.at(a0 + da, b0 + db, k0 + dk)];
   Fc[Gc.at(A, B, K)] = s;
+}
+
+// Full weighting on the colour-split layout, marching along z.  A thread
+// owns one fine compact column m of the fine rows 2B-sh-1 .. 2B-sh+1 of one
+// coarse row B (sh = g - 1; coarse node A sits on fine node 2A - sh) and the
+// coarse planes of its run.  Per fine row and plane it loads the C values of
+// its column (position q lives in colour array (q + row + plane + off) mod C)
+// and forms the x-weighted sums at the coarse positions of the column (q even)
+// with the left column's last value from the neighbouring lane; the y weights
+// combine its three rows, and the z weights combine consecutive fine planes,
+// the last of one coarse plane being the first of the next.  SKIPLAST: the
+// residuals of colour C-1 vanish (a Gauss-Seidel pass over that colour came
+// last) and are not loaded.
+template <typename T, int C, bool SKIPLAST>
+__global__ __launch_bounds__(256) void k_restrict_z(const T* __restrict__ Rf, Geom Gf, T* __restrict__ Fc, Geom Gc) {
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int sh = Gf.g - 1;
+  const int gc = Gc.g, nc = Gc.n;
+  const int Alo = gc, Ahi = gc + nc - 2;  // inner coarse nodes per axis
+  const int m_first = (2 * Alo - sh) / C, m_last = (2 * Ahi - sh) / C;
+  const int lane = threadIdx.x;
+  const int m = m_first + bx * 64 + lane;
+  const int B = Alo + by * 4 + (int)threadIdx.y;
+  const int kz = (nc - 1 + (int)gridDim.z - 1) / (int)gridDim.z;
+  const int K0 = Alo + bz * kz;
+  const int K1 = min(K0 + kz - 1, Ahi);
+  const bool live = m <= m_last && B <= Ahi;
+  const int mm = min(m, m_last);  // idle lanes of a partial wavefront load a valid column
+  const int Bc = min(B, Ahi);
+  const long long fplane = (long long)Gf.M * Gf.W;
+  const int b = 2 * Bc - sh;
+  const T q4 = (T)0.25, h2 = (T)0.5;
+  // x-weighted sums at the column's coarse positions (q = 0, 2, ... < C) of
+  // fine row j, plane p
+  auto xrow = [&](int j, int p, T* rx) {
+    const int sft = (j + p + Gf.off) & (C - 1);
+    const long long ro = (long long)p * fplane + (long long)j * Gf.W;
+    T v[C];
+#pragma unroll
+    for (int q = 0; q < C; ++q) {
+      const int col = (q + sft) & (C - 1);
+      v[q] = (SKIPLAST && col == C - 1) ? (T)0 : Rf[(long long)col * Gf.cs + ro + mm];
+    }
+    T left = __shfl_up(v[C - 1], 1, 64);
+    if (lane == 0) {
+      const int col = (C - 1 + sft) & (C - 1);
+      left = (SKIPLAST && col == C - 1) ? (T)0 : Rf[(long long)col * Gf.cs + ro + mm - 1];
+    }
+#pragma unroll
+    for (int q = 0; q < C; q += 2) rx[q / 2] = q4 * (q == 0 ? left : v[q - 1]) + h2 * v[q] + q4 * v[q + 1];
+  };
+  constexpr int NQ = C / 2;
+  auto yplane = [&](int p, T* ry) {
+    T r0[NQ], r1[NQ], r2[NQ];
+    xrow(b - 1, p, r0);
+    xrow(b, p, r1);
+    xrow(b + 1, p, r2);
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) ry[i] = q4 * r0[i] + h2 * r1[i] + q4 * r2[i];
+  };
+  if (K0 > K1) return;
+  T prev[NQ];
+  yplane(2 * K0 - sh - 1, prev);
+  for (int K = K0; K <= K1; ++K) {
+    T mid[NQ], nxt[NQ];
+    yplane(2 * K - sh, mid);
+    yplane(2 * K - sh + 1, nxt);
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < NQ; ++i) {
+        const int A = (C * m + 2 * i + sh) / 2;
+        if (A >= Alo && A <= Ahi) Fc[Gc.at(A, B, K)] = q4 * prev[i] + h2 * mid[i] + q4 * nxt[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) prev[i] = nxt[i];
+  }
 }
 
 // Residual of the 7-point operator fused with full-weighting restriction:
@@ -1316,10 +1434,24 @@ void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, i
       pass7_launch<double>((double*)phi, (const double*)f, G, colour, sor, zg, omega, h2, grid, blk, st);
     }
   } else {
-    if (f32)
-      k_pass19w<float><<<grid, blk, 0, st>>>((float*)phi, (const float*)f, G, colour, (float)h2, zmask);
-    else
-      k_pass19w<double><<<grid, blk, 0, st>>>((double*)phi, (const double*)f, G, colour, h2, zmask);
+    // planes per run: 8 from 127^3 up (16 for FP64 from 255^3 up), one on
+    // smaller levels, where parallelism rather than reuse along z matters
+    const int E = G.n - 1;
+    if (f32) {
+      const int kz = G.n >= 128 ? 8 : 1;
+      const dim3 g4((col_groups<4>(G) * E + 255) / 256, 1, (E + kz - 1) / kz);
+      if (zmask)
+        k_pass19v<float, 4, true><<<g4, 256, 0, st>>>((float*)phi, (const float*)f, G, colour, (float)h2, zmask);
+      else
+        k_pass19v<float, 4, false><<<g4, 256, 0, st>>>((float*)phi, (const float*)f, G, colour, (float)h2, 0);
+    } else {
+      const int kz = G.n >= 256 ? 16 : (G.n >= 128 ? 8 : 1);
+      const dim3 g2((col_groups<2>(G) * E + 255) / 256, 1, (E + kz - 1) / kz);
+      if (zmask)
+        k_pass19v<double, 2, true><<<g2, 256, 0, st>>>((double*)phi, (const double*)f, G, colour, h2, zmask);
+      else
+        k_pass19v<double, 2, false><<<g2, 256, 0, st>>>((double*)phi, (const double*)f, G, colour, h2, 0);
+    }
   }
 }
 
@@ -1390,12 +1522,27 @@ void resrestrict(const void* phi, const void* f, bool f32, const Geom& Gf, void*
     resrestrict7_t<double>((const double*)phi, (const double*)f, Gf, (double*)f_coarse, Gc, r0only, st);
 }
 
-void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom& Gc, bool f32, hipStream_t st) {
-  const dim3 grid = node_grid(Gc.M), blk(BX, BY);
-  if (f32)
-    k_restrict<float><<<grid, blk, 0, st>>>((const float*)r_fine, Gf, (float*)f_coarse, Gc);
-  else
-    k_restrict<double><<<grid, blk, 0, st>>>((const double*)r_fine, Gf, (double*)f_coarse, Gc);
+void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom& Gc, bool f32, hipStream_t st,
+                 bool last_zero) {
+  const int sh = Gf.g - 1, nc = Gc.n, C = Gf.C;
+  const int mcols = (2 * (Gc.g + nc - 2) - sh) / C - (2 * Gc.g - sh) / C + 1;
+  const int kzc = nc >= 128 ? 8 : (nc >= 32 ? 4 : 1);
+  const dim3 grid((mcols + 63) / 64, (nc - 1 + 3) / 4, (nc - 1 + kzc - 1) / kzc), blk(64, 4);
+#define PSN_RZ(T, CC, SK) \
+  k_restrict_z<T, CC, SK><<<grid, blk, 0, st>>>((const T*)r_fine, Gf, (T*)f_coarse, Gc)
+  if (C == 4) {
+    if (f32) {
+      if (last_zero) PSN_RZ(float, 4, true); else PSN_RZ(float, 4, false);
+    } else {
+      if (last_zero) PSN_RZ(double, 4, true); else PSN_RZ(double, 4, false);
+    }
+  } else {  // two colours: every residual is read
+    if (f32)
+      PSN_RZ(float, 2, false);
+    else
+      PSN_RZ(double, 2, false);
+  }
+#undef PSN_RZ
 }
 
 void prolong_add(const void* e_coarse, const Geom& Gc, void* phi_fine, const Geom& Gf, bool f32,

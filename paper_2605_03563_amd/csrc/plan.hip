@@ -834,8 +834,10 @@ void vcycle(poisson_plan_s* P, int l, bool zero_guess, hipStream_t st) {
   if (P->order == 2 && resrestrict_ok(L.G)) {
     resrestrict(L.phi, L.f, f32, L.G, Lc.f, Lc.G, st, o.nu1 > 0);
   } else {
+    // after a forward pre-smoothing sweep the residuals of the last colour
+    // vanish; on four-colour levels the restriction does not read them
     residual(L.phi, L.f, f32, L.tmp, f32, L.G, P->order, false, nullptr, st);
-    restrict_fw(L.tmp, L.G, Lc.f, Lc.G, f32, st);
+    restrict_fw(L.tmp, L.G, Lc.f, Lc.G, f32, st, C == 4 && o.nu1 > 0);
   }
   vcycle(P, l + 1, true, st);
   prolong_add(Lc.phi, Lc.G, L.phi, L.G, f32, st, o.nu2 > 0);

@@ -81,10 +81,14 @@ def test_four_colour_sweep(n, forward):
     assert rel_max(host(t), ref) < KTOL
 
 
-@pytest.mark.parametrize("n", [16, 64])
-def test_restrict_and_prolong(n):
-    say(f"transfers n={n}")
-    plan = pg.Plan(pg.cart_grid(n), pg.options("mg", lmax=-1))
+@pytest.mark.parametrize("order,n", [(2, 16), (2, 64), (2, 96), (6, 16), (6, 64), (6, 128)])
+def test_restrict_and_prolong(order, n):
+    """Full weighting and trilinear prolongation on the two-colour (7-point)
+    and four-colour (19-point) level layouts; n = 96 (coarsest 6) has ragged
+    tiles, n = 128 the plane runs of the large levels."""
+    say(f"transfers order={order} n={n}")
+    g = 1 if order == 2 else 3
+    plan = pg.Plan(pg.cart_grid(n, ghost=g), pg.options("mg", order=order, lmax=-1, coarsest=6 if n == 96 else 8))
     rng = np.random.default_rng(n)
     fine = rng.normal(size=(n - 1,) * 3)
     coarse = torch.zeros((n // 2 - 1,) * 3, dtype=torch.float64, device="cuda:0")
