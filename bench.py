@@ -396,7 +396,11 @@ def bench_c3(args):
     p64 = pg.Plan(grid, pg.options("mg", order=6, lmax=8), device=dev)
     phi = torch.zeros_like(rho)
     sec, r64, rec = _timed_solves(p64, rho, phi, args.tol, args.steps, args.warmup)
-    cycles = statistics.mean(rec["iterations"])
+    # the FP64 19-point multigrid stops on the residual its cycles form after
+    # the pre-smoothing: the last cycle begun ends there and counts as the
+    # half (nu1 of nu1 + nu2 sweeps) it runs
+    cycles_begun = statistics.mean(rec["iterations"])
+    cycles = cycles_begun - 0.5
     value = unknowns * cycles / sec / 1e9
     pass_ms = _pass_ms(p64, 4)
     bytes_per_pass = 10.0 * unknowns   # FP64: three other colours and f_c read, colour c written
@@ -468,7 +472,7 @@ def bench_c3(args):
         "time_to_1e-8_p50_ms": _pct(rec["lat_ms"], 50), "time_to_1e-8_p99_ms": _pct(rec["lat_ms"], 99),
         "time_to_1e-8_median_device_ms": statistics.median(a + b for a, b in zip(rec["t_multipole_ms"],
                                                                                  rec["t_iter_ms"])),
-        "v_cycles": cycles, "rate": r64.rate, "rel_residual": r64.rel_residual,
+        "v_cycles": cycles, "v_cycles_begun": cycles_begun, "rate": r64.rate, "rel_residual": r64.rel_residual,
         "t_multipole_ms": statistics.mean(rec["t_multipole_ms"]), "t_iter_ms": statistics.mean(rec["t_iter_ms"]),
         "s_s_gzups": unknowns / (statistics.mean(rec["t_iter_ms"]) / cycles * 1e-3) / 1e9,
         "s_t_gzups": unknowns / sec / 1e9,

@@ -67,7 +67,13 @@ extern "C" {
 #define POISSON_CG             1  /* conjugate gradients (Section 2.1.2) */
 #define POISSON_BICGSTAB       2  /* BiCGSTAB, spherical grids (Section 2.1.2), right-preconditioned
                                      by one red-black Gauss-Seidel step (Section 2.1.1) */
-#define POISSON_MG             3  /* FP64 geometric multigrid V-cycles (Section 2.1.3) */
+#define POISSON_MG             3  /* FP64 geometric multigrid V-cycles (Section 2.1.3); where the
+                                     finest level stores its residual for the restriction
+                                     (19-point star; 7-point grids above 256 intervals) the
+                                     stopping test reads that residual, formed after each
+                                     cycle's pre-smoothing, and the iterate returned is the one
+                                     after the last cycle's pre-smoothing (iterations counts the
+                                     cycles begun) */
 #define POISSON_MG_IR32        4  /* FP32 V-cycles inside FP64 iterative refinement */
 #define POISSON_BICGSTAB_MG32  5  /* spherical grids: BiCGSTAB right-preconditioned by one FP32
                                      V(nu1, nu2) cycle (four-colour Gauss-Seidel, cell-pair

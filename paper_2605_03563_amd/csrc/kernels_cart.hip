@@ -32,11 +32,12 @@ inline dim3 col_grid(const Geom& G) {
   return dim3((mc + BX - 1) / BX, (E + BY - 1) / BY, (E + kz - 1) / kz);
 }
 
-// grid of the LDS-staged 19-point kernels (64 x 8 threads per block)
+// grid of the LDS-staged 19-point kernels (64 x 8 threads per block); runs of
+// 32 planes from 255^3 up, 8 on the 127^3 level, one below
 inline dim3 staged_grid(const Geom& G) {
   const int mc = G.mhi() - G.mlo() + 1;
   const int E = G.n - 1;
-  const int kz = kz_for(G);
+  const int kz = G.n >= 256 ? 32 : kz_for(G);
   return dim3((mc + BX - 1) / BX, (E + TBY - 1) / TBY, (E + kz - 1) / kz);
 }
 
@@ -161,6 +162,7 @@ __global__ __launch_bounds__(256) void k_pass7(T* __restrict__ X, const T* __res
 // adjacent lanes and needs no barrier.
 constexpr int TROWS = TBY + 6;
 static_assert(TBY >= 6, "the six halo rows of a plane tile are loaded by the first six thread rows");
+static_assert(BX * TBY >= 8 * TROWS, "one halo-column cell per thread");
 constexpr int TCOLS = BX + 2;
 
 // Four-colour pass without LDS or barriers.  A lane owns CPL consecutive
@@ -289,7 +291,13 @@ __global__ __launch_bounds__(256) void k_pass19v(T* __restrict__ X, const T* __r
 // register window and the LDS tile are indexed by the node's position q in
 // its compact column (colour (q + shift) mod 4 of that row), so every register
 // index is a compile-time constant; the colour rotation goes into the load
-// and store addresses.
+// and store addresses.  The tile of a plane is the window's centre plane of
+// the block's rows, three halo rows above and below (loaded by the first six
+// thread rows) and one halo column on each side (one cell per thread for the
+// first 8 TROWS threads).  Those halo values, the right-hand sides and the
+// window's next plane are loaded one plane ahead, while the current plane is
+// computed from the other tile buffer, so each plane's loads are in flight
+// across the barrier and the compute of the plane before.
 template <typename T, typename TO>
 __global__ __launch_bounds__(BX * TBY) void k_residual19s(const T* __restrict__ X, const T* __restrict__ F,
                                                           TO* __restrict__ R, Geom G, T ih2,
@@ -298,6 +306,7 @@ __global__ __launch_bounds__(BX * TBY) void k_residual19s(const T* __restrict__ 
   int bx, by, bz;
   xcd_block(bx, by, bz);
   const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tid = ty * BX + tx;
   const int m0 = G.mlo() + bx * BX;
   const int m = m0 + tx;
   const int b0 = G.g + by * TBY;
@@ -315,42 +324,52 @@ __global__ __launch_bounds__(BX * TBY) void k_residual19s(const T* __restrict__ 
     const int col = (q + bb + kk + G.off) & 3;
     return X[(long long)col * G.cs + kk * plane + (long long)bb * G.W + mm];
   };
+  // this thread's halo row (thread rows 0..5) and halo-column cell (threads
+  // 0 .. 8 TROWS - 1: position, side, tile row)
+  const int hb = ty < 3 ? b0 - 3 + ty : b0 + TBY + (ty - 3);
+  const int htr = ty < 3 ? ty : TBY + ty;
+  const bool hrow = ty < 6 && hb >= 0 && hb < G.M && colok;
+  const int cq = tid & 3, cside = (tid >> 2) & 1, ctr = tid >> 3;
+  const int chb = b0 - 3 + ctr, chm = cside ? m0 + BX : m0 - 1;
+  const int ctc = cside ? BX + 1 : 0;
+  const bool hcell = tid < 8 * TROWS;
+  const bool hcol = hcell && chb >= 0 && chb < G.M && chm >= 0 && chm < G.W;
   T win[7][4];  // win[d + 3][q] at (m, b, k + d)
 #pragma unroll
   for (int d = -3; d <= 2; ++d)
 #pragma unroll
     for (int q = 0; q < 4; ++q) win[d + 3][q] = (colok && rowok) ? load(b, k0 + d, m, q) : (T)0;
-  double acc = 0.0;
   const bool live = m <= G.mhi() && b <= last;
-  for (int k = k0; k <= k1; ++k) {
-    const int buf = k & 1;
+  T hr[4], hc, fq[4], wn[4];
+  auto fetch = [&](int k) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) win[6][q] = (colok && rowok) ? load(b, k + 3, m, q) : (T)0;
-    // right-hand sides of the column's four nodes, loaded before the barrier
+    for (int q = 0; q < 4; ++q) hr[q] = hrow ? load(hb, k, m, q) : (T)0;
+    hc = hcol ? load(chb, k, chm, cq) : (T)0;
     const int s = (b + k + G.off) & 3;
-    T fq[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) fq[q] = live ? F[(long long)((q + s) & 3) * G.cs + k * plane + cb] : (T)0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) tile[buf][ty + 3][q][tx + 1] = win[3][q];
+    for (int q = 0; q < 4; ++q) wn[q] = (colok && rowok) ? load(b, k + 3, m, q) : (T)0;
+  };
+  fetch(k0);
+  double acc = 0.0;
+  for (int k = k0; k <= k1; ++k) {
+    const int buf = k & 1;
+    T fc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      win[6][q] = wn[q];
+      fc[q] = fq[q];
+      tile[buf][ty + 3][q][tx + 1] = win[3][q];
+    }
     if (ty < 6) {
-      const int hb = ty < 3 ? b0 - 3 + ty : b0 + TBY + (ty - 3);
-      const int tr = ty < 3 ? ty : TBY + ty;
-      const bool ok = hb >= 0 && hb < G.M && colok;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) tile[buf][tr][q][tx + 1] = ok ? load(hb, k, m, q) : (T)0;
+      for (int q = 0; q < 4; ++q) tile[buf][htr][q][tx + 1] = hr[q];
     }
-    if (tx < 2) {
-      const int hm = tx == 0 ? m0 - 1 : m0 + BX;
-      const int tc = tx == 0 ? 0 : BX + 1;
-      for (int tr = ty; tr < TROWS; tr += TBY) {
-        const int hb = b0 - 3 + tr;
-        const bool ok = hb >= 0 && hb < G.M && hm >= 0 && hm < G.W;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) tile[buf][tr][q][tc] = ok ? load(hb, k, hm, q) : (T)0;
-      }
-    }
+    if (hcell) tile[buf][ctr][cq][ctc] = hc;
     __syncthreads();
+    if (k < k1) fetch(k + 1);
+    const int s = (b + k + G.off) & 3;
     if (live) {
       const int r0 = ty + 3;
 #pragma unroll
@@ -369,7 +388,7 @@ __global__ __launch_bounds__(BX * TBY) void k_residual19s(const T* __restrict__ 
         }
         const T lap = ((T)(3.0 * kC0) * win[3][q] + (T)kC1 * sd[0] + (T)kC2 * sd[1] + (T)kC3 * sd[2]) * ih2;
         const long long idx = (long long)((q + s) & 3) * G.cs + k * plane + cb;
-        const T res = fq[q] - lap;
+        const T res = fc[q] - lap;
         if (R) R[idx] = (TO)res;
         acc += (double)res * (double)res;
       }
@@ -1434,18 +1453,19 @@ void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, i
       pass7_launch<double>((double*)phi, (const double*)f, G, colour, sor, zg, omega, h2, grid, blk, st);
     }
   } else {
-    // planes per run: 8 from 127^3 up (16 for FP64 from 255^3 up), one on
-    // smaller levels, where parallelism rather than reuse along z matters
+    // planes per run: long runs on the 511^3 level, where the window's reload
+    // at each run start costs bandwidth; shorter ones below, where the
+    // blocks of a pass must still fill the chip
     const int E = G.n - 1;
     if (f32) {
-      const int kz = G.n >= 128 ? 8 : 1;
+      const int kz = G.n >= 512 ? 8 : G.n >= 256 ? 4 : G.n >= 128 ? 2 : 1;
       const dim3 g4((col_groups<4>(G) * E + 255) / 256, 1, (E + kz - 1) / kz);
       if (zmask)
         k_pass19v<float, 4, true><<<g4, 256, 0, st>>>((float*)phi, (const float*)f, G, colour, (float)h2, zmask);
       else
         k_pass19v<float, 4, false><<<g4, 256, 0, st>>>((float*)phi, (const float*)f, G, colour, (float)h2, 0);
     } else {
-      const int kz = G.n >= 256 ? 16 : (G.n >= 128 ? 8 : 1);
+      const int kz = G.n >= 512 ? 16 : G.n >= 256 ? 8 : G.n >= 128 ? 2 : 1;
       const dim3 g2((col_groups<2>(G) * E + 255) / 256, 1, (E + kz - 1) / kz);
       if (zmask)
         k_pass19v<double, 2, true><<<g2, 256, 0, st>>>((double*)phi, (const double*)f, G, colour, h2, zmask);

@@ -987,26 +987,88 @@ void mg_step(poisson_plan_s* P, hipStream_t st) {
   finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
 }
 
-int capture_step(poisson_plan_s* P) {
-  if (P->step_exec) return POISSON_OK;
+// Record what fn enqueues on the capture stream into *exec (once).
+template <typename Fn>
+int capture_into(poisson_plan_s* P, hipGraphExec_t* exec, Fn fn) {
+  if (*exec) return POISSON_OK;
   hipGraph_t graph = nullptr;
   hipStream_t cs = capture_stream(P);
   HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  if (!P->nlv.empty())
-    spai_step(P, cs);
-  else
-    mg_step(P, cs);
+  fn(cs);
   hipError_t e = hipStreamEndCapture(cs, &graph);
   if (e != hipSuccess) {
     set_error("graph capture failed: %s", hipGetErrorString(e));
     return POISSON_EHIP;
   }
-  e = hipGraphInstantiate(&P->step_exec, graph, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
   hipGraphDestroy(graph);
   if (e != hipSuccess) {
-    P->step_exec = nullptr;
+    *exec = nullptr;
     set_error("graph instantiation failed: %s", hipGetErrorString(e));
     return POISSON_EHIP;
+  }
+  return POISSON_OK;
+}
+
+int capture_step(poisson_plan_s* P) {
+  return capture_into(P, &P->step_exec, [P](hipStream_t cs) {
+    if (!P->nlv.empty())
+      spai_step(P, cs);
+    else
+      mg_step(P, cs);
+  });
+}
+
+// FP64 multigrid whose finest level stores its residual for the restriction
+// (four-colour levels; two-colour levels too large for the fused residual and
+// restriction): a solve stops on that residual, formed after the
+// pre-smoothing of every cycle, instead of forming another one after the
+// cycle.  The iterate it returns is the one after that pre-smoothing.
+bool split_cycle(const poisson_plan_s* P) {
+  return !P->mg32 && P->lv.size() > 1 && P->opts.nu1 > 0 && !(P->order == 2 && resrestrict_ok(P->G0));
+}
+
+// head of a cycle: pre-smoothing of the finest level, its residual (kept for
+// the restriction) and the residual's norm^2 into scal->v[kRes2]
+void cycle_head(poisson_plan_s* P, hipStream_t st) {
+  Level& L = P->lv[0];
+  for (int s = 0; s < P->opts.nu1; ++s)
+    for (int c = 0; c < P->C; ++c) colour_pass(L.phi, L.f, false, L.G, P->order, c, 1.0, st);
+  residual(L.phi, L.f, false, L.tmp, false, L.G, P->order, false, P->partial, st);
+  finish_sum(P->partial, residual_blocks(L.G), 1, P->scal, kRes2, st);
+}
+
+// tail of a cycle: restriction of the head's residual (the last colour's
+// vanish on four-colour levels), the coarse cycle, prolongation and
+// post-smoothing
+void cycle_tail(poisson_plan_s* P, hipStream_t st) {
+  Level& L = P->lv[0];
+  Level& Lc = P->lv[1];
+  const poisson_opts_t& o = P->opts;
+  restrict_fw(L.tmp, L.G, Lc.f, Lc.G, false, st, P->C == 4);
+  vcycle(P, 1, true, st);
+  prolong_add(Lc.phi, Lc.G, L.phi, L.G, false, st, o.nu2 > 0);
+  for (int s = 0; s < o.nu2; ++s)
+    for (int c = P->C - 1; c >= 0; --c) colour_pass(L.phi, L.f, false, L.G, P->order, c, 1.0, st);
+}
+
+// first == true: the head of the first cycle; else the tail of the current
+// cycle and the head of the next
+int launch_split(poisson_plan_s* P, bool first) {
+  if (!capture_stream(P)) {
+    if (!first) cycle_tail(P, P->st);
+    cycle_head(P, P->st);
+    return launch_check("multigrid step");
+  }
+  if (first) {
+    CHK(capture_into(P, &P->head_exec, [P](hipStream_t cs) { cycle_head(P, cs); }));
+    HIPCHK(hipGraphLaunch(P->head_exec, P->st));
+  } else {
+    CHK(capture_into(P, &P->cont_exec, [P](hipStream_t cs) {
+      cycle_tail(P, cs);
+      cycle_head(P, cs);
+    }));
+    HIPCHK(hipGraphLaunch(P->cont_exec, P->st));
   }
   return POISSON_OK;
 }
@@ -1308,8 +1370,9 @@ int solve_cart(poisson_plan_s* P, const double* rho, double* phi, double tol, po
       }
     }
   } else {  // multigrid
+    const bool split = split_cycle(P);
     while (!conv && it < o.max_iter) {
-      CHK(launch_step(P));
+      CHK(split ? launch_split(P, it == 0) : launch_step(P));
       ++it;
       if (it % o.check_every == 0 || it == o.max_iter) {
         CHK(read_scalars(P, kRes2, 1));
@@ -1821,6 +1884,8 @@ int poisson_plan(poisson_plan_t* out, const poisson_grid_t* grid, const poisson_
 void poisson_plan_destroy(poisson_plan_t P) {
   if (!P) return;
   if (P->step_exec) hipGraphExecDestroy(P->step_exec);
+  if (P->head_exec) hipGraphExecDestroy(P->head_exec);
+  if (P->cont_exec) hipGraphExecDestroy(P->cont_exec);
   if (P->iter_exec) hipGraphExecDestroy(P->iter_exec);
   for (int i = 0; i < 3; ++i)
     if (P->ev[i]) hipEventDestroy(P->ev[i]);

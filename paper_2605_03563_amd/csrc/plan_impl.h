@@ -83,6 +83,10 @@ struct poisson_plan_s {
   double* host = nullptr; // pinned scalars
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   hipGraphExec_t step_exec = nullptr;
+  // FP64 multigrid solves whose fine level stores its residual: the first
+  // cycle head, and the tail of a cycle followed by the next head
+  hipGraphExec_t head_exec = nullptr;
+  hipGraphExec_t cont_exec = nullptr;
 };
 
 namespace psn {
