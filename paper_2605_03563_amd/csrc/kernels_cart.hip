@@ -165,19 +165,20 @@ static_assert(TBY >= 6, "the six halo rows of a plane tile are loaded by the fir
 static_assert(BX * TBY >= 8 * TROWS, "one halo-column cell per thread");
 constexpr int TCOLS = BX + 2;
 
-// Four-colour pass without LDS or barriers.  A lane owns CPL consecutive
-// compact columns m0 .. m0+CPL-1 of one row (16-byte vector loads: two FP64
-// or four FP32 columns) and marches the planes of its run; lanes are numbered
-// over (column group, row) pairs of the level, so every lane of a wavefront
-// has work whatever the row length.  The register window along z holds the
-// three other colours at the lane's columns for planes k-3..k+3 (one new
-// vector load per colour and plane); x-neighbours in the adjacent compact
-// columns come from the lane's own vector or from the neighbouring lanes,
-// which hold the adjacent column group of the same row (lanes at a wavefront
-// or row edge load theirs); y-neighbours are loaded.  ZM: colours whose bit
-// is set in zmask are read as zero (the first sweep on a zero initial guess).
-// The node at position q of a compact column in a row with colour shift s has
-// colour (q + s) mod 4.
+// Four-colour pass.  A lane owns CPL consecutive compact columns
+// m0 .. m0+CPL-1 of one row (16-byte vector loads: two FP64 or four FP32
+// columns) and marches the planes of its run; lanes are numbered over (column
+// group, row) pairs of the level, so every lane of a wavefront has work
+// whatever the row length, and a block of 256 lanes holds about 256 / groups
+// consecutive rows.  The register window along z holds the three other
+// colours at the lane's columns for planes k-3..k+3 (one new vector load per
+// colour and plane).  Each plane the lanes put their window's centre vectors
+// in LDS (double-buffered, one barrier per plane); x-neighbours in the
+// adjacent compact columns and y-neighbours in rows b +- 1..3 come from there
+// when the lane holding them is in the block, and are loaded otherwise.  ZM:
+// colours whose bit is set in zmask are read as zero (the first sweep on a
+// zero initial guess).  The node at position q of a compact column in a row
+// with colour shift s has colour (q + s) mod 4.
 template <typename T, int N> struct VecOf;
 template <> struct VecOf<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
 template <> struct VecOf<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
@@ -192,14 +193,17 @@ template <typename T, int CPL, bool ZM>
 __global__ __launch_bounds__(256) void k_pass19v(T* __restrict__ X, const T* __restrict__ F, Geom G, int c, T h2,
                                                  int zmask) {
   typedef typename VecOf<T, CPL>::type V;
+  constexpr int BT = 256;
+  __shared__ V cen[2][3][BT];
   int bx, by, bz;
   xcd_block(bx, by, bz);
   const int ngr = col_groups<CPL>(G);
   const int E = G.n - 1;
-  const int lane = threadIdx.x & 63;
-  const int fi = bx * 256 + (int)threadIdx.x;
-  const bool live = fi < ngr * E;
-  const int fl = live ? fi : ngr * E - 1;  // idle lanes mirror the last pair (loads stay in the array)
+  const int tid = threadIdx.x;
+  const int fi = bx * BT + tid;
+  const int nfl = ngr * E;
+  const bool live = fi < nfl;
+  const int fl = live ? fi : nfl - 1;  // idle lanes mirror the last pair (loads stay in the array)
   const int gp = fl % ngr;
   const int m0 = gp * CPL;
   const int b = G.g + fl / ngr;
@@ -207,8 +211,11 @@ __global__ __launch_bounds__(256) void k_pass19v(T* __restrict__ X, const T* __r
   const int kz = planes_per_block(G);
   const int k0 = G.g + bz * kz;
   const int k1 = min(k0 + kz - 1, last);
-  const bool needl = (lane == 0 || gp == 0) && m0 >= 1;
-  const bool needr = (lane == 63 || gp == ngr - 1) && m0 + CPL < G.W;
+  // x-neighbour groups of the same row held by the adjacent lanes of the block
+  const bool lds_l = gp > 0 && tid > 0;
+  const bool lds_r = gp < ngr - 1 && tid < BT - 1;
+  const bool needl = !lds_l && m0 >= 1;
+  const bool needr = !lds_r && m0 + CPL < G.W;
   const T* P[3];
   bool zero[3];
 #pragma unroll
@@ -223,6 +230,16 @@ __global__ __launch_bounds__(256) void k_pass19v(T* __restrict__ X, const T* __r
     if (ZM && zero[e]) return V{};
     return *reinterpret_cast<const V*>(P[e] + off);
   };
+  // y-neighbours: colour c+d (slot d-1) at row b+d, colour c-d (slot 3-d) at
+  // row b-d, d = 1, 2, 3; lane tid + dy ngr holds row b+dy of the same group
+  constexpr int dy[6] = {1, -1, 2, -2, 3, -3};
+  constexpr int ey[6] = {0, 2, 1, 1, 2, 0};
+  bool ylds[6];
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const int t = tid + dy[i] * ngr;
+    ylds[i] = t >= 0 && t < BT && fi + dy[i] * ngr < nfl;
+  }
   V win[7][3];
 #pragma unroll
   for (int d = -3; d <= 2; ++d)
@@ -232,25 +249,31 @@ __global__ __launch_bounds__(256) void k_pass19v(T* __restrict__ X, const T* __r
   const T* __restrict__ Fc = F + (long long)c * G.cs;
   const T inv = (T)(1.0 / (3.0 * kC0));
   for (int k = k0; k <= k1; ++k) {
+    const int buf = k & 1;
     const long long row = k * plane + cb;
 #pragma unroll
+    for (int e = 0; e < 3; ++e) cen[buf][e][tid] = win[3][e];
+#pragma unroll
     for (int e = 0; e < 3; ++e) win[6][e] = ldv(e, row + 3 * plane);
-    // y-neighbours: colour c+d (slot d-1) at row b+d, colour c-d (slot 3-d) at row b-d
     V yv[6];
-    yv[0] = ldv(0, row + G.W);
-    yv[1] = ldv(2, row - G.W);
-    yv[2] = ldv(1, row + 2 * (long long)G.W);
-    yv[3] = ldv(1, row - 2 * (long long)G.W);
-    yv[4] = ldv(2, row + 3 * (long long)G.W);
-    yv[5] = ldv(0, row - 3 * (long long)G.W);
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+      if (!ylds[i]) yv[i] = ldv(ey[i], row + dy[i] * (long long)G.W);
     const V fv = *reinterpret_cast<const V*>(Fc + row);
     T lft[3], rgt[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
-      lft[e] = __shfl_up(win[3][e][CPL - 1], 1, 64);
-      rgt[e] = __shfl_down(win[3][e][0], 1, 64);
-      if (needl) lft[e] = (ZM && zero[e]) ? (T)0 : P[e][row - 1];
-      if (needr) rgt[e] = (ZM && zero[e]) ? (T)0 : P[e][row + CPL];
+      lft[e] = (needl && !(ZM && zero[e])) ? P[e][row - 1] : (T)0;
+      rgt[e] = (needr && !(ZM && zero[e])) ? P[e][row + CPL] : (T)0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+      if (ylds[i]) yv[i] = cen[buf][ey[i]][tid + dy[i] * ngr];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      if (lds_l) lft[e] = cen[buf][e][tid - 1][CPL - 1];
+      if (lds_r) rgt[e] = cen[buf][e][tid + 1][0];
     }
     const int q = (c - b - k - G.off) & 3;  // position of the colour-c node in each compact column
     T out[CPL];
@@ -280,6 +303,8 @@ __global__ __launch_bounds__(256) void k_pass19v(T* __restrict__ X, const T* __r
       for (int i = 0; i < CPL; ++i)
         if (ok[i]) store_stream(Xc + row + i, out[i]);
     }
+    // the next plane writes the other buffer; the plane after it waits at
+    // that plane's barrier, which every lane passes only after these reads
 #pragma unroll
     for (int d = 0; d < 6; ++d)
 #pragma unroll
