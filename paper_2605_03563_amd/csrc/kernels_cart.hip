@@ -1483,14 +1483,14 @@ void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, i
     // blocks of a pass must still fill the chip
     const int E = G.n - 1;
     if (f32) {
-      const int kz = G.n >= 512 ? 8 : G.n >= 256 ? 4 : G.n >= 128 ? 2 : 1;
+      const int kz = G.n >= 512 ? 8 : G.n >= 128 ? 2 : 1;
       const dim3 g4((col_groups<4>(G) * E + 255) / 256, 1, (E + kz - 1) / kz);
       if (zmask)
         k_pass19v<float, 4, true><<<g4, 256, 0, st>>>((float*)phi, (const float*)f, G, colour, (float)h2, zmask);
       else
         k_pass19v<float, 4, false><<<g4, 256, 0, st>>>((float*)phi, (const float*)f, G, colour, (float)h2, 0);
     } else {
-      const int kz = G.n >= 512 ? 16 : G.n >= 256 ? 8 : G.n >= 128 ? 2 : 1;
+      const int kz = G.n >= 512 ? 16 : G.n >= 256 ? 4 : G.n >= 128 ? 2 : 1;
       const dim3 g2((col_groups<2>(G) * E + 255) / 256, 1, (E + kz - 1) / kz);
       if (zmask)
         k_pass19v<double, 2, true><<<g2, 256, 0, st>>>((double*)phi, (const double*)f, G, colour, h2, zmask);
