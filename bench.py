@@ -434,8 +434,8 @@ def bench_c3(args):
              "GBps": 12.0 * unknowns / (pass7_ms * 1e-3) / 1e9,
              "frac": 12.0 * unknowns / (pass7_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
              "gcell_updates_per_s": unknowns / (2 * pass7_ms * 1e-3) / 1e9,
-             "traffic": traffic_from_profiles("rb_pass7_f64_c2_511"),
-             "kernel": "k_pass7<double> (fine-level red-black GS colour pass)",
+             "traffic": traffic_from_profiles("rb_pass7v_f64_c2_511"),
+             "kernel": "k_pass7v<double, 2> (fine-level red-black GS colour pass)",
              "solve": {"v_cycles": r7.iterations, "ms": r7.t_multipole_ms + r7.t_iter_ms}}
     del p7, phi7, rho7
 

@@ -152,6 +152,104 @@ __global__ __launch_bounds__(256) void k_pass7(T* __restrict__ X, const T* __res
   }
 }
 
+// Vector types of CPL consecutive compact columns (16-byte loads for two
+// FP64 or four FP32 values, 8-byte for two FP32).
+template <typename T, int N> struct VecOf;
+template <> struct VecOf<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct VecOf<float, 2> { typedef float type __attribute__((ext_vector_type(2))); };
+
+// 7-point red-black Gauss-Seidel pass (omega = 1) of colour c with CPL
+// consecutive compact columns m0 .. m0+CPL-1 per lane, read and written as
+// vectors; otherwise as k_pass7 (other colour's plane window z[], every load
+// of the lane's KZP planes issued before the first update).  In a row of
+// colour shift r the node of column m is a = 2m + r: its x-neighbours are the
+// other colour at columns m and m - 1 (r = 0) or m + 1 (r = 1), from the
+// lane's own vector except at its ends, where the neighbouring lanes supply
+// them (the wavefront's edge lanes load theirs).  ZG: the other colour is
+// taken as zero.
+template <typename T, int CPL, bool ZG, int KZP>
+__global__ __launch_bounds__(256) void k_pass7v(T* __restrict__ X, const T* __restrict__ F, Geom G, int c, T h2) {
+  typedef typename VecOf<T, CPL>::type V;
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int lane = threadIdx.x;
+  const int m0 = G.mlo() + CPL * (bx * BX + lane);
+  const int b = G.g + by * BY + (int)threadIdx.y;
+  const int last = G.g + G.n - 2;
+  const bool live = m0 <= G.mhi() && b <= last;
+  const int mm = live ? m0 : G.mlo();  // idle lanes load a valid group (they still shuffle)
+  const int bb = min(b, last);
+  const int kz = planes_per_block(G);
+  const int k0 = G.g + bz * kz;
+  const int k1 = min(k0 + kz - 1, last);
+  const long long plane = (long long)G.M * G.W;
+  const long long W = G.W;
+  const long long q0 = G.row(bb, 0) + mm;
+  T* __restrict__ xc = X + (long long)c * G.cs + q0;
+  const T* __restrict__ xo = X + (long long)(c ^ 1) * G.cs + q0;
+  const T* __restrict__ fc = F + (long long)c * G.cs + q0;
+  auto ld = [](const T* p) -> V { return *reinterpret_cast<const V*>(p); };
+  V z[KZP + 2];
+#pragma unroll
+  for (int t = 0; t < KZP + 2; ++t) z[t] = ZG ? V{} : ld(xo + (long long)min(k0 - 1 + t, k1 + 1) * plane);
+  V ym[KZP], yp[KZP], fv[KZP];
+  T xe[KZP];
+  const bool needl = lane == 0 && mm >= 1;
+  const bool needr = lane == BX - 1 && mm + CPL < G.W;
+#pragma unroll
+  for (int t = 0; t < KZP; ++t) {
+    const int k = min(k0 + t, k1);
+    const long long o = (long long)k * plane;
+    const int r = (c - bb - k - G.off) & 1;
+    if (!ZG) {
+      ym[t] = ld(xo + o - W);
+      yp[t] = ld(xo + o + W);
+      xe[t] = (T)0;
+      if (r == 0 && needl) xe[t] = xo[o - 1];
+      if (r == 1 && needr) xe[t] = xo[o + CPL];
+    }
+    fv[t] = ld(fc + o);
+  }
+  const T sixth = (T)(1.0 / 6.0);
+#pragma unroll
+  for (int t = 0; t < KZP; ++t) {
+    const int k = k0 + t;
+    const int r = (c - bb - k - G.off) & 1;
+    V o;
+    if (ZG) {
+#pragma unroll
+      for (int i = 0; i < CPL; ++i) o[i] = ((T)0 - h2 * fv[t][i]) * sixth;
+    } else {
+      T lft = __shfl_up(z[t + 1][CPL - 1], 1, 64);
+      T rgt = __shfl_down(z[t + 1][0], 1, 64);
+      if (lane == 0) lft = xe[t];
+      if (lane == BX - 1) rgt = xe[t];
+#pragma unroll
+      for (int i = 0; i < CPL; ++i) {
+        const T xs = r == 0 ? (i == 0 ? lft : z[t + 1][i - 1]) : (i == CPL - 1 ? rgt : z[t + 1][i + 1]);
+        const T sum = z[t + 1][i] + xs + ym[t][i] + yp[t][i] + z[t][i] + z[t + 2][i];
+        o[i] = (sum - h2 * fv[t][i]) * sixth;
+      }
+    }
+    bool ok[CPL];
+    bool all = live && k <= k1;
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      ok[i] = live && k <= k1 && mm + i <= G.mhi() && G.inner(2 * (mm + i) + r);
+      all = all && ok[i];
+    }
+    T* __restrict__ dst = xc + (long long)k * plane;
+    if (all) {
+      __builtin_nontemporal_store(o, reinterpret_cast<V*>(dst));
+    } else {
+#pragma unroll
+      for (int i = 0; i < CPL; ++i)
+        if (ok[i]) store_stream(dst + i, o[i]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------- 19-point star
 // Both kernels keep a register window along z: the values at the thread's own
 // compact columns of row b for planes k-3..k+3, so each plane costs one new
@@ -179,10 +277,6 @@ constexpr int TCOLS = BX + 2;
 // colours whose bit is set in zmask are read as zero (the first sweep on a
 // zero initial guess).  The node at position q of a compact column in a row
 // with colour shift s has colour (q + s) mod 4.
-template <typename T, int N> struct VecOf;
-template <> struct VecOf<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
-template <> struct VecOf<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
-
 // column groups of CPL compact columns covering the columns 0 .. mhi (the
 // four-colour levels have mlo = 0); loads of a group stay below the row pitch
 // because W is a multiple of 32 and W >= mhi + 1
@@ -1453,9 +1547,39 @@ static void pass7_kz(T* x, const T* f, const Geom& G, int colour, T omega, T h2,
     k_pass7<T, SOR, ZG, 1, false><<<grid, blk, 0, st>>>(x, f, G, colour, omega, h2, nullptr);
 }
 
+// columns per lane of the vector 7-point pass: as many as make one 16-byte
+// load while a row still fills a wavefront, and the last group stays inside
+// the row pitch; 1 selects the one-column kernel
+template <typename T>
+static int pass7_cpl(const Geom& G) {
+  const int mc = G.mhi() - G.mlo() + 1;
+  for (int cpl = (int)(16 / sizeof(T)); cpl >= 2; cpl /= 2)
+    if (mc >= BX * cpl && G.mhi() + cpl - 1 < G.W && G.mlo() % cpl == 0) return cpl;
+  return 1;
+}
+
+template <typename T, int CPL>
+static void pass7v_launch(T* x, const T* f, const Geom& G, int colour, bool zg, T h2, hipStream_t st) {
+  const int mc = G.mhi() - G.mlo() + 1, E = G.n - 1;
+  constexpr int KZP = 4;
+  const dim3 grid((mc + BX * CPL - 1) / (BX * CPL), (E + BY - 1) / BY, (E + KZP - 1) / KZP), blk(BX, BY);
+  if (zg)
+    k_pass7v<T, CPL, true, KZP><<<grid, blk, 0, st>>>(x, f, G, colour, h2);
+  else
+    k_pass7v<T, CPL, false, KZP><<<grid, blk, 0, st>>>(x, f, G, colour, h2);
+}
+
 template <typename T>
 static void pass7_launch(T* x, const T* f, const Geom& G, int colour, bool sor, bool zg, T omega, T h2, dim3 grid,
                          dim3 blk, hipStream_t st) {
+  if (!sor) {
+    const int cpl = pass7_cpl<T>(G);
+    if (cpl == 4) {
+      if constexpr (sizeof(T) == 4) return pass7v_launch<T, 4>(x, f, G, colour, zg, h2, st);
+    } else if (cpl == 2) {
+      return pass7v_launch<T, 2>(x, f, G, colour, zg, h2, st);
+    }
+  }
   if (sor)
     pass7_kz<T, true, false>(x, f, G, colour, omega, h2, grid, blk, st);
   else if (zg)
