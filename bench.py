@@ -974,7 +974,7 @@ def bench_c2(args):
     pass_ms = ev0.elapsed_time(ev1) / (2 * sweeps)
     bytes_per_pass = 12.0 * unknowns          # FP64 GS colour pass: 24 B per unknown per full sweep
     achieved = bytes_per_pass / (pass_ms * 1e-3) / 1e9
-    traffic = traffic_from_profiles("rb_pass7_f64_c2_255")
+    traffic = traffic_from_profiles("rb_pass7v_f64_c2_255")
 
     # plain copy bandwidth on the same device for context
     a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -1027,7 +1027,7 @@ def bench_c2(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": traffic,
-                     "kernel": "k_pass7<double,false> (fine-level red-black GS colour pass)",
+                     "kernel": "k_pass7v<double, 2> (fine-level red-black GS colour pass)",
                      "algorithmic_bytes_per_launch": bytes_per_pass},
         "cpu_baseline": cpu,
     }
