@@ -32,10 +32,31 @@ inline dim3 col_grid(const Geom& G) {
   return dim3((mc + BX - 1) / BX, (E + BY - 1) / BY, (E + kz - 1) / kz);
 }
 
+// First compact column of the LDS-staged 19-point kernels' blocks.  On
+// four-colour levels compact column 0 holds a single unknown per row (node 3
+// of the first three ghost layers), and the unknowns span mhi + 1 = n/4 + 1
+// columns: starting the blocks at column 1 lets n/4 columns fill whole
+// wavefronts, and a small kernel forms the residuals of column 0.
+inline int staged_mbase(const Geom& G) { return (G.C == 4 && G.mlo() == 0 && G.g == 3) ? 1 : G.mlo(); }
+inline bool staged_col0(const Geom& G) { return staged_mbase(G) > G.mlo(); }
+inline unsigned col0_blocks(const Geom& G) {
+  const long long E = G.n - 1;
+  return staged_col0(G) ? (unsigned)((E * E + 255) / 256) : 0u;
+}
+
+// 256-thread blocks numbered over the (compact column, row) pairs of the
+// unknowns, z-runs as col_grid
+inline dim3 flat_grid(const Geom& G) {
+  const int mc = G.mhi() - G.mlo() + 1;
+  const int E = G.n - 1;
+  const int kz = kz_for(G);
+  return dim3((unsigned)(((long long)mc * E + 255) / 256), 1, (E + kz - 1) / kz);
+}
+
 // grid of the LDS-staged 19-point kernels (64 x 8 threads per block); runs of
 // 32 planes from 255^3 up, 8 on the 127^3 level, one below
 inline dim3 staged_grid(const Geom& G) {
-  const int mc = G.mhi() - G.mlo() + 1;
+  const int mc = G.mhi() - staged_mbase(G) + 1;
   const int E = G.n - 1;
   const int kz = G.n >= 256 ? 32 : kz_for(G);
   return dim3((mc + BX - 1) / BX, (E + TBY - 1) / TBY, (E + kz - 1) / kz);
@@ -420,13 +441,13 @@ __global__ __launch_bounds__(256) void k_pass19v(T* __restrict__ X, const T* __r
 template <typename T, typename TO>
 __global__ __launch_bounds__(BX * TBY) void k_residual19s(const T* __restrict__ X, const T* __restrict__ F,
                                                           TO* __restrict__ R, Geom G, T ih2,
-                                                          double* __restrict__ partial) {
+                                                          double* __restrict__ partial, int mbase) {
   __shared__ T tile[2][TROWS][4][TCOLS];  // double-buffered by plane parity
   int bx, by, bz;
   xcd_block(bx, by, bz);
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * BX + tx;
-  const int m0 = G.mlo() + bx * BX;
+  const int m0 = mbase + bx * BX;
   const int m = m0 + tx;
   const int b0 = G.g + by * TBY;
   const int b = b0 + ty;
@@ -525,6 +546,32 @@ __global__ __launch_bounds__(BX * TBY) void k_residual19s(const T* __restrict__ 
   }
 }
 
+// Residuals of the unknowns in compact column 0 of a four-colour level (node
+// a = 3, the blocks of the staged kernels start at column 1): one thread per
+// (row, plane); partial sums of r^2 per block go to partial[pbase + block].
+// ZU: the unknowns of u are taken as zero.
+template <typename T, typename TO, bool ZU>
+__global__ __launch_bounds__(256) void k_res19_col0(const T* __restrict__ X, const T* __restrict__ F,
+                                                    TO* __restrict__ R, Geom G, T ih2, double* __restrict__ partial,
+                                                    unsigned pbase) {
+  const int E = G.n - 1;
+  const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  double acc = 0.0;
+  if (t < (long long)E * E) {
+    const int b = G.g + (int)(t % E);
+    const int k = G.g + (int)(t / E);
+    const int a = 3;  // the only unknown of column 0 (three ghost layers)
+    const long long idx = G.at(a, b, k);
+    const T res = F[idx] - lap_at<T, 6, ZU>(X, G, a, b, k, ih2);
+    if (R) R[idx] = (TO)res;
+    acc = (double)res * (double)res;
+  }
+  if (partial) {
+    const double sum = block_sum(acc);
+    if (threadIdx.x == 0) partial[pbase + blockIdx.x] = sum;
+  }
+}
+
 // ---------------------------------------------------------------- residual
 // r = f - L u for every unknown.  One thread handles the C consecutive nodes
 // a = C*m .. C*m+C-1 of row (b, k) and marches KZ planes.  In a row whose
@@ -536,11 +583,11 @@ __global__ __launch_bounds__(BX * TBY) void k_residual19s(const T* __restrict__ 
 template <typename T, typename TO, int ORDER, bool ZU>
 __global__ __launch_bounds__(512) void k_residual(const T* __restrict__ X, const T* __restrict__ F,
                                                   TO* __restrict__ R, Geom G, T ih2,
-                                                  double* __restrict__ partial) {
+                                                  double* __restrict__ partial, int mbase) {
   constexpr int C = ORDER == 2 ? 2 : 4;
   int bx, by, bz;
   xcd_block(bx, by, bz);
-  const int m = G.mlo() + bx * BX + (int)threadIdx.x;
+  const int m = mbase + bx * BX + (int)threadIdx.x;
   const int b = G.g + by * (int)blockDim.y + (int)threadIdx.y;  // launched with 4 or 8 rows per block
   const int last = G.g + G.n - 2;
   double acc = 0.0;
@@ -1015,7 +1062,9 @@ __global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ Ec, G
 }
 
 // Four-colour (19-point hierarchy) prolongation: a thread owns the four fine
-// nodes 4m + q of compact column m in row b and marches fine planes; the
+// nodes 4m + q of compact column m in row b (threads numbered over the
+// level's (column, row) pairs, so no wavefront idles on a short last block
+// of columns) and marches fine planes; the
 // coarse values it needs on a coarse plane (interpolated along x, and along
 // y when the fine row is odd) are formed once per coarse plane and kept for
 // the two or three fine planes that use them.
@@ -1023,10 +1072,13 @@ template <typename T, bool SKIP3>
 __global__ __launch_bounds__(256) void k_prolong4(const T* __restrict__ Ec, Geom Gc, T* __restrict__ Xf, Geom Gf) {
   int bx, by, bz;
   xcd_block(bx, by, bz);
-  const int m = Gf.mlo() + bx * BX + (int)threadIdx.x;
-  const int b = Gf.g + by * BY + (int)threadIdx.y;
+  // lanes numbered over (compact column, row) pairs of the fine unknowns
+  const int mc = Gf.mhi() - Gf.mlo() + 1;
+  const int fi = bx * 256 + (int)threadIdx.x;
+  if (fi >= mc * (Gf.n - 1)) return;
+  const int m = Gf.mlo() + fi % mc;
+  const int b = Gf.g + fi / mc;
   const int last = Gf.g + Gf.n - 2;
-  if (m > Gf.mhi() || b > last) return;
   const int sh = Gf.g - 1;
   const int kz = planes_per_block(Gf);
   const int k0 = Gf.g + bz * kz;
@@ -1235,10 +1287,13 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_add_corr(double* __restrict__ X, const T* __restrict__ E, Geom G) {
   int bx, by, bz;
   xcd_block(bx, by, bz);
-  const int m = G.mlo() + bx * BX + (int)threadIdx.x;
-  const int b = G.g + by * BY + (int)threadIdx.y;
+  // threads numbered over the level's (compact column, row) pairs
+  const int mc = G.mhi() - G.mlo() + 1;
+  const int fi = bx * 256 + (int)threadIdx.x;
+  if (fi >= mc * (G.n - 1)) return;
+  const int m = G.mlo() + fi % mc;
+  const int b = G.g + fi / mc;
   const int last = G.g + G.n - 2;
-  if (m > G.mhi() || b > last) return;
   const int kz = planes_per_block(G);
   const int k1 = min(G.g + bz * kz + kz - 1, last);
   for (int k = G.g + bz * kz; k <= k1; ++k)
@@ -1649,7 +1704,7 @@ static void residual_t(const T* phi, const T* f, TO* r, const Geom& G, int order
   const T ih2 = (T)(1.0 / (G.h * G.h));
   if (order == 2) {
     if (zu)
-      k_residual<T, TO, 2, true><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial);
+      k_residual<T, TO, 2, true><<<grid, blk, 0, st>>>(phi, f, r, G, ih2, partial, G.mlo());
     else if (colour == 0)
       residual7_col<T, TO, 0>(phi, f, r, G, ih2, partial, st);
     else if (colour == 1)
@@ -1657,16 +1712,27 @@ static void residual_t(const T* phi, const T* f, TO* r, const Geom& G, int order
     else
       residual7_col<T, TO, -1>(phi, f, r, G, ih2, partial, st);
   } else {
-    // both variants launch on the staged grid so that partial-sum counts agree
+    // both variants launch on the staged grid (and the column-0 kernel) so
+    // that partial-sum counts agree
     const dim3 sg = staged_grid(G), sb(BX, TBY);
+    const int mb = staged_mbase(G);
     if (zu)
-      k_residual<T, TO, 6, true><<<sg, sb, 0, st>>>(phi, f, r, G, ih2, partial);
+      k_residual<T, TO, 6, true><<<sg, sb, 0, st>>>(phi, f, r, G, ih2, partial, mb);
     else
-      k_residual19s<T, TO><<<sg, sb, 0, st>>>(phi, f, r, G, ih2, partial);
+      k_residual19s<T, TO><<<sg, sb, 0, st>>>(phi, f, r, G, ih2, partial, mb);
+    if (staged_col0(G)) {
+      const unsigned nb0 = col0_blocks(G);
+      if (zu)
+        k_res19_col0<T, TO, true><<<nb0, 256, 0, st>>>(phi, f, r, G, ih2, partial, nblocks(sg));
+      else
+        k_res19_col0<T, TO, false><<<nb0, 256, 0, st>>>(phi, f, r, G, ih2, partial, nblocks(sg));
+    }
   }
 }
 
-int residual_blocks(const Geom& G) { return (int)nblocks(G.C == 4 ? staged_grid(G) : col_grid(G)); }
+int residual_blocks(const Geom& G) {
+  return G.C == 4 ? (int)(nblocks(staged_grid(G)) + col0_blocks(G)) : (int)nblocks(col_grid(G));
+}
 
 void residual(const void* phi, const void* f, bool in_f32, void* r_out, bool out_f32, const Geom& G, int order,
               bool zu, double* partial, hipStream_t st, int colour) {
@@ -1733,16 +1799,19 @@ void prolong_add(const void* e_coarse, const Geom& Gc, void* phi_fine, const Geo
     return;
   }
   if (Gf.C == 4) {
+    const int mc = Gf.mhi() - Gf.mlo() + 1, E = Gf.n - 1;
+    const int kz = kz_for(Gf);
+    const dim3 g4((mc * E + 255) / 256, 1, (E + kz - 1) / kz);
     if (f32) {
       if (c0only)
-        k_prolong4<float, true><<<grid, blk, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
+        k_prolong4<float, true><<<g4, 256, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
       else
-        k_prolong4<float, false><<<grid, blk, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
+        k_prolong4<float, false><<<g4, 256, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
     } else {
       if (c0only)
-        k_prolong4<double, true><<<grid, blk, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
+        k_prolong4<double, true><<<g4, 256, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
       else
-        k_prolong4<double, false><<<grid, blk, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
+        k_prolong4<double, false><<<g4, 256, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
     }
     return;
   }
@@ -1764,9 +1833,9 @@ void coarse_solve(const double* inv, const void* f, void* phi, bool f32, const G
 
 void add_correction(double* phi, const void* e, bool e_f32, const Geom& G, hipStream_t st) {
   if (e_f32)
-    k_add_corr<float><<<col_grid(G), dim3(BX, BY), 0, st>>>(phi, (const float*)e, G);
+    k_add_corr<float><<<flat_grid(G), 256, 0, st>>>(phi, (const float*)e, G);
   else
-    k_add_corr<double><<<col_grid(G), dim3(BX, BY), 0, st>>>(phi, (const double*)e, G);
+    k_add_corr<double><<<flat_grid(G), 256, 0, st>>>(phi, (const double*)e, G);
 }
 
 void dense_to_split(const double* dense, void* split, bool f32, const Geom& G, hipStream_t st) {
