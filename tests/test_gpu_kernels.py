@@ -81,6 +81,33 @@ def test_four_colour_sweep(n, forward):
     assert rel_max(host(t), ref) < KTOL
 
 
+def test_four_colour_pass_and_residual_at_511():
+    """The 512-interval level in the launch configuration of the benchmark
+    (two FP64 compact columns per lane, 16-plane runs, in-block neighbours
+    from LDS; residual blocks from compact column 1 plus the column-0 kernel):
+    one forward four-colour sweep and the residual with its norm, element by
+    element against the oracle."""
+    n, g = 512, 3
+    say(f"4-colour sweep and residual at n={n}")
+    plan = pg.Plan(pg.cart_grid(n, ghost=g), pg.options("mg", order=6, lmax=-1))
+    phi, rho = random_cart(n, g, 23)
+    t = dev(phi)
+    r = dev(rho)
+    plan.smooth(r, t, sweeps=1, forward=True)
+    got = host(t)
+    say("  oracle sweep")
+    ref = OS.smooth(phi, rho, n, 1.0 / n, 6, g, forward=True)
+    assert rel_max(got, ref) < KTOL
+    del phi, got
+    res = torch.zeros_like(t)
+    n2 = plan.residual(r, t, res)
+    say("  oracle residual")
+    rref = OO.residual(ref, rho, n, 1.0 / n, 6, g)
+    s = slice(g, g + n - 1)
+    assert rel_max(host(res)[s, s, s], rref) < KTOL
+    assert n2 == pytest.approx(float(np.sum(rref * rref)), rel=1e-12)
+
+
 @pytest.mark.parametrize("order,n", [(2, 16), (2, 64), (2, 96), (6, 16), (6, 64), (6, 128)])
 def test_restrict_and_prolong(order, n):
     """Full weighting and trilinear prolongation on the two-colour (7-point)
