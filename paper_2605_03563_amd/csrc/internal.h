@@ -186,6 +186,8 @@ void finish_sum(const double* partial, int nb, int nslots, Scalars* scal, int ds
 // the preconditioned residual z, which has the opposite sign).
 void cg_direction_apply(const double* r, const double* p_old, double* p_new, double* q, const Geom& G,
                         int order, const Scalars* scal, double* partial, hipStream_t st, double sr = 1.0);
+// partial sums cg_direction_apply writes
+int cg_dir_blocks(const Geom& G, int order);
 // partial sums of -(r . z) over the unknowns (the PCG inner product)
 void pcg_dot(const double* r, const double* z, const Geom& G, double* partial, hipStream_t st);
 // 7-point FP64 Gauss-Seidel pass of one colour that also writes the blocks'

@@ -1323,7 +1323,7 @@ int solve_cart(poisson_plan_s* P, const double* rho, double* phi, double tol, po
     double* pnew = P->cp1;
     while (!conv && it < o.max_iter) {
       cg_direction_apply(P->cz, pold, pnew, P->cq, G, P->order, P->scal, P->partial, st, -1.0);
-      cg_scalars(P->partial, cb, P->scal, 0, st);
+      cg_scalars(P->partial, cg_dir_blocks(G, P->order), P->scal, 0, st);
       cg_update(P->phi64, P->cr, pnew, P->cq, G, P->scal, P->partial, st);
       finish_sum(P->partial, cb, 1, P->scal, kRes2, st);
       cg_scalars(P->partial, pcg_precondition(P, st), P->scal, 1, st);
@@ -1352,7 +1352,7 @@ int solve_cart(poisson_plan_s* P, const double* rho, double* phi, double tol, po
     double* pnew = P->cp1;
     while (!conv && it < o.max_iter) {
       cg_direction_apply(P->cr, pold, pnew, P->cq, G, P->order, P->scal, P->partial, st);
-      cg_scalars(P->partial, cb, P->scal, 0, st);
+      cg_scalars(P->partial, cg_dir_blocks(G, P->order), P->scal, 0, st);
       cg_update(P->phi64, P->cr, pnew, P->cq, G, P->scal, P->partial, st);
       cg_scalars(P->partial, cb, P->scal, 1, st);
       std::swap(pold, pnew);
