@@ -780,7 +780,7 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ Rf, Geom
   Fc[Gc.at(A, B, K)] = s;
 }
 
-// Full weighting on the colour-split layout, marching along z.  A thread
+// Full weighting on the two-colour layout, marching along z.  A thread
 // owns one fine compact column m of the fine rows 2B-sh-1 .. 2B-sh+1 of one
 // coarse row B (sh = g - 1; coarse node A sits on fine node 2A - sh) and the
 // coarse planes of its run.  Per fine row and plane it loads the C values of
@@ -788,10 +788,8 @@ __global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ Rf, Geom
 // and forms the x-weighted sums at the coarse positions of the column (q even)
 // with the left column's last value from the neighbouring lane; the y weights
 // combine its three rows, and the z weights combine consecutive fine planes,
-// the last of one coarse plane being the first of the next.  SKIPLAST: the
-// residuals of colour C-1 vanish (a Gauss-Seidel pass over that colour came
-// last) and are not loaded.
-template <typename T, int C, bool SKIPLAST>
+// the last of one coarse plane being the first of the next.
+template <typename T, int C>
 __global__ __launch_bounds__(256) void k_restrict_z(const T* __restrict__ Rf, Geom Gf, T* __restrict__ Fc, Geom Gc) {
   int bx, by, bz;
   xcd_block(bx, by, bz);
@@ -820,12 +818,12 @@ __global__ __launch_bounds__(256) void k_restrict_z(const T* __restrict__ Rf, Ge
 #pragma unroll
     for (int q = 0; q < C; ++q) {
       const int col = (q + sft) & (C - 1);
-      v[q] = (SKIPLAST && col == C - 1) ? (T)0 : Rf[(long long)col * Gf.cs + ro + mm];
+      v[q] = Rf[(long long)col * Gf.cs + ro + mm];
     }
     T left = __shfl_up(v[C - 1], 1, 64);
     if (lane == 0) {
       const int col = (C - 1 + sft) & (C - 1);
-      left = (SKIPLAST && col == C - 1) ? (T)0 : Rf[(long long)col * Gf.cs + ro + mm - 1];
+      left = Rf[(long long)col * Gf.cs + ro + mm - 1];
     }
 #pragma unroll
     for (int q = 0; q < C; q += 2) rx[q / 2] = q4 * (q == 0 ? left : v[q - 1]) + h2 * v[q] + q4 * v[q + 1];
@@ -855,6 +853,92 @@ __global__ __launch_bounds__(256) void k_restrict_z(const T* __restrict__ Rf, Ge
     }
 #pragma unroll
     for (int i = 0; i < NQ; ++i) prev[i] = nxt[i];
+  }
+}
+
+// Full weighting on the four-colour levels (three ghost layers).  A lane
+// owns CPL consecutive compact columns m0 .. m0+CPL-1 (groups aligned to
+// CPL, 16-byte loads) of the fine rows 2B-3 .. 2B-1 of one coarse row B, and
+// the coarse planes of its run; lanes are numbered over (column group, coarse
+// row) pairs.  Per fine row and plane it loads the four positions of its
+// columns (position q of a row with colour shift s lives in colour array
+// (q + s) mod 4) and forms the x-weighted sums at the coarse positions q = 0
+// and 2 of each column, the value left of the first column coming from the
+// previous lane when it holds the previous group of the same row, and loaded
+// otherwise; y and z weights as in the two-colour kernel.  SKIPLAST: the
+// residuals of colour 3 vanish (a Gauss-Seidel pass over that colour came
+// last) and are not loaded.
+template <typename T, int CPL, bool SKIPLAST>
+__global__ __launch_bounds__(256) void k_restrict4(const T* __restrict__ Rf, Geom Gf, T* __restrict__ Fc, Geom Gc) {
+  typedef typename VecOf<T, CPL>::type V;
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  constexpr int sh = 2;
+  constexpr int NO = 2 * CPL;  // coarse positions per lane
+  const int Alo = Gc.g, Ahi = Gc.g + Gc.n - 2;
+  const int gf = ((2 * Alo - sh) >> 2) / CPL;
+  const int ngr = ((2 * Ahi - sh) >> 2) / CPL - gf + 1;
+  const int nB = Ahi - Alo + 1;
+  const int fi = bx * 256 + (int)threadIdx.x;
+  const bool live = fi < ngr * nB;
+  const int fl = live ? fi : ngr * nB - 1;  // idle lanes mirror the last pair (loads stay in the array)
+  const int gp = fl % ngr;
+  const int B = Alo + fl / ngr;
+  const int m0 = (gf + gp) * CPL;
+  const int kz = (Gc.n - 1 + (int)gridDim.z - 1) / (int)gridDim.z;
+  const int K0 = Alo + bz * kz;
+  const int K1 = min(K0 + kz - 1, Ahi);
+  const long long fplane = (long long)Gf.M * Gf.W;
+  const int b = 2 * B - sh;
+  const T q4 = (T)0.25, h2 = (T)0.5;
+  const bool left_lane = gp > 0 && (threadIdx.x & 63) > 0;
+  const bool left_load = !left_lane && m0 >= 1;
+  // x-weighted sums at the lane's coarse positions of fine row j, plane p
+  auto xrow = [&](int j, int p, T* rx) {
+    const int sft = (j + p + Gf.off) & 3;
+    const long long ro = (long long)p * fplane + (long long)j * Gf.W + m0;
+    V v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int col = (q + sft) & 3;
+      v[q] = (SKIPLAST && col == 3) ? V{} : *reinterpret_cast<const V*>(Rf + (long long)col * Gf.cs + ro);
+    }
+    T left = __shfl_up(v[3][CPL - 1], 1, 64);
+    if (!left_lane) {
+      const int col = (3 + sft) & 3;
+      left = (left_load && !(SKIPLAST && col == 3)) ? Rf[(long long)col * Gf.cs + ro - 1] : (T)0;
+    }
+#pragma unroll
+    for (int jj = 0; jj < CPL; ++jj) {
+      const T l = jj == 0 ? left : v[3][jj - 1];
+      rx[2 * jj] = q4 * l + h2 * v[0][jj] + q4 * v[1][jj];
+      rx[2 * jj + 1] = q4 * v[1][jj] + h2 * v[2][jj] + q4 * v[3][jj];
+    }
+  };
+  auto yplane = [&](int p, T* ry) {
+    T r0[NO], r1[NO], r2[NO];
+    xrow(b - 1, p, r0);
+    xrow(b, p, r1);
+    xrow(b + 1, p, r2);
+#pragma unroll
+    for (int i = 0; i < NO; ++i) ry[i] = q4 * r0[i] + h2 * r1[i] + q4 * r2[i];
+  };
+  if (K0 > K1) return;
+  T prev[NO];
+  yplane(2 * K0 - sh - 1, prev);
+  for (int K = K0; K <= K1; ++K) {
+    T mid[NO], nxt[NO];
+    yplane(2 * K - sh, mid);
+    yplane(2 * K - sh + 1, nxt);
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < NO; ++i) {
+        const int A = (4 * m0 + 2 * i + sh) / 2;
+        if (A >= Alo && A <= Ahi) Fc[Gc.at(A, B, K)] = q4 * prev[i] + h2 * mid[i] + q4 * nxt[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < NO; ++i) prev[i] = nxt[i];
   }
 }
 
@@ -1061,55 +1145,68 @@ __global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ Ec, G
   }
 }
 
-// Four-colour (19-point hierarchy) prolongation: a thread owns the four fine
-// nodes 4m + q of compact column m in row b (threads numbered over the
-// level's (column, row) pairs, so no wavefront idles on a short last block
-// of columns) and marches fine planes; the
-// coarse values it needs on a coarse plane (interpolated along x, and along
-// y when the fine row is odd) are formed once per coarse plane and kept for
-// the two or three fine planes that use them.
-template <typename T, bool SKIP3>
+// Four-colour (19-point hierarchy, three ghost layers) prolongation: a lane
+// owns CPL consecutive compact columns m0 .. m0+CPL-1 of one fine row (groups
+// aligned to CPL over the columns 0 .. mhi, lanes numbered over (group, row)
+// pairs) and marches fine planes.  Its 4 CPL fine nodes 4 m0 + p sit at
+// coarse x-index 2 m0 + ((p - 2) >> 1) + 2, halfway to the next coarse node
+// when p is odd, so one coarse row of a coarse plane contributes the 2 CPL + 1
+// consecutive coarse nodes from 2 m0 + 1; the interpolated values of a coarse
+// plane (along x, and along y when the fine row is odd) are formed once and
+// kept for the two or three fine planes that use them.  The correction is a
+// 16-byte read-modify-write per colour array; nodes outside the unknowns are
+// written back unchanged.  SKIP3: colour 3 is not corrected (the following
+// Gauss-Seidel pass over colour 3 reads no colour-3 value and overwrites it).
+template <typename T, int CPL, bool SKIP3>
 __global__ __launch_bounds__(256) void k_prolong4(const T* __restrict__ Ec, Geom Gc, T* __restrict__ Xf, Geom Gf) {
+  typedef typename VecOf<T, CPL>::type V;
   int bx, by, bz;
   xcd_block(bx, by, bz);
-  // lanes numbered over (compact column, row) pairs of the fine unknowns
-  const int mc = Gf.mhi() - Gf.mlo() + 1;
+  constexpr int sh = 2;
+  constexpr int NP = 4 * CPL;      // fine nodes of the lane's columns
+  constexpr int NC = 2 * CPL + 1;  // coarse nodes of one coarse row they use
+  const int ngr = col_groups<CPL>(Gf);
+  const int E = Gf.n - 1;
   const int fi = bx * 256 + (int)threadIdx.x;
-  if (fi >= mc * (Gf.n - 1)) return;
-  const int m = Gf.mlo() + fi % mc;
-  const int b = Gf.g + fi / mc;
+  if (fi >= ngr * E) return;
+  const int m0 = (fi % ngr) * CPL;
+  const int b = Gf.g + fi / ngr;
   const int last = Gf.g + Gf.n - 2;
-  const int sh = Gf.g - 1;
   const int kz = planes_per_block(Gf);
   const int k0 = Gf.g + bz * kz;
   const int k1 = min(k0 + kz - 1, last);
   const int j = b - sh;
   const int J = (j >> 1) + sh, oj = j & 1;
   const T half = (T)0.5;
-  bool in[4];
+  bool in[NP];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) in[q] = Gf.inner(4 * m + q);
+  for (int p = 0; p < NP; ++p) in[p] = Gf.inner(4 * m0 + p);
+  const int I0 = 2 * m0 + ((0 - sh) >> 1) + sh;
   auto plane_vals = [&](int L, T* v) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = (T)0;
+    for (int p = 0; p < NP; ++p) v[p] = (T)0;
     for (int db = 0; db <= oj; ++db) {
       const int Bc = J + db;
       const int sc = Bc + L + Gc.off;
       const long long crow = Gc.row(Bc, L);
       const T wy = oj ? half : (T)1;
+      T c[NC];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (!in[q]) continue;
-        const int i = 4 * m + q - sh;
-        const int I = (i >> 1) + sh;
-        T t = Ec[(long long)((I + sc) & 3) * Gc.cs + crow + (I >> 2)];
-        if (i & 1) t = half * (t + Ec[(long long)((I + 1 + sc) & 3) * Gc.cs + crow + ((I + 1) >> 2)]);
-        v[q] += wy * t;
+      for (int t = 0; t < NC; ++t) {
+        const int I = min(I0 + t, Gc.M - 1);  // nodes past the array only feed non-unknowns
+        c[t] = Ec[(long long)((I + sc) & 3) * Gc.cs + crow + (I >> 2)];
+      }
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const int t = ((p - sh) >> 1) - ((0 - sh) >> 1);
+        T x = c[t];
+        if ((p - sh) & 1) x = half * (x + c[t + 1]);
+        v[p] += wy * x;
       }
     }
   };
   int Lc = ((k0 - sh) >> 1) + sh;
-  T cv[4], nv[4];
+  T cv[NP], nv[NP];
   plane_vals(Lc, cv);
   plane_vals(Lc + 1, nv);
   for (int k = k0; k <= k1; ++k) {
@@ -1117,17 +1214,24 @@ __global__ __launch_bounds__(256) void k_prolong4(const T* __restrict__ Ec, Geom
     const int L = (l >> 1) + sh;
     if (L != Lc) {  // one coarse plane further
 #pragma unroll
-      for (int q = 0; q < 4; ++q) cv[q] = nv[q];
+      for (int p = 0; p < NP; ++p) cv[p] = nv[p];
       Lc = L;
       plane_vals(L + 1, nv);
     }
     const int s = (b + k + Gf.off) & 3;
-    const long long row = Gf.row(b, k);
+    const long long row = Gf.row(b, k) + m0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      if (!in[q] || (SKIP3 && ((q + s) & 3) == 3)) continue;
-      const T e = (l & 1) ? half * (cv[q] + nv[q]) : cv[q];
-      Xf[(long long)((q + s) & 3) * Gf.cs + row + m] += e;
+      const int col = (q + s) & 3;
+      if (SKIP3 && col == 3) continue;
+      V* x = reinterpret_cast<V*>(Xf + (long long)col * Gf.cs + row);
+      V v = *x;
+#pragma unroll
+      for (int jj = 0; jj < CPL; ++jj) {
+        const int p = 4 * jj + q;
+        if (in[p]) v[jj] += (l & 1) ? half * (cv[p] + nv[p]) : cv[p];
+      }
+      *x = v;
     }
   }
 }
@@ -1880,24 +1984,30 @@ void resrestrict(const void* phi, const void* f, bool f32, const Geom& Gf, void*
 void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom& Gc, bool f32, hipStream_t st,
                  bool last_zero) {
   const int sh = Gf.g - 1, nc = Gc.n, C = Gf.C;
+  if (C == 4) {  // four colours, three ghost layers
+    const int kzc = nc >= 32 ? 4 : 1;
+    auto grid = [&](int cpl) {
+      const long long groups = ((2 * (Gc.g + nc - 2) - sh) >> 2) / cpl - ((2 * Gc.g - sh) >> 2) / cpl + 1;
+      return dim3((unsigned)((groups * (nc - 1) + 255) / 256), 1, (nc - 1 + kzc - 1) / kzc);
+    };
+#define PSN_R4(T, CPL, SK) \
+  k_restrict4<T, CPL, SK><<<grid(CPL), 256, 0, st>>>((const T*)r_fine, Gf, (T*)f_coarse, Gc)
+    if (f32) {
+      if (last_zero) PSN_R4(float, 4, true); else PSN_R4(float, 4, false);
+    } else {
+      if (last_zero) PSN_R4(double, 2, true); else PSN_R4(double, 2, false);
+    }
+#undef PSN_R4
+    return;
+  }
+  // two colours: every residual is read
   const int mcols = (2 * (Gc.g + nc - 2) - sh) / C - (2 * Gc.g - sh) / C + 1;
   const int kzc = nc >= 128 ? 8 : (nc >= 32 ? 4 : 1);
   const dim3 grid((mcols + 63) / 64, (nc - 1 + 3) / 4, (nc - 1 + kzc - 1) / kzc), blk(64, 4);
-#define PSN_RZ(T, CC, SK) \
-  k_restrict_z<T, CC, SK><<<grid, blk, 0, st>>>((const T*)r_fine, Gf, (T*)f_coarse, Gc)
-  if (C == 4) {
-    if (f32) {
-      if (last_zero) PSN_RZ(float, 4, true); else PSN_RZ(float, 4, false);
-    } else {
-      if (last_zero) PSN_RZ(double, 4, true); else PSN_RZ(double, 4, false);
-    }
-  } else {  // two colours: every residual is read
-    if (f32)
-      PSN_RZ(float, 2, false);
-    else
-      PSN_RZ(double, 2, false);
-  }
-#undef PSN_RZ
+  if (f32)
+    k_restrict_z<float, 2><<<grid, blk, 0, st>>>((const float*)r_fine, Gf, (float*)f_coarse, Gc);
+  else
+    k_restrict_z<double, 2><<<grid, blk, 0, st>>>((const double*)r_fine, Gf, (double*)f_coarse, Gc);
 }
 
 void prolong_add(const void* e_coarse, const Geom& Gc, void* phi_fine, const Geom& Gf, bool f32,
@@ -1918,20 +2028,22 @@ void prolong_add(const void* e_coarse, const Geom& Gc, void* phi_fine, const Geo
     }
     return;
   }
-  if (Gf.C == 4) {
-    const int mc = Gf.mhi() - Gf.mlo() + 1, E = Gf.n - 1;
-    const int kz = kz_for(Gf);
-    const dim3 g4((mc * E + 255) / 256, 1, (E + kz - 1) / kz);
+  if (Gf.C == 4) {  // four colours, three ghost layers
+    const int E = Gf.n - 1;
+    const int kz = Gf.n >= 128 ? 4 : 1;
+    auto grid = [&](int groups) { return dim3((unsigned)(((long long)groups * E + 255) / 256), 1, (E + kz - 1) / kz); };
     if (f32) {
+      const dim3 g4 = grid(col_groups<4>(Gf));
       if (c0only)
-        k_prolong4<float, true><<<g4, 256, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
+        k_prolong4<float, 4, true><<<g4, 256, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
       else
-        k_prolong4<float, false><<<g4, 256, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
+        k_prolong4<float, 4, false><<<g4, 256, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
     } else {
+      const dim3 g4 = grid(col_groups<2>(Gf));
       if (c0only)
-        k_prolong4<double, true><<<g4, 256, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
+        k_prolong4<double, 2, true><<<g4, 256, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
       else
-        k_prolong4<double, false><<<g4, 256, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
+        k_prolong4<double, 2, false><<<g4, 256, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
     }
     return;
   }
