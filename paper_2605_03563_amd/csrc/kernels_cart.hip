@@ -546,6 +546,151 @@ __global__ __launch_bounds__(BX * TBY) void k_residual19s(const T* __restrict__ 
   }
 }
 
+// The same residual with two positions of two adjacent compact columns per
+// thread: a block of 32 x 2 x TBY threads covers 64 compact columns from
+// mbase (lanes of thread-y 0 own positions 0 and 1, of thread-y 1 positions 2
+// and 3), so the window, right-hand side and result are moved with 16-byte
+// (FP64) or 8-byte (FP32) accesses, half as many instructions as one column
+// per thread.  The pair of a lane starts at an odd compact column (mbase 1),
+// so the vector accesses are aligned to the element size only.  Tile and
+// window as in k_residual19s, the tile's columns shifted by one so that a
+// lane's pair is aligned in LDS.  Same blocks per level as the staged grid.
+constexpr int VX2 = 32;                // lanes along x, two compact columns each
+constexpr int TCOLS2 = 2 * VX2 + 4;    // 64 columns, one halo column each side, alignment pad
+template <typename T, typename TO>
+__global__ __launch_bounds__(VX2 * 2 * TBY) void k_residual19v(const T* __restrict__ X, const T* __restrict__ F,
+                                                       TO* __restrict__ R, Geom G, T ih2,
+                                                       double* __restrict__ partial, int mbase) {
+  typedef T V __attribute__((ext_vector_type(2), aligned(sizeof(T))));
+  typedef TO VO __attribute__((ext_vector_type(2), aligned(sizeof(TO))));
+  __shared__ T tile[2][TROWS][4][TCOLS2];
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int tx = threadIdx.x, pp = threadIdx.y, ty = threadIdx.z;
+  const int tid = tx + VX2 * (pp + 2 * ty);
+  const int c0 = mbase + bx * 2 * VX2;
+  const int m0 = c0 + 2 * tx;
+  const int b0 = G.g + by * TBY;
+  const int b = b0 + ty;
+  const int last = G.g + G.n - 2;
+  const int kz = planes_per_block(G);
+  const int k0 = G.g + bz * kz;
+  const int k1 = min(k0 + kz - 1, last);
+  const bool colok = m0 + 1 < G.W;
+  const bool rowok = b < G.M;
+  const long long plane = (long long)G.M * G.W;
+  const long long cb = (long long)b * G.W + m0;
+  auto loadv = [&](int bb, int kk, int mm, int q) -> V {
+    const int col = (q + bb + kk + G.off) & 3;
+    return *reinterpret_cast<const V*>(X + (long long)col * G.cs + kk * plane + (long long)bb * G.W + mm);
+  };
+  auto load1 = [&](int bb, int kk, int mm, int q) -> T {
+    const int col = (q + bb + kk + G.off) & 3;
+    return X[(long long)col * G.cs + kk * plane + (long long)bb * G.W + mm];
+  };
+  const int q0 = 2 * pp;
+  const int hb = ty < 3 ? b0 - 3 + ty : b0 + TBY + (ty - 3);
+  const int htr = ty < 3 ? ty : TBY + ty;
+  const bool hrow = ty < 6 && hb >= 0 && hb < G.M && colok;
+  const int cq = tid & 3, cside = (tid >> 2) & 1, ctr = tid >> 3;
+  const int chb = b0 - 3 + ctr, chm = cside ? c0 + 2 * VX2 : c0 - 1;
+  const int ctc = cside ? 2 * VX2 + 2 : 1;
+  const bool hcell = tid < 8 * TROWS;
+  const bool hcol = hcell && chb >= 0 && chb < G.M && chm >= 0 && chm < G.W;
+  V win[7][2];
+#pragma unroll
+  for (int d = -3; d <= 2; ++d)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) win[d + 3][j] = (colok && rowok) ? loadv(b, k0 + d, m0, q0 + j) : V{};
+  const bool live = b <= last && colok;
+  V hr[2], fq[2], wn[2];
+  T hc;
+  auto fetch = [&](int k) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) hr[j] = hrow ? loadv(hb, k, m0, q0 + j) : V{};
+    hc = hcol ? load1(chb, k, chm, cq) : (T)0;
+    const int s = (b + k + G.off) & 3;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      fq[j] = live ? *reinterpret_cast<const V*>(F + (long long)((q0 + j + s) & 3) * G.cs + k * plane + cb) : V{};
+#pragma unroll
+    for (int j = 0; j < 2; ++j) wn[j] = (colok && rowok) ? loadv(b, k + 3, m0, q0 + j) : V{};
+  };
+  fetch(k0);
+  double acc = 0.0;
+  for (int k = k0; k <= k1; ++k) {
+    const int buf = k & 1;
+    V fc[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      win[6][j] = wn[j];
+      fc[j] = fq[j];
+      tile[buf][ty + 3][q0 + j][2 * tx + 2] = win[3][j][0];
+      tile[buf][ty + 3][q0 + j][2 * tx + 3] = win[3][j][1];
+    }
+    if (ty < 6) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        tile[buf][htr][q0 + j][2 * tx + 2] = hr[j][0];
+        tile[buf][htr][q0 + j][2 * tx + 3] = hr[j][1];
+      }
+    }
+    if (hcell) tile[buf][ctr][cq][ctc] = hc;
+    __syncthreads();
+    if (k < k1) fetch(k + 1);
+    const int s = (b + k + G.off) & 3;
+    if (live) {
+      const int r0 = ty + 3;
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int q = q0 + j;
+        T res[2];
+        bool ok[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int a = 4 * (m0 + i) + q;
+          const int tc = 2 * tx + 2 + i;
+          ok[i] = G.inner(a);
+          T sd[3];
+#pragma unroll
+          for (int d = 1; d <= 3; ++d) {
+            const int qp = q + d, qm = q - d;
+            const T xp = tile[buf][r0][qp & 3][tc + (qp >> 2)];
+            const T xm = tile[buf][r0][qm & 3][tc + (qm >> 2)];
+            sd[d - 1] = xp + xm + tile[buf][r0 + d][q][tc] + tile[buf][r0 - d][q][tc] + win[3 + d][j][i] +
+                        win[3 - d][j][i];
+          }
+          const T lap = ((T)(3.0 * kC0) * win[3][j][i] + (T)kC1 * sd[0] + (T)kC2 * sd[1] + (T)kC3 * sd[2]) * ih2;
+          res[i] = fc[j][i] - lap;
+        }
+        const long long idx = (long long)((q + s) & 3) * G.cs + k * plane + cb;
+        if (R) {
+          if (ok[0] && ok[1]) {
+            VO o;
+            o[0] = (TO)res[0];
+            o[1] = (TO)res[1];
+            *reinterpret_cast<VO*>(R + idx) = o;
+          } else {
+            if (ok[0]) R[idx] = (TO)res[0];
+            if (ok[1]) R[idx + 1] = (TO)res[1];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          if (ok[i]) acc += (double)res[i] * (double)res[i];
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < 6; ++d)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) win[d][j] = win[d + 1][j];
+  }
+  if (partial) {
+    const double sum = block_sum(acc);
+    if (tid == 0) partial[linear_block()] = sum;
+  }
+}
+
 // Residuals of the unknowns in compact column 0 of a four-colour level (node
 // a = 3, the blocks of the staged kernels start at column 1): one thread per
 // (row, plane); partial sums of r^2 per block go to partial[pbase + block].
@@ -1940,9 +2085,17 @@ static void residual_t(const T* phi, const T* f, TO* r, const Geom& G, int order
     // that partial-sum counts agree
     const dim3 sg = staged_grid(G), sb(BX, TBY);
     const int mb = staged_mbase(G);
+    // FP32 results on the large levels: two columns per thread (the FP64
+    // form needs 194 registers and gains nothing); BX = 2 VX2, so the block
+    // count equals the staged grid's
+    bool two_col = false;
+    if constexpr (sizeof(TO) == 4) two_col = !zu && G.n >= 256 && mb == 1;
     if (zu)
       k_residual<T, TO, 6, true><<<sg, sb, 0, st>>>(phi, f, r, G, ih2, partial, mb);
-    else
+    else if (two_col) {
+      if constexpr (sizeof(TO) == 4)
+        k_residual19v<T, TO><<<sg, dim3(VX2, 2, TBY), 0, st>>>(phi, f, r, G, ih2, partial, mb);
+    } else
       k_residual19s<T, TO><<<sg, sb, 0, st>>>(phi, f, r, G, ih2, partial, mb);
     if (staged_col0(G)) {
       const unsigned nb0 = col0_blocks(G);

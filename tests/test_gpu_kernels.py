@@ -108,11 +108,12 @@ def test_four_colour_pass_and_residual_at_511():
     assert n2 == pytest.approx(float(np.sum(rref * rref)), rel=1e-12)
 
 
-@pytest.mark.parametrize("order,n", [(2, 16), (2, 64), (2, 96), (6, 16), (6, 64), (6, 128)])
+@pytest.mark.parametrize("order,n", [(2, 16), (2, 64), (2, 96), (6, 16), (6, 64), (6, 96), (6, 128), (6, 256)])
 def test_restrict_and_prolong(order, n):
     """Full weighting and trilinear prolongation on the two-colour (7-point)
     and four-colour (19-point) level layouts; n = 96 (coarsest 6) has ragged
-    tiles, n = 128 the plane runs of the large levels."""
+    tiles (on the four-colour levels a last column group with one column of
+    unknowns), n = 128 and 256 the plane runs of the large levels."""
     say(f"transfers order={order} n={n}")
     g = 1 if order == 2 else 3
     plan = pg.Plan(pg.cart_grid(n, ghost=g), pg.options("mg", order=order, lmax=-1, coarsest=6 if n == 96 else 8))
@@ -127,8 +128,8 @@ def test_restrict_and_prolong(order, n):
     assert rel_max(host(tf), fine + OS.prolong(ec)) < KTOL
 
 
-@pytest.mark.parametrize("order,n", [(2, 32), (2, 64), (2, 96), (2, 128), (2, 256), (6, 32), (6, 128),
-                                     (6, 256)])
+@pytest.mark.parametrize("order,n", [(2, 32), (2, 64), (2, 96), (2, 128), (2, 256), (6, 32), (6, 96),
+                                     (6, 128), (6, 256)])
 def test_one_vcycle_matches_reference_cycle(order, n):
     """One V(2,2) cycle against the oracle's cycle; n = 96 has ragged tiles,
     n = 128 and 256 take the large-level shapes of the fused residual and
