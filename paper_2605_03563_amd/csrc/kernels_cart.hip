@@ -904,27 +904,6 @@ __global__ __launch_bounds__(256) void k_residual7(const T* __restrict__ X, cons
 }
 
 // ---------------------------------------------------------------- transfers
-// coarse f(A,B,K) = sum over the 27 fine nodes around fine node 2I of
-// (1/4)[1 2 1] weights per axis; fine array index of coarse array index A is
-// 2A - (g-1).
-template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(const T* __restrict__ Rf, Geom Gf, T* __restrict__ Fc,
-                                                  Geom Gc) {
-  const int A = blockIdx.x * BX + threadIdx.x;
-  const int B = blockIdx.y * BY + threadIdx.y;
-  const int K = blockIdx.z;
-  if (A >= Gc.M || B >= Gc.M || !Gc.inner(A) || !Gc.inner(B) || !Gc.inner(K)) return;
-  const int sh = Gf.g - 1;
-  const int a0 = 2 * A - sh, b0 = 2 * B - sh, k0 = 2 * K - sh;
-  const T w[3] = {(T)0.25, (T)0.5, (T)0.25};
-  T s = (T)0;
-  for (int dk = -1; dk <= 1; ++dk)
-    for (int db = -1; db <= 1; ++db)
-      for (int da = -1; da <= 1; ++da)
-        s += w[dk + 1] * w[db + 1] * w[da + 1] * Rf[Gf.at(a0 + da, b0 + db, k0 + dk)];
-  Fc[Gc.at(A, B, K)] = s;
-}
-
 // Full weighting on the two-colour layout, marching along z.  A thread
 // owns one fine compact column m of the fine rows 2B-sh-1 .. 2B-sh+1 of one
 // coarse row B (sh = g - 1; coarse node A sits on fine node 2A - sh) and the
@@ -1235,59 +1214,6 @@ static void resrestrict7_t(const T* phi, const T* f, const Geom& Gf, T* fc, cons
     resrestrict7_go<T, 64, 1, 4>(phi, f, Gf, fc, Gc, r0, st);
   else
     resrestrict7_go<T, 128, 2, 4>(phi, f, Gf, fc, Gc, r0, st);
-}
-
-// phi_fine += P e_coarse, P = 8 R^T (trilinear interpolation).  One thread
-// handles the C fine nodes at compact column m of row (b, k), marching KZ
-// planes; fine node i takes coarse node i/2 when i is even and the mean of
-// (i-1)/2 and (i+1)/2 when odd, independently along each axis.
-template <typename T>
-__global__ __launch_bounds__(256) void k_prolong_add(const T* __restrict__ Ec, Geom Gc, T* __restrict__ Xf,
-                                                     Geom Gf) {
-  int bx, by, bz;
-  xcd_block(bx, by, bz);
-  const int m = Gf.mlo() + bx * BX + (int)threadIdx.x;
-  const int b = Gf.g + by * BY + (int)threadIdx.y;
-  const int last = Gf.g + Gf.n - 2;
-  if (m > Gf.mhi() || b > last) return;
-  const int C = Gf.C;
-  const int sh = Gf.g - 1;
-  const int kz = planes_per_block(Gf);
-  const int k1 = min(Gf.g + bz * kz + kz - 1, last);
-  const int j = b - sh;
-  const int J = (j >> 1) + sh, oj = j & 1;
-  const T half = (T)0.5;
-  for (int k = Gf.g + bz * kz; k <= k1; ++k) {
-    const int l = k - sh;
-    const int L = (l >> 1) + sh, ol = l & 1;
-    T acc[4] = {(T)0, (T)0, (T)0, (T)0};
-    for (int dk = 0; dk <= ol; ++dk)
-      for (int db = 0; db <= oj; ++db) {
-        const int Bc = J + db, Kc = L + dk;
-        const int sc = Bc + Kc + Gc.off;
-        const long long crow = Gc.row(Bc, Kc);
-        const T wyz = (oj ? half : (T)1) * (ol ? half : (T)1);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          if (q >= C) break;
-          const int a = C * m + q;
-          if (!Gf.inner(a)) continue;
-          const int i = a - sh;
-          const int I = (i >> 1) + sh;
-          T v = Ec[(long long)((I + sc) & (C - 1)) * Gc.cs + crow + (I >> Gc.lc)];
-          if (i & 1) v = half * (v + Ec[(long long)((I + 1 + sc) & (C - 1)) * Gc.cs + crow + ((I + 1) >> Gc.lc)]);
-          acc[q] += wyz * v;
-        }
-      }
-    const int s = (b + k + Gf.off) & (C - 1);
-    const long long row = Gf.row(b, k);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (q >= C) break;
-      if (!Gf.inner(C * m + q)) continue;
-      Xf[(long long)((q + s) & (C - 1)) * Gf.cs + row + m] += acc[q];
-    }
-  }
 }
 
 // Four-colour (19-point hierarchy, three ghost layers) prolongation: a lane
@@ -2165,7 +2091,9 @@ void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom&
 
 void prolong_add(const void* e_coarse, const Geom& Gc, void* phi_fine, const Geom& Gf, bool f32,
                  hipStream_t st, bool c0only) {
-  // c0only: the last colour's correction is dead (see the declaration)
+  // c0only: the last colour's correction is dead (see the declaration).
+  // Plans create two layouts only: two colours with one ghost layer (7-point)
+  // and four colours with three (19-point star).
   const dim3 grid = col_grid(Gf), blk(BX, BY);
   if (Gf.C == 2 && Gf.g == 1) {
     if (f32) {
@@ -2200,10 +2128,6 @@ void prolong_add(const void* e_coarse, const Geom& Gc, void* phi_fine, const Geo
     }
     return;
   }
-  if (f32)
-    k_prolong_add<float><<<grid, blk, 0, st>>>((const float*)e_coarse, Gc, (float*)phi_fine, Gf);
-  else
-    k_prolong_add<double><<<grid, blk, 0, st>>>((const double*)e_coarse, Gc, (double*)phi_fine, Gf);
 }
 
 void coarse_solve(const double* inv, const void* f, void* phi, bool f32, const Geom& G, hipStream_t st) {
