@@ -136,7 +136,6 @@ void merge_to_natural(const double* src_split, double* dst, long long p0, long l
                       bool unknowns_only, double scale, hipStream_t st);
 void fill_zero(void* x, bool f32, long long count, hipStream_t st);
 void zero_unknowns(void* x, bool f32, const Geom& G, hipStream_t st);
-void copy_ghosts_split(const double* src, void* dst, bool dst_f32, const Geom& G, hipStream_t st);
 
 // one colour pass of Gauss-Seidel / SOR in place (order 2: 7-point, order 6:
 // star); colours whose bit is set in zmask are read as zero (first sweep on a
@@ -292,8 +291,6 @@ long long n27_blocks(const NGeom& G);
 // sum of r^2 per block.  f32: the level is stored in FP32 (arithmetic FP64).
 void n27_residual(const void* u, const void* f, void* r, bool f32, const NGeom& G, const W4& A, bool norm,
                   double* partial, hipStream_t st);
-// u -= M r (M includes omega h^2)
-void n27_update(const void* r, void* u, bool f32, const NGeom& G, const W4& M, hipStream_t st);
 // fused Richardson step out of place: out = u - M (f - A u) at the unknowns
 // (ghost entries of out are not written)
 void n_spai_step(const void* u, const void* f, void* out, bool f32, const NGeom& G, const W4& A, const W4& M,

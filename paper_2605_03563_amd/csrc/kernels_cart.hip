@@ -1423,18 +1423,6 @@ __global__ __launch_bounds__(256) void k_merge(const double* __restrict__ src, d
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_ghost_copy(const double* __restrict__ src, T* __restrict__ dst,
-                                                    Geom G) {
-  const int a = blockIdx.x * BX + threadIdx.x;
-  const int b = blockIdx.y * BY + threadIdx.y;
-  const int k = blockIdx.z;
-  if (a >= G.M || b >= G.M) return;
-  if (G.inner(a) && G.inner(b) && G.inner(k)) return;
-  const long long i = G.at(a, b, k);
-  dst[i] = (T)src[i];
-}
-
-template <typename T>
 __global__ __launch_bounds__(256) void k_fill(T* __restrict__ x, long long count) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count;
        i += (long long)gridDim.x * blockDim.x)
@@ -1878,13 +1866,6 @@ void zero_unknowns(void* x, bool f32, const Geom& G, hipStream_t st) {
     k_zero_unknowns<float><<<col_grid(G), dim3(BX, BY), 0, st>>>((float*)x, G);
   else
     k_zero_unknowns<double><<<col_grid(G), dim3(BX, BY), 0, st>>>((double*)x, G);
-}
-
-void copy_ghosts_split(const double* src, void* dst, bool dst_f32, const Geom& G, hipStream_t st) {
-  if (dst_f32)
-    k_ghost_copy<float><<<node_grid(G.M), dim3(BX, BY), 0, st>>>(src, (float*)dst, G);
-  else
-    k_ghost_copy<double><<<node_grid(G.M), dim3(BX, BY), 0, st>>>(src, (double*)dst, G);
 }
 
 // planes per thread fixed at compile time: KZ on large levels, one on small

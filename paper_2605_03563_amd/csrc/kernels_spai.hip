@@ -48,12 +48,10 @@ __device__ inline double apply_sums(const W4& w, const Plane& m, const Plane& z,
   return w.c * z.c + w.f * (z.f + m.c + p.c) + w.e * (z.e + m.f + p.f) + w.k * (m.e + p.e);
 }
 
-// MODE 0: r = f - A u (r stored unless r == nullptr; with NORM the squares
-// summed into one partial per block).  MODE 1: u -= M r (M already holds
-// omega h^2): reads the stencil of r, writes u at the centre only.  T is the
-// storage type of the level (FP64, or FP32 on coarse levels); all arithmetic
-// is FP64.
-template <int MODE, bool NORM, typename T>
+// r = f - A u (r stored unless r == nullptr; with NORM the squares summed
+// into one partial per block).  T is the storage type of the level (FP64, or
+// FP32 on coarse levels); all arithmetic is FP64.
+template <bool NORM, typename T>
 __global__ __launch_bounds__(BX* BY) void k_n27(const T* __restrict__ src, const T* __restrict__ f,
                                                 T* __restrict__ dst, NGeom G, W4 w, double* __restrict__ partial) {
   int bx, by, bz;
@@ -71,13 +69,9 @@ __global__ __launch_bounds__(BX* BY) void k_n27(const T* __restrict__ src, const
       const long long idx = G.at(i, j, k);
       const Plane p = plane_sums(src, idx + G.P, G.W);
       const double s = apply_sums(w, m, z, p);
-      if (MODE == 0) {
-        const double r = (double)f[idx] - s;
-        if (dst) dst[idx] = (T)r;
-        if (NORM) acc += r * r;
-      } else {
-        dst[idx] = (T)((double)dst[idx] - s);
-      }
+      const double r = (double)f[idx] - s;
+      if (dst) dst[idx] = (T)r;
+      if (NORM) acc += r * r;
       m = z;
       z = p;
     }
@@ -449,23 +443,15 @@ void n27_residual(const void* u, const void* f, void* r, bool f32, const NGeom& 
   const dim3 gr = ngrid(G), bl(BX, BY);
   if (f32) {
     if (norm)
-      k_n27<0, true, float><<<gr, bl, 0, st>>>((const float*)u, (const float*)f, (float*)r, G, A, partial);
+      k_n27<true, float><<<gr, bl, 0, st>>>((const float*)u, (const float*)f, (float*)r, G, A, partial);
     else
-      k_n27<0, false, float><<<gr, bl, 0, st>>>((const float*)u, (const float*)f, (float*)r, G, A, nullptr);
+      k_n27<false, float><<<gr, bl, 0, st>>>((const float*)u, (const float*)f, (float*)r, G, A, nullptr);
   } else {
     if (norm)
-      k_n27<0, true, double><<<gr, bl, 0, st>>>((const double*)u, (const double*)f, (double*)r, G, A, partial);
+      k_n27<true, double><<<gr, bl, 0, st>>>((const double*)u, (const double*)f, (double*)r, G, A, partial);
     else
-      k_n27<0, false, double><<<gr, bl, 0, st>>>((const double*)u, (const double*)f, (double*)r, G, A, nullptr);
+      k_n27<false, double><<<gr, bl, 0, st>>>((const double*)u, (const double*)f, (double*)r, G, A, nullptr);
   }
-}
-
-void n27_update(const void* r, void* u, bool f32, const NGeom& G, const W4& M, hipStream_t st) {
-  if (f32)
-    k_n27<1, false, float><<<ngrid(G), dim3(BX, BY), 0, st>>>((const float*)r, nullptr, (float*)u, G, M, nullptr);
-  else
-    k_n27<1, false, double><<<ngrid(G), dim3(BX, BY), 0, st>>>((const double*)r, nullptr, (double*)u, G, M,
-                                                                nullptr);
 }
 
 // Tile rows FY and planes per block kz: on the 511^3 level 64 x 16 tiles
