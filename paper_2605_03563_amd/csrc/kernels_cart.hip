@@ -691,6 +691,194 @@ __global__ __launch_bounds__(VX2 * 2 * TBY) void k_residual19v(const T* __restri
   }
 }
 
+// Residual of the 19-point star fused with full weighting onto the next
+// coarser four-colour level: the coarse right-hand side without storing the
+// fine residual, the squares of the fine residuals summed per block as in
+// k_residual19s.  The block, tile and register window are those of
+// k_residual19s with one more thread row: rows b0 .. b0+7 are the block's
+// own (their residuals enter the norm) and row b0+8, the next block's first,
+// completes the three fine rows of the block's last coarse row; likewise
+// the run marches one plane past its own (b0 and the first plane of a run
+// are odd, so the block's coarse centres, on even fine rows and planes, lie
+// inside it).  Coarse node A sits on fine node 2A-2: per fine row and plane
+// a thread restricts along x at its compact column's positions 0 and 2, the
+// value left of position 0 coming from the previous lane; the first lane
+// forms the residual at position 3 of the compact column before the block
+// (a window along z kept in LDS, and the tile's halo column).  The x sums go
+// to LDS and are combined along y by the threads of the even rows one plane
+// later (after that plane's barrier), and along z in registers.  SKIPLAST:
+// the residuals of colour 3 are zero after a Gauss-Seidel pass over colour 3
+// and are restricted as zero (they still enter the norm).  Requires runs of
+// an even number of planes (levels from 128 intervals).
+constexpr int RRY = TBY + 1;        // thread rows of the fused kernel
+constexpr int RTROWS = RRY + 6;
+static_assert(BX * RRY >= 8 * RTROWS, "one halo-column cell per thread");
+
+template <typename T, bool SKIPLAST>
+__global__ __launch_bounds__(BX * RRY) void k_resrestrict19(const T* __restrict__ X, const T* __restrict__ F, Geom G,
+                                                            T ih2, T* __restrict__ Fc, Geom Gc,
+                                                            double* __restrict__ partial, int mbase) {
+  __shared__ T tile[2][RTROWS][4][TCOLS];
+  __shared__ T srx[2][RRY][2][BX];
+  __shared__ T hz[RRY][8];  // the first lane's halo window, ring over planes
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int tid = ty * BX + tx;
+  const int m0 = mbase + bx * BX;
+  const int m = m0 + tx;
+  const int b0 = G.g + by * TBY;
+  const int b = b0 + ty;
+  const int last = G.g + G.n - 2;
+  const int kz = planes_per_block(G);
+  const int k0 = G.g + bz * kz;
+  const int k1 = min(k0 + kz - 1, last);
+  const int kend = min(k1 + 1, last);
+  const bool colok = m < G.W;
+  const bool rowok = b < G.M;
+  const long long plane = (long long)G.M * G.W;
+  const long long cb = (long long)b * G.W + m;
+  auto load = [&](int bb, int kk, int mm, int q) -> T {
+    const int col = (q + bb + kk + G.off) & 3;
+    return X[(long long)col * G.cs + kk * plane + (long long)bb * G.W + mm];
+  };
+  const int hb = ty < 3 ? b0 - 3 + ty : b0 + RRY + (ty - 3);
+  const int htr = ty < 3 ? ty : RRY + ty;
+  const bool hrow = ty < 6 && hb >= 0 && hb < G.M && colok;
+  const int cq = tid & 3, cside = (tid >> 2) & 1, ctr = tid >> 3;
+  const int chb = b0 - 3 + ctr, chm = cside ? m0 + BX : m0 - 1;
+  const int ctc = cside ? BX + 1 : 0;
+  const bool hcell = tid < 8 * RTROWS;
+  const bool hcol = hcell && chb >= 0 && chb < G.M && chm >= 0 && chm < G.W;
+  // the first lane also keeps a window at position 3 of compact column m0-1
+  const int mh = m0 - 1;
+  const bool halo = tx == 0 && rowok && mh >= 0;
+  T win[7][4];
+#pragma unroll
+  for (int d = -3; d <= 2; ++d) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) win[d + 3][q] = (colok && rowok) ? load(b, k0 + d, m, q) : (T)0;
+    if (halo) hz[ty][(k0 + d) & 7] = load(b, k0 + d, mh, 3);
+  }
+  const bool live = m <= G.mhi() && b <= last;
+  const bool own = live && ty < TBY;  // the block's own rows: their residuals enter the norm
+  T hr[4], hc, fq[4], wn[4], hwn, fhn;
+  auto fetch = [&](int k) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) hr[q] = hrow ? load(hb, k, m, q) : (T)0;
+    hc = hcol ? load(chb, k, chm, cq) : (T)0;
+    const int s = (b + k + G.off) & 3;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) fq[q] = live ? F[(long long)((q + s) & 3) * G.cs + k * plane + cb] : (T)0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wn[q] = (colok && rowok) ? load(b, k + 3, m, q) : (T)0;
+    hwn = halo ? load(b, k + 3, mh, 3) : (T)0;
+    fhn = halo ? F[(long long)((3 + s) & 3) * G.cs + k * plane + (long long)b * G.W + mh] : (T)0;
+  };
+  fetch(k0);
+  const T q4 = (T)0.25, h2 = (T)0.5;
+  const int Alo = Gc.g, Ahi = Gc.g + Gc.n - 2;
+  const bool centre = ((b & 1) == 0) && ty > 0 && ty < RRY - 1;  // fine row 2B-2 of coarse row B
+  const int B = (b + 2) >> 1;
+  T acc0 = (T)0, acc2 = (T)0;
+  double nrm = 0.0;
+  // y weights of plane p's x sums (buffer p & 1), then z weights; a coarse
+  // plane is written at its last (odd) fine plane
+  auto ycombine = [&](int p) {
+    if (!centre) return;
+    const int pb = p & 1;
+    const T ry0 = q4 * srx[pb][ty - 1][0][tx] + h2 * srx[pb][ty][0][tx] + q4 * srx[pb][ty + 1][0][tx];
+    const T ry2 = q4 * srx[pb][ty - 1][1][tx] + h2 * srx[pb][ty][1][tx] + q4 * srx[pb][ty + 1][1][tx];
+    if (p & 1) {
+      if (p > k0) {
+        acc0 += q4 * ry0;
+        acc2 += q4 * ry2;
+        const int K = (p + 1) >> 1;
+        const int A0 = 2 * m + 1, A2 = 2 * m + 2;
+        if (m <= G.mhi() && B >= Alo && B <= Ahi && K >= Alo && K <= Ahi) {
+          if (A0 >= Alo && A0 <= Ahi) Fc[Gc.at(A0, B, K)] = acc0;
+          if (A2 >= Alo && A2 <= Ahi) Fc[Gc.at(A2, B, K)] = acc2;
+        }
+      }
+      acc0 = q4 * ry0;
+      acc2 = q4 * ry2;
+    } else {
+      acc0 += h2 * ry0;
+      acc2 += h2 * ry2;
+    }
+  };
+  for (int k = k0; k <= kend; ++k) {
+    const int buf = k & 1;
+    T fc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      win[6][q] = wn[q];
+      fc[q] = fq[q];
+      tile[buf][ty + 3][q][tx + 1] = win[3][q];
+    }
+    if (halo) hz[ty][(k + 3) & 7] = hwn;
+    const T fh = fhn;
+    if (ty < 6) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tile[buf][htr][q][tx + 1] = hr[q];
+    }
+    if (hcell) tile[buf][ctr][cq][ctc] = hc;
+    __syncthreads();
+    if (k < kend) fetch(k + 1);
+    if (k > k0) ycombine(k - 1);
+    const int s = (b + k + G.off) & 3;
+    const int r0 = ty + 3;
+    // staged-order 19-point residual at position q of the tile column tc
+    auto res_at = [&](int q, int tc, const T* w, T f) -> T {
+      T sd[3];
+#pragma unroll
+      for (int d = 1; d <= 3; ++d) {
+        const int qp = q + d, qm = q - d;
+        const T xp = tile[buf][r0][qp & 3][tc + (qp >> 2)];
+        const T xm = tile[buf][r0][qm & 3][tc + (qm >> 2)];
+        sd[d - 1] = xp + xm + tile[buf][r0 + d][q][tc] + tile[buf][r0 - d][q][tc] + w[3 + d] + w[3 - d];
+      }
+      const T lap = ((T)(3.0 * kC0) * w[3] + (T)kC1 * sd[0] + (T)kC2 * sd[1] + (T)kC3 * sd[2]) * ih2;
+      return f - lap;
+    };
+    T r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      r[q] = (T)0;
+      if (live && G.inner(4 * m + q)) {
+        T w[7];
+#pragma unroll
+        for (int d = 0; d < 7; ++d) w[d] = win[d][q];
+        r[q] = res_at(q, tx + 1, w, fc[q]);
+        if (own && k <= k1) nrm += (double)r[q] * (double)r[q];
+      }
+      if (SKIPLAST && ((q + s) & 3) == 3) r[q] = (T)0;
+    }
+    T left = __shfl_up(r[3], 1, 64);
+    if (tx == 0) {
+      left = (T)0;
+      if (halo && b <= last && G.inner(4 * mh + 3) && !(SKIPLAST && ((3 + s) & 3) == 3)) {
+        T w[7];
+#pragma unroll
+        for (int d = 0; d < 7; ++d) w[d] = hz[ty][(k + d - 3) & 7];
+        left = res_at(3, 0, w, fh);
+      }
+    }
+    srx[buf][ty][0][tx] = q4 * left + h2 * r[0] + q4 * r[1];
+    srx[buf][ty][1][tx] = q4 * r[1] + h2 * r[2] + q4 * r[3];
+#pragma unroll
+    for (int d = 0; d < 6; ++d)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) win[d][q] = win[d + 1][q];
+  }
+  __syncthreads();
+  ycombine(kend);
+  if (partial) {
+    const double sum = block_sum(nrm);
+    if (tid == 0) partial[linear_block()] = sum;
+  }
+}
+
 // Residuals of the unknowns in compact column 0 of a four-colour level (node
 // a = 3, the blocks of the staged kernels start at column 1): one thread per
 // (row, plane); partial sums of r^2 per block go to partial[pbase + block].
@@ -707,7 +895,17 @@ __global__ __launch_bounds__(256) void k_res19_col0(const T* __restrict__ X, con
     const int k = G.g + (int)(t / E);
     const int a = 3;  // the only unknown of column 0 (three ghost layers)
     const long long idx = G.at(a, b, k);
-    const T res = F[idx] - lap_at<T, 6, ZU>(X, G, a, b, k, ih2);
+    // the staged kernels' order of terms: x+d, x-d, y+d, y-d, z+d, z-d
+    auto v = [&](int aa, int bb, int kk) -> T {
+      if (ZU && G.inner(aa) && G.inner(bb) && G.inner(kk)) return (T)0;
+      return X[G.at(aa, bb, kk)];
+    };
+    T sd[3];
+#pragma unroll
+    for (int d = 1; d <= 3; ++d)
+      sd[d - 1] = v(a + d, b, k) + v(a - d, b, k) + v(a, b + d, k) + v(a, b - d, k) + v(a, b, k + d) + v(a, b, k - d);
+    const T lap = ((T)(3.0 * kC0) * v(a, b, k) + (T)kC1 * sd[0] + (T)kC2 * sd[1] + (T)kC3 * sd[2]) * ih2;
+    const T res = F[idx] - lap;
     if (R) R[idx] = (TO)res;
     acc = (double)res * (double)res;
   }
@@ -2039,6 +2237,28 @@ void resrestrict(const void* phi, const void* f, bool f32, const Geom& Gf, void*
     resrestrict7_t<float>((const float*)phi, (const float*)f, Gf, (float*)f_coarse, Gc, r0only, st);
   else
     resrestrict7_t<double>((const double*)phi, (const double*)f, Gf, (double*)f_coarse, Gc, r0only, st);
+}
+
+bool resrestrict19_ok(const Geom& Gf) {
+  // runs of an even number of planes from odd first planes: the staged grid's
+  // 32-plane runs from 256 intervals, 8-plane runs at 128
+  return Gf.C == 4 && Gf.g == 3 && Gf.n >= 128 && staged_mbase(Gf) == 1 && (Gf.n % 2) == 0;
+}
+
+void resrestrict19(const double* phi, const double* f, const Geom& Gf, double* f_coarse, const Geom& Gc,
+                   double* partial, bool last_zero, hipStream_t st) {
+  const dim3 sg = staged_grid(Gf), blk(BX, RRY);
+  const double ih2 = 1.0 / (Gf.h * Gf.h);
+  const int mb = staged_mbase(Gf);
+  if (last_zero)
+    k_resrestrict19<double, true><<<sg, blk, 0, st>>>(phi, f, Gf, ih2, f_coarse, Gc, partial, mb);
+  else
+    k_resrestrict19<double, false><<<sg, blk, 0, st>>>(phi, f, Gf, ih2, f_coarse, Gc, partial, mb);
+  // the norm of column 0's unknowns (its residuals enter the restriction
+  // through the first lane's halo window)
+  if (partial && staged_col0(Gf))
+    k_res19_col0<double, double, false><<<col0_blocks(Gf), 256, 0, st>>>(phi, f, (double*)nullptr, Gf, ih2,
+                                                                          partial, nblocks(sg));
 }
 
 void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom& Gc, bool f32, hipStream_t st,

@@ -833,6 +833,8 @@ void vcycle(poisson_plan_s* P, int l, bool zero_guess, hipStream_t st) {
   Level& Lc = P->lv[l + 1];
   if (P->order == 2 && resrestrict_ok(L.G)) {
     resrestrict(L.phi, L.f, f32, L.G, Lc.f, Lc.G, st, o.nu1 > 0);
+  } else if (!f32 && resrestrict19_ok(L.G)) {
+    resrestrict19((const double*)L.phi, (const double*)L.f, L.G, (double*)Lc.f, Lc.G, nullptr, o.nu1 > 0, st);
   } else {
     // after a forward pre-smoothing sweep the residuals of the last colour
     // vanish; on four-colour levels the restriction does not read them
@@ -1034,18 +1036,24 @@ void cycle_head(poisson_plan_s* P, hipStream_t st) {
   Level& L = P->lv[0];
   for (int s = 0; s < P->opts.nu1; ++s)
     for (int c = 0; c < P->C; ++c) colour_pass(L.phi, L.f, false, L.G, P->order, c, 1.0, st);
-  residual(L.phi, L.f, false, L.tmp, false, L.G, P->order, false, P->partial, st);
+  if (resrestrict19_ok(L.G)) {
+    // the coarse right-hand side is formed here, with the norm
+    Level& Lc = P->lv[1];
+    resrestrict19((const double*)L.phi, (const double*)L.f, L.G, (double*)Lc.f, Lc.G, P->partial, true, st);
+  } else {
+    residual(L.phi, L.f, false, L.tmp, false, L.G, P->order, false, P->partial, st);
+  }
   finish_sum(P->partial, residual_blocks(L.G), 1, P->scal, kRes2, st);
 }
 
 // tail of a cycle: restriction of the head's residual (the last colour's
-// vanish on four-colour levels), the coarse cycle, prolongation and
-// post-smoothing
+// vanish on four-colour levels) unless the head restricted it already, the
+// coarse cycle, prolongation and post-smoothing
 void cycle_tail(poisson_plan_s* P, hipStream_t st) {
   Level& L = P->lv[0];
   Level& Lc = P->lv[1];
   const poisson_opts_t& o = P->opts;
-  restrict_fw(L.tmp, L.G, Lc.f, Lc.G, false, st, P->C == 4);
+  if (!resrestrict19_ok(L.G)) restrict_fw(L.tmp, L.G, Lc.f, Lc.G, false, st, P->C == 4);
   vcycle(P, 1, true, st);
   prolong_add(Lc.phi, Lc.G, L.phi, L.G, false, st, o.nu2 > 0);
   for (int s = 0; s < o.nu2; ++s)
