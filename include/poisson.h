@@ -283,6 +283,17 @@ int poisson_op_smooth(poisson_plan_t plan, const double* d_rho, double* d_phi, i
    unknown values to a dense (n/2-1)^3 array (both x fastest, no ghosts). */
 int poisson_op_restrict(poisson_plan_t plan, const double* d_fine, double* d_coarse);
 
+/* Restricted residual (Section 2.1.3): d_coarse = R (4 pi G rho - L_h Phi),
+   the right-hand side a V-cycle hands to the next coarser level, as a dense
+   (n/2-1)^3 array (x fastest, no ghosts); rho and Phi as in
+   poisson_op_residual (caller layout, Phi's ghosts used as given); and
+   *h_norm2 = sum of squares of the fine residual over the unknowns (NULL to
+   skip; synchronises).  FP64 multigrid plans with at least two levels
+   (POISSON_EINVAL otherwise).  On four-colour levels from 128 intervals one
+   fused kernel forms both without storing the fine residual. */
+int poisson_op_restrict_residual(poisson_plan_t plan, const double* d_rho, const double* d_phi,
+                                 double* d_coarse, double* h_norm2);
+
 /* d_fine += P d_coarse, P = 8 R^T (trilinear), dense interior arrays as above. */
 int poisson_op_prolong_add(poisson_plan_t plan, const double* d_coarse, double* d_fine);
 

@@ -215,6 +215,16 @@ class Plan:
         _check(self.lib.poisson_op_restrict(self.handle, _ptr(fine, self._dense_elems(0)),
                                             _ptr(coarse, self._dense_elems(1))), "poisson_op_restrict")
 
+    def restrict_residual(self, rho, phi, coarse) -> float:
+        """coarse = R (4 pi G rho - L phi) (dense coarse unknowns); returns the
+        fine residual's sum of squares."""
+        n2 = C.c_double()
+        ne = self.node_elems
+        _check(self.lib.poisson_op_restrict_residual(self.handle, _ptr(rho, ne), _ptr(phi, ne),
+                                                     _ptr(coarse, self._dense_elems(1)), C.byref(n2)),
+               "poisson_op_restrict_residual")
+        return n2.value
+
     def prolong_add(self, coarse, fine):
         _check(self.lib.poisson_op_prolong_add(self.handle, _ptr(coarse, self._dense_elems(1)),
                                                _ptr(fine, self._dense_elems(0))), "poisson_op_prolong_add")

@@ -59,6 +59,7 @@ SIGNATURES = {
     "poisson_op_smooth": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
                                     C.c_double]),
     "poisson_op_restrict": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "poisson_op_restrict_residual": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "poisson_op_prolong_add": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "poisson_op_vcycle": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32]),
     "poisson_op_sweep_resident": (C.c_int, [C.c_void_p, C.c_int32]),

@@ -2091,6 +2091,38 @@ int poisson_op_restrict(poisson_plan_t P, const double* d_fine, double* d_coarse
   return launch_check("poisson_op_restrict");
 }
 
+int poisson_op_restrict_residual(poisson_plan_t P, const double* d_rho, const double* d_phi, double* d_coarse,
+                                 double* h_norm2) {
+  CHK(need_cart(P));
+  if (!d_rho || !d_phi || !d_coarse) {
+    set_error("null argument");
+    return POISSON_EINVAL;
+  }
+  if (P->lv.size() < 2 || P->mg32) {
+    set_error("the restricted residual needs an FP64 multigrid plan with at least two levels");
+    return POISSON_EINVAL;
+  }
+  hipStream_t st = P->st;
+  const poisson_grid_t& g = P->grid;
+  Level& L1 = P->lv[1];
+  split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);
+  split_from_natural(d_rho, g.pitch[0], g.pitch[1], P->f64, false, P->G0, P->opts.four_pi_G, st);
+  if (resrestrict19_ok(P->G0)) {
+    resrestrict19(P->phi64, P->f64, P->G0, (double*)L1.f, L1.G, P->partial, false, st);
+  } else {
+    residual(P->phi64, P->f64, false, P->t64, false, P->G0, P->order, false, P->partial, st);
+    restrict_fw(P->t64, P->G0, L1.f, L1.G, false, st);
+  }
+  finish_sum(P->partial, residual_blocks(P->G0), 1, P->scal, kRes2, st);
+  split_to_dense(L1.f, false, d_coarse, L1.G, st);
+  CHK(launch_check("poisson_op_restrict_residual"));
+  if (h_norm2) {
+    CHK(read_scalars(P, kRes2, 1));
+    *h_norm2 = P->host[0];
+  }
+  return POISSON_OK;
+}
+
 int poisson_op_prolong_add(poisson_plan_t P, const double* d_coarse, double* d_fine) {
   CHK(need_cart(P));
   if (P->lv.size() < 2 || P->mg32) {

@@ -108,6 +108,29 @@ def test_four_colour_pass_and_residual_at_511():
     assert n2 == pytest.approx(float(np.sum(rref * rref)), rel=1e-12)
 
 
+@pytest.mark.parametrize("order,n", [(2, 64), (2, 256), (6, 64), (6, 128), (6, 256), (6, 512)])
+def test_restricted_residual(order, n):
+    """R (f - L phi) and the fine residual's sum of squares against the
+    oracle's residual followed by its full weighting.  On the four-colour
+    levels from 128 intervals one fused kernel forms both (n = 512: the
+    launch configuration of the 511^3 solve's cycle head, here restricting
+    every colour)."""
+    say(f"restricted residual n={n} order={order}")
+    plan, g = _plan(n, order, method="mg")
+    phi, rho = random_cart(n, g, 29)
+    rng = np.random.default_rng(31)
+    s = slice(g, g + n - 1)
+    phi[s, s, s] = rng.normal(size=(n - 1,) * 3)
+    coarse = torch.zeros((n // 2 - 1,) * 3, dtype=torch.float64, device="cuda:0")
+    n2 = plan.restrict_residual(dev(rho), dev(phi), coarse)
+    rref = OO.residual(phi, rho, n, 1.0 / n, order, g)
+    del phi, rho
+    assert n2 == pytest.approx(float(np.sum(rref * rref)), rel=1e-12)
+    cref = OS.restrict(rref)
+    del rref
+    assert rel_max(host(coarse), cref) < KTOL
+
+
 @pytest.mark.parametrize("order,n", [(2, 16), (2, 64), (2, 96), (6, 16), (6, 64), (6, 96), (6, 128), (6, 256)])
 def test_restrict_and_prolong(order, n):
     """Full weighting and trilinear prolongation on the two-colour (7-point)
