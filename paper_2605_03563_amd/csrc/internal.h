@@ -143,12 +143,12 @@ void zero_unknowns(void* x, bool f32, const Geom& G, hipStream_t st);
 void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, int colour,
                  double omega, hipStream_t st, int zmask = 0);
 
-// FP64 four-colour levels from 128 intervals: the 19-point residual fused
-// with full weighting into f_coarse, without storing the fine residual;
-// partial (when not null) receives residual_blocks(Gf) sums of r^2 as the
-// residual does; last_zero as restrict_fw.
+// Four-colour levels from 128 intervals (FP64, or FP32 when f32): the
+// 19-point residual fused with full weighting into f_coarse, without storing
+// the fine residual; partial (when not null) receives residual_blocks(Gf)
+// sums of r^2 as the residual does; last_zero as restrict_fw.
 bool resrestrict19_ok(const Geom& Gf);
-void resrestrict19(const double* phi, const double* f, const Geom& Gf, double* f_coarse, const Geom& Gc,
+void resrestrict19(const void* phi, const void* f, bool f32, const Geom& Gf, void* f_coarse, const Geom& Gc,
                    double* partial, bool last_zero, hipStream_t st);
 
 // r = f - L phi on the unknowns (split in, split out or nullptr); partial sums

@@ -709,7 +709,7 @@ __global__ __launch_bounds__(VX2 * 2 * TBY) void k_residual19v(const T* __restri
 // later (after that plane's barrier), and along z in registers.  SKIPLAST:
 // the residuals of colour 3 are zero after a Gauss-Seidel pass over colour 3
 // and are restricted as zero (they still enter the norm).  Requires runs of
-// an even number of planes (levels from 128 intervals).
+// an even number of planes (levels from 128 intervals).  FP64 or FP32 levels.
 constexpr int RRY = TBY + 1;        // thread rows of the fused kernel
 constexpr int RTROWS = RRY + 6;
 static_assert(BX * RRY >= 8 * RTROWS, "one halo-column cell per thread");
@@ -2245,20 +2245,28 @@ bool resrestrict19_ok(const Geom& Gf) {
   return Gf.C == 4 && Gf.g == 3 && Gf.n >= 128 && staged_mbase(Gf) == 1 && (Gf.n % 2) == 0;
 }
 
-void resrestrict19(const double* phi, const double* f, const Geom& Gf, double* f_coarse, const Geom& Gc,
-                   double* partial, bool last_zero, hipStream_t st) {
+template <typename T>
+static void resrestrict19_t(const T* phi, const T* f, const Geom& Gf, T* f_coarse, const Geom& Gc, double* partial,
+                            bool last_zero, hipStream_t st) {
   const dim3 sg = staged_grid(Gf), blk(BX, RRY);
-  const double ih2 = 1.0 / (Gf.h * Gf.h);
+  const T ih2 = (T)(1.0 / (Gf.h * Gf.h));
   const int mb = staged_mbase(Gf);
   if (last_zero)
-    k_resrestrict19<double, true><<<sg, blk, 0, st>>>(phi, f, Gf, ih2, f_coarse, Gc, partial, mb);
+    k_resrestrict19<T, true><<<sg, blk, 0, st>>>(phi, f, Gf, ih2, f_coarse, Gc, partial, mb);
   else
-    k_resrestrict19<double, false><<<sg, blk, 0, st>>>(phi, f, Gf, ih2, f_coarse, Gc, partial, mb);
-  // the norm of column 0's unknowns (its residuals enter the restriction
+    k_resrestrict19<T, false><<<sg, blk, 0, st>>>(phi, f, Gf, ih2, f_coarse, Gc, partial, mb);
+  // the norm of column 0's unknowns (their residuals enter the restriction
   // through the first lane's halo window)
   if (partial && staged_col0(Gf))
-    k_res19_col0<double, double, false><<<col0_blocks(Gf), 256, 0, st>>>(phi, f, (double*)nullptr, Gf, ih2,
-                                                                          partial, nblocks(sg));
+    k_res19_col0<T, T, false><<<col0_blocks(Gf), 256, 0, st>>>(phi, f, (T*)nullptr, Gf, ih2, partial, nblocks(sg));
+}
+
+void resrestrict19(const void* phi, const void* f, bool f32, const Geom& Gf, void* f_coarse, const Geom& Gc,
+                   double* partial, bool last_zero, hipStream_t st) {
+  if (f32)
+    resrestrict19_t((const float*)phi, (const float*)f, Gf, (float*)f_coarse, Gc, partial, last_zero, st);
+  else
+    resrestrict19_t((const double*)phi, (const double*)f, Gf, (double*)f_coarse, Gc, partial, last_zero, st);
 }
 
 void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom& Gc, bool f32, hipStream_t st,

@@ -833,8 +833,8 @@ void vcycle(poisson_plan_s* P, int l, bool zero_guess, hipStream_t st) {
   Level& Lc = P->lv[l + 1];
   if (P->order == 2 && resrestrict_ok(L.G)) {
     resrestrict(L.phi, L.f, f32, L.G, Lc.f, Lc.G, st, o.nu1 > 0);
-  } else if (!f32 && resrestrict19_ok(L.G)) {
-    resrestrict19((const double*)L.phi, (const double*)L.f, L.G, (double*)Lc.f, Lc.G, nullptr, o.nu1 > 0, st);
+  } else if (resrestrict19_ok(L.G)) {
+    resrestrict19(L.phi, L.f, f32, L.G, Lc.f, Lc.G, nullptr, o.nu1 > 0, st);
   } else {
     // after a forward pre-smoothing sweep the residuals of the last colour
     // vanish; on four-colour levels the restriction does not read them
@@ -1039,7 +1039,7 @@ void cycle_head(poisson_plan_s* P, hipStream_t st) {
   if (resrestrict19_ok(L.G)) {
     // the coarse right-hand side is formed here, with the norm
     Level& Lc = P->lv[1];
-    resrestrict19((const double*)L.phi, (const double*)L.f, L.G, (double*)Lc.f, Lc.G, P->partial, true, st);
+    resrestrict19(L.phi, L.f, false, L.G, Lc.f, Lc.G, P->partial, true, st);
   } else {
     residual(L.phi, L.f, false, L.tmp, false, L.G, P->order, false, P->partial, st);
   }
@@ -2108,7 +2108,7 @@ int poisson_op_restrict_residual(poisson_plan_t P, const double* d_rho, const do
   split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);
   split_from_natural(d_rho, g.pitch[0], g.pitch[1], P->f64, false, P->G0, P->opts.four_pi_G, st);
   if (resrestrict19_ok(P->G0)) {
-    resrestrict19(P->phi64, P->f64, P->G0, (double*)L1.f, L1.G, P->partial, false, st);
+    resrestrict19(P->phi64, P->f64, false, P->G0, L1.f, L1.G, P->partial, false, st);
   } else {
     residual(P->phi64, P->f64, false, P->t64, false, P->G0, P->order, false, P->partial, st);
     restrict_fw(P->t64, P->G0, L1.f, L1.G, false, st);
