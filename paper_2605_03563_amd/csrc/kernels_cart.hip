@@ -1818,129 +1818,161 @@ __global__ __launch_bounds__(256) void k_cg_dir7(const double* __restrict__ Rr, 
   if (threadIdx.x == 0 && threadIdx.y == 0) partial[linear_block()] = sum;
 }
 
-// x -= alpha p; r -= alpha q; partial (r . r).  The vectors follow the
-// residual r = f - L x (the negative of the residual of the SPD system
-// -L x = -f), so the direction enters x with a minus sign.
 // CG direction and operator, 7-point, with two compact columns m0, m0+1 per
 // lane read and written as 16-byte vectors: p_new = sr r + beta p_old and
 // q = -L p_new at the four nodes 2m0 .. 2m0+3, plus the block's partial sum of
-// p_new . q.  Per plane the lane forms p for both colours at its columns on
-// planes k-1..k+1 (a window along z) and at rows b -+ 1; x-neighbours come
-// from its own vectors or the adjacent lanes (edge lanes load theirs).  All
-// loads of the lane's KZP planes are issued before the first update.
-template <int KZP>
-__global__ __launch_bounds__(256) void k_cg_dir7v(const double* __restrict__ Rr, const double* __restrict__ Pold,
-                                                  double* __restrict__ Pnew, double* __restrict__ Q, Geom G,
-                                                  double ih2, double sr, const Scalars* __restrict__ scal,
-                                                  double* __restrict__ partial) {
+// p_new . q.  The lane marches KZR planes keeping p for both colour arrays at
+// its columns on planes k-1 .. k+1, and loads plane k+2 (r and p_old) one
+// step ahead; the centre plane goes to LDS (double-buffered, one barrier per
+// plane), so the y-neighbours inside the block's BY rows come from there and
+// only the first and last thread rows load theirs (also one plane ahead);
+// x-neighbours come from the lane's own vectors or the adjacent lanes (edge
+// lanes load theirs).
+template <int KZR>
+__global__ __launch_bounds__(BX* BY) void k_cg_dir7z(const double* __restrict__ Rr, const double* __restrict__ Pold,
+                                                     double* __restrict__ Pnew, double* __restrict__ Q, Geom G,
+                                                     double ih2, double sr, const Scalars* __restrict__ scal,
+                                                     double* __restrict__ partial) {
   typedef VecOf<double, 2>::type V;
+  __shared__ V cen[2][2][BY][BX];
   int bx, by, bz;
   xcd_block(bx, by, bz);
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x, ty = threadIdx.y;
   const int m0 = G.mlo() + 2 * (bx * BX + lane);
-  const int b = G.g + by * BY + (int)threadIdx.y;
+  const int b = G.g + by * BY + ty;
   const int last = G.g + G.n - 2;
   const double beta = scal->v[2];
   const bool live = m0 <= G.mhi() && b <= last;
   const int mm = live ? m0 : G.mlo();
   const int bb = min(b, last);
-  const int kz = planes_per_block(G);
-  const int k0 = G.g + bz * kz;
-  const int k1 = min(k0 + kz - 1, last);
+  const int k0 = G.g + bz * KZR;
+  const int k1 = min(k0 + KZR - 1, last);
   const long long plane = (long long)G.M * G.W;
   const long long W = G.W;
   const long long q0 = G.row(bb, 0) + mm;
   auto ld = [](const double* p) -> V { return *reinterpret_cast<const V*>(p); };
   auto pv = [&](long long i) -> V { return sr * ld(Rr + i) + beta * ld(Pold + i); };
   auto ps = [&](long long i) -> double { return sr * Rr[i] + beta * Pold[i]; };
-  V z0[KZP + 2], z1[KZP + 2];  // colour arrays 0 and 1 at the lane's columns, planes k0-1 ..
+  // rows above and below the block's: loaded by its first and last thread rows
+  const bool ylo = ty == 0 || bb - 1 < G.g + by * BY;   // b - 1 outside the block's rows
+  const bool yhi = ty == BY - 1 || bb + 1 > min(G.g + by * BY + BY - 1, last);
+  const bool needl = lane == 0 && mm >= 1;
+  const bool needr = lane == BX - 1 && mm + 2 < G.W;
+  // window: p of colour arrays 0 and 1 on planes k-1, k, k+1
+  V z0[3], z1[3];
 #pragma unroll
-  for (int t = 0; t < KZP + 2; ++t) {
+  for (int t = 0; t < 3; ++t) {
     const long long o = (long long)min(k0 - 1 + t, k1 + 1) * plane;
     z0[t] = pv(q0 + o);
     z1[t] = pv(G.cs + q0 + o);
   }
-  V y0m[KZP], y0p[KZP], y1m[KZP], y1p[KZP];
-  double el[KZP], er[KZP];
-  const bool needl = lane == 0 && mm >= 1;
-  const bool needr = lane == BX - 1 && mm + 2 < G.W;
-#pragma unroll
-  for (int t = 0; t < KZP; ++t) {
-    const int k = min(k0 + t, k1);
+  // one step ahead: plane k+2 of the window, rows b -+ 1 and the x edges of plane k+1
+  V n0, n1, ym0, ym1, yp0, yp1;
+  double el, er;
+  auto side = [&](int k) {  // rows b -+ 1 and x edges of plane k
     const long long o = (long long)k * plane;
-    y0m[t] = pv(q0 + o - W);
-    y0p[t] = pv(q0 + o + W);
-    y1m[t] = pv(G.cs + q0 + o - W);
-    y1p[t] = pv(G.cs + q0 + o + W);
-    const long long sa = (long long)((bb + k + G.off) & 1) * G.cs;  // colour array of the even nodes 2m
+    if (ylo) {
+      ym0 = pv(q0 + o - W);
+      ym1 = pv(G.cs + q0 + o - W);
+    }
+    if (yhi) {
+      yp0 = pv(q0 + o + W);
+      yp1 = pv(G.cs + q0 + o + W);
+    }
+    const long long sa = (long long)((bb + k + G.off) & 1) * G.cs;
     const long long sb = G.cs - sa;
-    el[t] = needl ? ps(sb + q0 + o - 1) : 0.0;   // node 2m0 - 1 (odd)
-    er[t] = needr ? ps(sa + q0 + o + 2) : 0.0;   // node 2m0 + 4 (even)
-  }
+    el = needl ? ps(sb + q0 + o - 1) : 0.0;
+    er = needr ? ps(sa + q0 + o + 2) : 0.0;
+  };
+  side(k0);
   double acc = 0.0;
-#pragma unroll
-  for (int t = 0; t < KZP; ++t) {
-    const int k = k0 + t;
+  for (int k = k0; k <= k1; ++k) {
+    const int buf = k & 1;
+    cen[buf][0][ty][lane] = z0[1];
+    cen[buf][1][ty][lane] = z1[1];
+    V cym0 = ym0, cym1 = ym1, cyp0 = yp0, cyp1 = yp1;
+    const double cel = el, cer = er;
+    if (k < k1) {
+      const long long o = (long long)min(k + 2, k1 + 1) * plane;
+      n0 = pv(q0 + o);
+      n1 = pv(G.cs + q0 + o);
+      side(k + 1);
+    }
+    __syncthreads();
+    if (!ylo) {
+      cym0 = cen[buf][0][ty - 1][lane];
+      cym1 = cen[buf][1][ty - 1][lane];
+    }
+    if (!yhi) {
+      cyp0 = cen[buf][0][ty + 1][lane];
+      cyp1 = cen[buf][1][ty + 1][lane];
+    }
     const int s = (bb + k + G.off) & 1;  // colour of the even nodes
-    const long long o = (long long)k * plane;
-    // the even nodes sit in colour array s; their y- and z-neighbours (the
-    // same x on the adjacent rows and planes) have the other colour
-    const V pE = s ? z1[t + 1] : z0[t + 1], pO = s ? z0[t + 1] : z1[t + 1];
-    const V zE = s ? z0[t] + z0[t + 2] : z1[t] + z1[t + 2];
-    const V zO = s ? z1[t] + z1[t + 2] : z0[t] + z0[t + 2];
-    const V yE = s ? y0m[t] + y0p[t] : y1m[t] + y1p[t];
-    const V yO = s ? y1m[t] + y1p[t] : y0m[t] + y0p[t];
-    double lftO = __shfl_up(pO[1], 1, 64);    // odd node 2m0 - 1 of the left lane
-    double rgtE = __shfl_down(pE[0], 1, 64);  // even node 2m0 + 4 of the right lane
-    if (lane == 0) lftO = el[t];
-    if (lane == BX - 1) rgtE = er[t];
+    const V pE = s ? z1[1] : z0[1], pO = s ? z0[1] : z1[1];
+    const V zE = s ? z0[0] + z0[2] : z1[0] + z1[2];
+    const V zO = s ? z1[0] + z1[2] : z0[0] + z0[2];
+    const V yE = s ? cym0 + cyp0 : cym1 + cyp1;
+    const V yO = s ? cym1 + cyp1 : cym0 + cyp0;
+    double lftO = __shfl_up(pO[1], 1, 64);
+    double rgtE = __shfl_down(pE[0], 1, 64);
+    if (lane == 0) lftO = cel;
+    if (lane == BX - 1) rgtE = cer;
     V qE, qO;
-    // even node 2(m0+i): x-neighbours odd 2(m0+i)-1 and 2(m0+i)+1
     qE[0] = -(((lftO + pO[0]) + (yE[0] + zE[0]) - 6.0 * pE[0]) * ih2);
     qE[1] = -(((pO[0] + pO[1]) + (yE[1] + zE[1]) - 6.0 * pE[1]) * ih2);
-    // odd node 2(m0+i)+1: x-neighbours even 2(m0+i) and 2(m0+i)+2
     qO[0] = -(((pE[0] + pE[1]) + (yO[0] + zO[0]) - 6.0 * pO[0]) * ih2);
     qO[1] = -(((pE[1] + rgtE) + (yO[1] + zO[1]) - 6.0 * pO[1]) * ih2);
-    if (!live || k > k1) continue;
-    const long long iE = (long long)s * G.cs + q0 + o, iO = (long long)(s ^ 1) * G.cs + q0 + o;
-    bool inE[2], inO[2];
+    if (live) {
+      const long long o = (long long)k * plane;
+      const long long iE = (long long)s * G.cs + q0 + o, iO = (long long)(s ^ 1) * G.cs + q0 + o;
+      bool inE[2], inO[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      inE[i] = mm + i <= G.mhi() && G.inner(2 * (mm + i));
-      inO[i] = mm + i <= G.mhi() && G.inner(2 * (mm + i) + 1);
-    }
-    if (inE[0] && inE[1]) {
-      *reinterpret_cast<V*>(Pnew + iE) = pE;
-      *reinterpret_cast<V*>(Q + iE) = qE;
-    } else {
+      for (int i = 0; i < 2; ++i) {
+        inE[i] = mm + i <= G.mhi() && G.inner(2 * (mm + i));
+        inO[i] = mm + i <= G.mhi() && G.inner(2 * (mm + i) + 1);
+      }
+      if (inE[0] && inE[1]) {
+        *reinterpret_cast<V*>(Pnew + iE) = pE;
+        *reinterpret_cast<V*>(Q + iE) = qE;
+      } else {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        if (inE[i]) {
-          Pnew[iE + i] = pE[i];
-          Q[iE + i] = qE[i];
-        }
-    }
-    if (inO[0] && inO[1]) {
-      *reinterpret_cast<V*>(Pnew + iO) = pO;
-      *reinterpret_cast<V*>(Q + iO) = qO;
-    } else {
+        for (int i = 0; i < 2; ++i)
+          if (inE[i]) {
+            Pnew[iE + i] = pE[i];
+            Q[iE + i] = qE[i];
+          }
+      }
+      if (inO[0] && inO[1]) {
+        *reinterpret_cast<V*>(Pnew + iO) = pO;
+        *reinterpret_cast<V*>(Q + iO) = qO;
+      } else {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        if (inO[i]) {
-          Pnew[iO + i] = pO[i];
-          Q[iO + i] = qO[i];
-        }
-    }
+        for (int i = 0; i < 2; ++i)
+          if (inO[i]) {
+            Pnew[iO + i] = pO[i];
+            Q[iO + i] = qO[i];
+          }
+      }
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      if (inE[i]) acc += pE[i] * qE[i];
-      if (inO[i]) acc += pO[i] * qO[i];
+      for (int i = 0; i < 2; ++i) {
+        if (inE[i]) acc += pE[i] * qE[i];
+        if (inO[i]) acc += pO[i] * qO[i];
+      }
     }
+    z0[0] = z0[1];
+    z0[1] = z0[2];
+    z0[2] = n0;
+    z1[0] = z1[1];
+    z1[1] = z1[2];
+    z1[2] = n1;
   }
   const double sum = block_sum(acc);
   if (threadIdx.x == 0 && threadIdx.y == 0) partial[linear_block()] = sum;
 }
 
+// x -= alpha p; r -= alpha q; partial (r . r).  The vectors follow the
+// residual r = f - L x (the negative of the residual of the SPD system
+// -L x = -f), so the direction enters x with a minus sign.
 __global__ __launch_bounds__(256) void k_cg_upd(double* __restrict__ X, double* __restrict__ R,
                                                 const double* __restrict__ P, const double* __restrict__ Q,
                                                 Geom G, const Scalars* __restrict__ scal,
@@ -2385,9 +2417,11 @@ int cg_blocks(const Geom& G) { return (int)nblocks(col_grid(G)); }
 static bool cg_dir_vec(const Geom& G, int order) {
   return order == 2 && G.mhi() - G.mlo() + 1 >= 2 * BX && G.mlo() % 2 == 0 && G.mhi() + 1 < G.W;
 }
+// planes per block of the z-marching direction kernel
+static int cg_dir_kz(const Geom& G) { return G.n > 256 ? 16 : 8; }
 static dim3 cg_dir_vec_grid(const Geom& G) {
-  const int mc = G.mhi() - G.mlo() + 1, E = G.n - 1;
-  return dim3((mc + 2 * BX - 1) / (2 * BX), (E + BY - 1) / BY, (E + 1) / 2);
+  const int mc = G.mhi() - G.mlo() + 1, E = G.n - 1, kz = cg_dir_kz(G);
+  return dim3((mc + 2 * BX - 1) / (2 * BX), (E + BY - 1) / BY, (E + kz - 1) / kz);
 }
 
 int cg_dir_blocks(const Geom& G, int order) {
@@ -2397,8 +2431,12 @@ int cg_dir_blocks(const Geom& G, int order) {
 void cg_direction_apply(const double* r, const double* p_old, double* p_new, double* q, const Geom& G, int order,
                         const Scalars* scal, double* partial, hipStream_t st, double sr) {
   const double ih2 = 1.0 / (G.h * G.h);
-  if (cg_dir_vec(G, order))
-    k_cg_dir7v<2><<<cg_dir_vec_grid(G), dim3(BX, BY), 0, st>>>(r, p_old, p_new, q, G, ih2, sr, scal, partial);
+  if (cg_dir_vec(G, order)) {
+    if (cg_dir_kz(G) == 16)
+      k_cg_dir7z<16><<<cg_dir_vec_grid(G), dim3(BX, BY), 0, st>>>(r, p_old, p_new, q, G, ih2, sr, scal, partial);
+    else
+      k_cg_dir7z<8><<<cg_dir_vec_grid(G), dim3(BX, BY), 0, st>>>(r, p_old, p_new, q, G, ih2, sr, scal, partial);
+  }
   else if (order == 2 && kz_for(G) == KZ)
     k_cg_dir7<KZ><<<col_grid(G), dim3(BX, BY), 0, st>>>(r, p_old, p_new, q, G, ih2, sr, scal, partial);
   else if (order == 2)
