@@ -198,9 +198,9 @@ int cg_dir_blocks(const Geom& G, int order);
 // partial sums of -(r . z) over the unknowns (the PCG inner product)
 void pcg_dot(const double* r, const double* z, const Geom& G, double* partial, hipStream_t st);
 // 7-point FP64 Gauss-Seidel pass of one colour that also writes the blocks'
-// partial sums of -(f . phi_new) over the nodes it updates (cg_blocks(G) of
-// them at partial)
-void colour_pass_dot(double* phi, const double* f, const Geom& G, int colour, double* partial, hipStream_t st);
+// partial sums of -(f . phi_new) over the nodes it updates at partial;
+// returns how many (at most cg_blocks(G))
+int colour_pass_dot(double* phi, const double* f, const Geom& G, int colour, double* partial, hipStream_t st);
 void cg_update(double* x, double* r, const double* p, const double* q, const Geom& G, const Scalars* scal,
                double* partial, hipStream_t st);
 void cg_scalars(const double* partial, int nb, Scalars* scal, int stage, hipStream_t st);

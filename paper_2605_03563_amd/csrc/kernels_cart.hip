@@ -188,9 +188,11 @@ template <> struct VecOf<float, 2> { typedef float type __attribute__((ext_vecto
 // other colour at columns m and m - 1 (r = 0) or m + 1 (r = 1), from the
 // lane's own vector except at its ends, where the neighbouring lanes supply
 // them (the wavefront's edge lanes load theirs).  ZG: the other colour is
-// taken as zero.
-template <typename T, int CPL, bool ZG, int KZP>
-__global__ __launch_bounds__(256) void k_pass7v(T* __restrict__ X, const T* __restrict__ F, Geom G, int c, T h2) {
+// taken as zero.  DOT: also the block's partial sum of -(f . x_new) over the
+// updated nodes, as k_pass7.
+template <typename T, int CPL, bool ZG, int KZP, bool DOT>
+__global__ __launch_bounds__(256) void k_pass7v(T* __restrict__ X, const T* __restrict__ F, Geom G, int c, T h2,
+                                                double* __restrict__ partial) {
   typedef typename VecOf<T, CPL>::type V;
   int bx, by, bz;
   xcd_block(bx, by, bz);
@@ -233,6 +235,7 @@ __global__ __launch_bounds__(256) void k_pass7v(T* __restrict__ X, const T* __re
     fv[t] = ld(fc + o);
   }
   const T sixth = (T)(1.0 / 6.0);
+  double acc = 0.0;
 #pragma unroll
   for (int t = 0; t < KZP; ++t) {
     const int k = k0 + t;
@@ -268,6 +271,15 @@ __global__ __launch_bounds__(256) void k_pass7v(T* __restrict__ X, const T* __re
       for (int i = 0; i < CPL; ++i)
         if (ok[i]) store_stream(dst + i, o[i]);
     }
+    if constexpr (DOT) {
+#pragma unroll
+      for (int i = 0; i < CPL; ++i)
+        if (ok[i]) acc += (double)fv[t][i] * (double)o[i];
+    }
+  }
+  if constexpr (DOT) {
+    const double sum = block_sum(acc);
+    if (threadIdx.x == 0 && threadIdx.y == 0) partial[linear_block()] = -sum;
   }
 }
 
@@ -2119,15 +2131,19 @@ static int pass7_cpl(const Geom& G) {
   return 1;
 }
 
+constexpr int kPass7vKz = 4;  // planes per lane of the vector 7-point pass
+template <int CPL>
+static dim3 pass7v_grid(const Geom& G) {
+  const int mc = G.mhi() - G.mlo() + 1, E = G.n - 1;
+  return dim3((mc + BX * CPL - 1) / (BX * CPL), (E + BY - 1) / BY, (E + kPass7vKz - 1) / kPass7vKz);
+}
 template <typename T, int CPL>
 static void pass7v_launch(T* x, const T* f, const Geom& G, int colour, bool zg, T h2, hipStream_t st) {
-  const int mc = G.mhi() - G.mlo() + 1, E = G.n - 1;
-  constexpr int KZP = 4;
-  const dim3 grid((mc + BX * CPL - 1) / (BX * CPL), (E + BY - 1) / BY, (E + KZP - 1) / KZP), blk(BX, BY);
+  const dim3 grid = pass7v_grid<CPL>(G), blk(BX, BY);
   if (zg)
-    k_pass7v<T, CPL, true, KZP><<<grid, blk, 0, st>>>(x, f, G, colour, h2);
+    k_pass7v<T, CPL, true, kPass7vKz, false><<<grid, blk, 0, st>>>(x, f, G, colour, h2, nullptr);
   else
-    k_pass7v<T, CPL, false, KZP><<<grid, blk, 0, st>>>(x, f, G, colour, h2);
+    k_pass7v<T, CPL, false, kPass7vKz, false><<<grid, blk, 0, st>>>(x, f, G, colour, h2, nullptr);
 }
 
 template <typename T>
@@ -2185,13 +2201,21 @@ void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, i
   }
 }
 
-void colour_pass_dot(double* phi, const double* f, const Geom& G, int colour, double* partial, hipStream_t st) {
+int colour_pass_dot(double* phi, const double* f, const Geom& G, int colour, double* partial, hipStream_t st) {
   const dim3 grid = col_grid(G), blk(BX, BY);
   const double h2 = G.h * G.h;
+  // the vector pass where it applies and writes no more partial sums than
+  // the one-column pass (the callers size their partial arrays for those)
+  if (pass7_cpl<double>(G) == 2 && nblocks(pass7v_grid<2>(G)) <= nblocks(grid)) {
+    const dim3 gv = pass7v_grid<2>(G);
+    k_pass7v<double, 2, false, kPass7vKz, true><<<gv, blk, 0, st>>>(phi, f, G, colour, h2, partial);
+    return (int)nblocks(gv);
+  }
   if (kz_for(G) == KZ)
     k_pass7<double, false, false, KZ, true><<<grid, blk, 0, st>>>(phi, f, G, colour, 1.0, h2, partial);
   else
     k_pass7<double, false, false, 1, true><<<grid, blk, 0, st>>>(phi, f, G, colour, 1.0, h2, partial);
+  return (int)nblocks(grid);
 }
 
 template <typename T, typename TO, int COL>

@@ -1166,15 +1166,16 @@ double rel_of(double r2, double bnorm) {
 // forward sweep's last from unchanged neighbours and is left out.
 // Then partial[0 .. nb) holds the partial sums of -(r . z), nb returned.
 // On two-colour grids the passes that finish colours 1 and 0 form them
-// (2 cg_blocks); on four-colour grids a separate inner-product kernel.
+// (one partial per block of each); on four-colour grids a separate
+// inner-product kernel.
 int pcg_precondition(poisson_plan_s* P, hipStream_t st) {
   const Geom& G = P->G0;
   const int cb = cg_blocks(G);
   if (P->order == 2) {
     colour_pass(P->cz, P->cr, false, G, 2, 0, 1.0, st, 2);  // colour 1 still zero
-    colour_pass_dot(P->cz, P->cr, G, 1, P->partial, st);
-    colour_pass_dot(P->cz, P->cr, G, 0, P->partial + cb, st);
-    return 2 * cb;
+    const int nb1 = colour_pass_dot(P->cz, P->cr, G, 1, P->partial, st);
+    const int nb0 = colour_pass_dot(P->cz, P->cr, G, 0, P->partial + nb1, st);
+    return nb1 + nb0;
   }
   const int C = 4;
   for (int c = 0; c < C; ++c) {
