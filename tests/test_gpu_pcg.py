@@ -49,6 +49,30 @@ def test_iterates_match_oracle(order, n):
         assert np.array_equal(got[mask], phi0[mask])
 
 
+@pytest.mark.parametrize("method,n,iters", [("cg", 256, (1, 3)), ("pcg", 256, (1, 3)), ("cg", 512, (2,))])
+def test_full_size_iterates_match_oracle(method, n, iters):
+    """The 7-point CG and PCG at full size, where a row fills a wavefront with
+    two compact columns per lane: the direction kernel marching along z
+    (8-plane runs at 256 intervals, 16-plane runs at 512) and, for PCG, the
+    vector colour passes that form the inner product; the GPU iterate after
+    each listed count equals the oracle's."""
+    order, g = 2, 1
+    h = 1.0 / n
+    phi0, rho = _problem(n, g, n + 7)
+    s = slice(g, g + n - 1)
+    hist = []
+    say(f"oracle {method} n {n}: {max(iters)} iterations")
+    OK.cg(phi0, rho, n, h, order, g, tol=0.0, max_iter=max(iters), precondition=(method == "pcg"), history=hist)
+    for k in iters:
+        say(f"{method} n {n}: {k} iterations")
+        plan = pg.Plan(pg.cart_grid(n, ghost=g), pg.options(method, order=order, lmax=-1, max_iter=k))
+        phi = dev(phi0)
+        res = plan.solve(dev(rho), phi, tol=1e-30)
+        assert res.iterations == k and not res.converged
+        assert rel_l2(host(phi)[s, s, s], hist[k - 1]) < ITER_TOL
+        del plan, phi
+
+
 @pytest.mark.parametrize("order,n", [(2, 64), (6, 48)])
 def test_converged_matches_exact_and_beats_cg(order, n):
     """Clumps (C2 / C3 shapes at reduced size) with the multipole boundary:
