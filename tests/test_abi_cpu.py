@@ -268,3 +268,21 @@ def test_noalloc_multipole_validation_before_any_device_call():
     g.ghost = 4
     assert call(g) == L.EGRID
     assert pg.NOALLOC_SCRATCH_BYTES == 80 * 1024 * 1024
+
+
+def test_operator_calls_reject_a_null_plan_before_any_device_call():
+    """Every operator entry point checks its plan on the host: a NULL plan is
+    an argument error, reported before any kernel is launched."""
+    lib = L.load()
+    p = C.c_void_p(0x1000)
+    calls = [
+        lambda: lib.poisson_op_apply(None, p, p),
+        lambda: lib.poisson_op_residual(None, p, p, p, None),
+        lambda: lib.poisson_op_restrict(None, p, p),
+        lambda: lib.poisson_op_restrict_residual(None, p, p, p, None),
+        lambda: lib.poisson_op_prolong_add(None, p, p),
+        lambda: lib.poisson_op_vcycle(None, p, p, 1),
+    ]
+    for call in calls:
+        assert call() == L.EINVAL
+        assert lib.poisson_last_error() in (b"null plan", b"null argument")
