@@ -145,11 +145,12 @@ void colour_pass(void* phi, const void* f, bool f32, const Geom& G, int order, i
 
 // Four-colour levels from 128 intervals (FP64, or FP32 when f32): the
 // 19-point residual fused with full weighting into f_coarse, without storing
-// the fine residual; partial (when not null) receives residual_blocks(Gf)
-// sums of r^2 as the residual does; last_zero as restrict_fw.
+// the fine residual; partial (when not null) receives partial sums of r^2,
+// as many as the call returns (at most residual_blocks(Gf)); last_zero as
+// restrict_fw.
 bool resrestrict19_ok(const Geom& Gf);
-void resrestrict19(const void* phi, const void* f, bool f32, const Geom& Gf, void* f_coarse, const Geom& Gc,
-                   double* partial, bool last_zero, hipStream_t st);
+int resrestrict19(const void* phi, const void* f, bool f32, const Geom& Gf, void* f_coarse, const Geom& Gc,
+                  double* partial, bool last_zero, hipStream_t st);
 
 // r = f - L phi on the unknowns (split in, split out or nullptr); partial sums
 // of r^2 go to partial[kReduceBlocks].  zero_unknowns_in treats the unknowns of

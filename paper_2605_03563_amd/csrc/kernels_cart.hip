@@ -707,9 +707,10 @@ __global__ __launch_bounds__(VX2 * 2 * TBY) void k_residual19v(const T* __restri
 // coarser four-colour level: the coarse right-hand side without storing the
 // fine residual, the squares of the fine residuals summed per block as in
 // k_residual19s.  The block, tile and register window are those of
-// k_residual19s with one more thread row: rows b0 .. b0+7 are the block's
-// own (their residuals enter the norm) and row b0+8, the next block's first,
-// completes the three fine rows of the block's last coarse row; likewise
+// k_residual19s, TR own rows and one more thread row: rows b0 .. b0+TR-1 are
+// the block's own (their residuals enter the norm) and row b0+TR, the next
+// block's first, completes the three fine rows of the block's last coarse
+// row; likewise
 // the run marches one plane past its own (b0 and the first plane of a run
 // are odd, so the block's coarse centres, on even fine rows and planes, lie
 // inside it).  Coarse node A sits on fine node 2A-2: per fine row and plane
@@ -722,14 +723,15 @@ __global__ __launch_bounds__(VX2 * 2 * TBY) void k_residual19v(const T* __restri
 // the residuals of colour 3 are zero after a Gauss-Seidel pass over colour 3
 // and are restricted as zero (they still enter the norm).  Requires runs of
 // an even number of planes (levels from 128 intervals).  FP64 or FP32 levels.
-constexpr int RRY = TBY + 1;        // thread rows of the fused kernel
-constexpr int RTROWS = RRY + 6;
-static_assert(BX * RRY >= 8 * RTROWS, "one halo-column cell per thread");
-
-template <typename T, bool SKIPLAST>
-__global__ __launch_bounds__(BX * RRY) void k_resrestrict19(const T* __restrict__ X, const T* __restrict__ F, Geom G,
-                                                            T ih2, T* __restrict__ Fc, Geom Gc,
-                                                            double* __restrict__ partial, int mbase) {
+// TR: the block's own rows (even, so that its coarse rows are whole).
+template <typename T, bool SKIPLAST, int TR>
+__global__ __launch_bounds__(BX*(TR + 1)) void k_resrestrict19(const T* __restrict__ X, const T* __restrict__ F,
+                                                               Geom G, T ih2, T* __restrict__ Fc, Geom Gc,
+                                                               double* __restrict__ partial, int mbase) {
+  constexpr int RRY = TR + 1;  // thread rows
+  constexpr int RTROWS = RRY + 6;
+  static_assert(TR % 2 == 0, "coarse rows whole within a block");
+  static_assert(BX * RRY >= 8 * RTROWS, "one halo-column cell per thread");
   __shared__ T tile[2][RTROWS][4][TCOLS];
   __shared__ T srx[2][RRY][2][BX];
   __shared__ T hz[RRY][8];  // the first lane's halo window, ring over planes
@@ -739,7 +741,7 @@ __global__ __launch_bounds__(BX * RRY) void k_resrestrict19(const T* __restrict_
   const int tid = ty * BX + tx;
   const int m0 = mbase + bx * BX;
   const int m = m0 + tx;
-  const int b0 = G.g + by * TBY;
+  const int b0 = G.g + by * TR;
   const int b = b0 + ty;
   const int last = G.g + G.n - 2;
   const int kz = planes_per_block(G);
@@ -773,7 +775,7 @@ __global__ __launch_bounds__(BX * RRY) void k_resrestrict19(const T* __restrict_
     if (halo) hz[ty][(k0 + d) & 7] = load(b, k0 + d, mh, 3);
   }
   const bool live = m <= G.mhi() && b <= last;
-  const bool own = live && ty < TBY;  // the block's own rows: their residuals enter the norm
+  const bool own = live && ty < TR;  // the block's own rows: their residuals enter the norm
   T hr[4], hc, fq[4], wn[4], hwn, fhn;
   auto fetch = [&](int k) {
 #pragma unroll
@@ -2301,28 +2303,39 @@ bool resrestrict19_ok(const Geom& Gf) {
   return Gf.C == 4 && Gf.g == 3 && Gf.n >= 128 && staged_mbase(Gf) == 1 && (Gf.n % 2) == 0;
 }
 
-template <typename T>
-static void resrestrict19_t(const T* phi, const T* f, const Geom& Gf, T* f_coarse, const Geom& Gc, double* partial,
+// Own rows per block of the fused kernel: the residual kernel's 8, or 14 on
+// FP32 levels from 512 intervals, where one block of 15 waves fills the wave
+// slots of a CU (FP32: 4 per SIMD) and loads fewer halo rows per row (517
+// against 589 us at 511^3; FP64 with 10 rows and the smaller levels were not
+// faster).
+template <typename T, int TR>
+static int resrestrict19_tr(const T* phi, const T* f, const Geom& Gf, T* f_coarse, const Geom& Gc, double* partial,
                             bool last_zero, hipStream_t st) {
-  const dim3 sg = staged_grid(Gf), blk(BX, RRY);
+  const dim3 sg0 = staged_grid(Gf);
+  const dim3 sg(sg0.x, (Gf.n - 1 + TR - 1) / TR, sg0.z), blk(BX, TR + 1);
   const T ih2 = (T)(1.0 / (Gf.h * Gf.h));
   const int mb = staged_mbase(Gf);
   if (last_zero)
-    k_resrestrict19<T, true><<<sg, blk, 0, st>>>(phi, f, Gf, ih2, f_coarse, Gc, partial, mb);
+    k_resrestrict19<T, true, TR><<<sg, blk, 0, st>>>(phi, f, Gf, ih2, f_coarse, Gc, partial, mb);
   else
-    k_resrestrict19<T, false><<<sg, blk, 0, st>>>(phi, f, Gf, ih2, f_coarse, Gc, partial, mb);
+    k_resrestrict19<T, false, TR><<<sg, blk, 0, st>>>(phi, f, Gf, ih2, f_coarse, Gc, partial, mb);
   // the norm of column 0's unknowns (their residuals enter the restriction
   // through the first lane's halo window)
   if (partial && staged_col0(Gf))
     k_res19_col0<T, T, false><<<col0_blocks(Gf), 256, 0, st>>>(phi, f, (T*)nullptr, Gf, ih2, partial, nblocks(sg));
+  return (int)(nblocks(sg) + col0_blocks(Gf));
 }
 
-void resrestrict19(const void* phi, const void* f, bool f32, const Geom& Gf, void* f_coarse, const Geom& Gc,
-                   double* partial, bool last_zero, hipStream_t st) {
-  if (f32)
-    resrestrict19_t((const float*)phi, (const float*)f, Gf, (float*)f_coarse, Gc, partial, last_zero, st);
-  else
-    resrestrict19_t((const double*)phi, (const double*)f, Gf, (double*)f_coarse, Gc, partial, last_zero, st);
+int resrestrict19(const void* phi, const void* f, bool f32, const Geom& Gf, void* f_coarse, const Geom& Gc,
+                  double* partial, bool last_zero, hipStream_t st) {
+  if (f32) {
+    auto x = (const float*)phi, y = (const float*)f;
+    auto c = (float*)f_coarse;
+    return Gf.n >= 512 ? resrestrict19_tr<float, 14>(x, y, Gf, c, Gc, partial, last_zero, st)
+                       : resrestrict19_tr<float, TBY>(x, y, Gf, c, Gc, partial, last_zero, st);
+  }
+  return resrestrict19_tr<double, TBY>((const double*)phi, (const double*)f, Gf, (double*)f_coarse, Gc, partial,
+                                       last_zero, st);
 }
 
 void restrict_fw(const void* r_fine, const Geom& Gf, void* f_coarse, const Geom& Gc, bool f32, hipStream_t st,

@@ -1036,14 +1036,15 @@ void cycle_head(poisson_plan_s* P, hipStream_t st) {
   Level& L = P->lv[0];
   for (int s = 0; s < P->opts.nu1; ++s)
     for (int c = 0; c < P->C; ++c) colour_pass(L.phi, L.f, false, L.G, P->order, c, 1.0, st);
+  int nb = residual_blocks(L.G);
   if (resrestrict19_ok(L.G)) {
     // the coarse right-hand side is formed here, with the norm
     Level& Lc = P->lv[1];
-    resrestrict19(L.phi, L.f, false, L.G, Lc.f, Lc.G, P->partial, true, st);
+    nb = resrestrict19(L.phi, L.f, false, L.G, Lc.f, Lc.G, P->partial, true, st);
   } else {
     residual(L.phi, L.f, false, L.tmp, false, L.G, P->order, false, P->partial, st);
   }
-  finish_sum(P->partial, residual_blocks(L.G), 1, P->scal, kRes2, st);
+  finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
 }
 
 // tail of a cycle: restriction of the head's residual (the last colour's
@@ -2108,13 +2109,14 @@ int poisson_op_restrict_residual(poisson_plan_t P, const double* d_rho, const do
   Level& L1 = P->lv[1];
   split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);
   split_from_natural(d_rho, g.pitch[0], g.pitch[1], P->f64, false, P->G0, P->opts.four_pi_G, st);
+  int nb = residual_blocks(P->G0);
   if (resrestrict19_ok(P->G0)) {
-    resrestrict19(P->phi64, P->f64, false, P->G0, L1.f, L1.G, P->partial, false, st);
+    nb = resrestrict19(P->phi64, P->f64, false, P->G0, L1.f, L1.G, P->partial, false, st);
   } else {
     residual(P->phi64, P->f64, false, P->t64, false, P->G0, P->order, false, P->partial, st);
     restrict_fw(P->t64, P->G0, L1.f, L1.G, false, st);
   }
-  finish_sum(P->partial, residual_blocks(P->G0), 1, P->scal, kRes2, st);
+  finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
   split_to_dense(L1.f, false, d_coarse, L1.G, st);
   CHK(launch_check("poisson_op_restrict_residual"));
   if (h_norm2) {
