@@ -288,9 +288,11 @@ int poisson_op_restrict(poisson_plan_t plan, const double* d_fine, double* d_coa
    (n/2-1)^3 array (x fastest, no ghosts); rho and Phi as in
    poisson_op_residual (caller layout, Phi's ghosts used as given); and
    *h_norm2 = sum of squares of the fine residual over the unknowns (NULL to
-   skip; synchronises).  FP64 multigrid plans with at least two levels
-   (POISSON_EINVAL otherwise).  On four-colour levels from 128 intervals one
-   fused kernel forms both without storing the fine residual. */
+   skip; synchronises).  Multigrid plans with at least two levels
+   (POISSON_EINVAL otherwise): POISSON_MG in FP64; POISSON_MG_IR32 rounds Phi
+   and 4 pi G rho to FP32 and works in FP32 as its inner cycles do (the
+   squares still summed in FP64).  On four-colour levels from 128 intervals
+   one fused kernel forms both without storing the fine residual. */
 int poisson_op_restrict_residual(poisson_plan_t plan, const double* d_rho, const double* d_phi,
                                  double* d_coarse, double* h_norm2);
 

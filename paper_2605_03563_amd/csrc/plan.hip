@@ -2100,24 +2100,30 @@ int poisson_op_restrict_residual(poisson_plan_t P, const double* d_rho, const do
     set_error("null argument");
     return POISSON_EINVAL;
   }
-  if (P->lv.size() < 2 || P->mg32) {
-    set_error("the restricted residual needs an FP64 multigrid plan with at least two levels");
+  if (P->lv.size() < 2) {
+    set_error("the restricted residual needs a multigrid plan (MG or MG_IR32) with at least two levels");
     return POISSON_EINVAL;
   }
   hipStream_t st = P->st;
   const poisson_grid_t& g = P->grid;
+  // MG_IR32 plans: the FP32 cycle's finest arrays and kernels
+  const bool f32 = P->mg32;
+  Level& L0 = P->lv[0];
   Level& L1 = P->lv[1];
-  split_from_natural(d_phi, g.pitch[0], g.pitch[1], P->phi64, false, P->G0, 1.0, st);
-  split_from_natural(d_rho, g.pitch[0], g.pitch[1], P->f64, false, P->G0, P->opts.four_pi_G, st);
+  void* x = f32 ? L0.phi : (void*)P->phi64;
+  void* f = f32 ? L0.f : (void*)P->f64;
+  void* r = f32 ? L0.tmp : (void*)P->t64;
+  split_from_natural(d_phi, g.pitch[0], g.pitch[1], x, f32, P->G0, 1.0, st);
+  split_from_natural(d_rho, g.pitch[0], g.pitch[1], f, f32, P->G0, P->opts.four_pi_G, st);
   int nb = residual_blocks(P->G0);
   if (resrestrict19_ok(P->G0)) {
-    nb = resrestrict19(P->phi64, P->f64, false, P->G0, L1.f, L1.G, P->partial, false, st);
+    nb = resrestrict19(x, f, f32, P->G0, L1.f, L1.G, P->partial, false, st);
   } else {
-    residual(P->phi64, P->f64, false, P->t64, false, P->G0, P->order, false, P->partial, st);
-    restrict_fw(P->t64, P->G0, L1.f, L1.G, false, st);
+    residual(x, f, f32, r, f32, P->G0, P->order, false, P->partial, st);
+    restrict_fw(r, P->G0, L1.f, L1.G, f32, st);
   }
   finish_sum(P->partial, nb, 1, P->scal, kRes2, st);
-  split_to_dense(L1.f, false, d_coarse, L1.G, st);
+  split_to_dense(L1.f, f32, d_coarse, L1.G, st);
   CHK(launch_check("poisson_op_restrict_residual"));
   if (h_norm2) {
     CHK(read_scalars(P, kRes2, 1));

@@ -131,6 +131,38 @@ def test_restricted_residual(order, n):
     assert rel_max(host(coarse), cref) < KTOL
 
 
+# FP32 kernels against the oracle in FP64 on the same FP32-rounded inputs:
+# each residual sums up to 19 rounded terms of |c_k phi / h^2| and full
+# weighting 27 more; with unit roundoff 6e-8 and terms a few times the
+# result, the error stays below about 50 * 6e-8 * 3 of the largest value.
+F32TOL = 1e-5
+
+
+@pytest.mark.parametrize("order,n", [(2, 64), (2, 256), (6, 64), (6, 128), (6, 256), (6, 512)])
+def test_restricted_residual_fp32(order, n):
+    """The mixed plan's FP32 residual and restriction (the inner cycles'
+    kernels; at n = 512 the fused kernel's 14-row blocks of the 511^3 mixed
+    solve) against the oracle's residual and full weighting of the same
+    FP32-rounded Phi and rho, and the FP64 sum of squares of the FP32
+    residuals."""
+    say(f"restricted residual FP32 n={n} order={order}")
+    plan, g = _plan(n, order, method="mg_ir32")
+    phi, rho = random_cart(n, g, 37)
+    rng = np.random.default_rng(41)
+    s = slice(g, g + n - 1)
+    phi[s, s, s] = rng.normal(size=(n - 1,) * 3)
+    coarse = torch.zeros((n // 2 - 1,) * 3, dtype=torch.float64, device="cuda:0")
+    n2 = plan.restrict_residual(dev(rho), dev(phi), coarse)
+    phi = phi.astype(np.float32).astype(np.float64)
+    rho = rho.astype(np.float32).astype(np.float64)
+    rref = OO.residual(phi, rho, n, 1.0 / n, order, g)
+    del phi, rho
+    assert n2 == pytest.approx(float(np.sum(rref * rref)), rel=F32TOL)
+    cref = OS.restrict(rref)
+    del rref
+    assert rel_max(host(coarse), cref) < F32TOL
+
+
 @pytest.mark.parametrize("order,n", [(2, 16), (2, 64), (2, 96), (6, 16), (6, 64), (6, 96), (6, 128), (6, 256)])
 def test_restrict_and_prolong(order, n):
     """Full weighting and trilinear prolongation on the two-colour (7-point)
