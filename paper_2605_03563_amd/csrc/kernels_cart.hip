@@ -710,46 +710,52 @@ __global__ __launch_bounds__(VX2 * 2 * TBY) void k_residual19v(const T* __restri
 // k_residual19s, TR own rows and one more thread row: rows b0 .. b0+TR-1 are
 // the block's own (their residuals enter the norm) and row b0+TR, the next
 // block's first, completes the three fine rows of the block's last coarse
-// row; likewise
-// the run marches one plane past its own (b0 and the first plane of a run
-// are odd, so the block's coarse centres, on even fine rows and planes, lie
-// inside it).  Coarse node A sits on fine node 2A-2: per fine row and plane
-// a thread restricts along x at its compact column's positions 0 and 2, the
-// value left of position 0 coming from the previous lane; the first lane
-// forms the residual at position 3 of the compact column before the block
-// (a window along z kept in LDS, and the tile's halo column).  The x sums go
+// row; likewise the run marches one plane past its own (b0 and the first
+// plane of a run are odd, so the block's coarse centres, on even fine rows
+// and planes, lie inside it).  Coarse node A sits on fine node 2A-2: per
+// fine row and plane a thread restricts along x at its compact column's
+// positions 0 and 2, the value left of position 0 coming from the previous
+// lane.  For the first lane that value is the residual at position 3 of the
+// compact column before the block: one more wavefront forms it for all the
+// block's rows (lane r for row b0 + r, a window along z in registers, the
+// tile's halo column) and adds compact column 0's one unknown per row and
+// plane to the norm in the blocks of the first column group.  The x sums go
 // to LDS and are combined along y by the threads of the even rows one plane
-// later (after that plane's barrier), and along z in registers.  SKIPLAST:
-// the residuals of colour 3 are zero after a Gauss-Seidel pass over colour 3
-// and are restricted as zero (they still enter the norm).  Requires runs of
-// an even number of planes (levels from 128 intervals).  FP64 or FP32 levels.
+// later (after that plane's barrier; the first lane adds the halo residual
+// there), and along z in registers.  SKIPLAST: the residuals of colour 3 are
+// zero after a Gauss-Seidel pass over colour 3 and are restricted as zero
+// (they still enter the norm).  Requires runs of an even number of planes
+// (levels from 128 intervals).  FP64 or FP32 levels.
 // TR: the block's own rows (even, so that its coarse rows are whole).
 template <typename T, bool SKIPLAST, int TR>
-__global__ __launch_bounds__(BX*(TR + 1)) void k_resrestrict19(const T* __restrict__ X, const T* __restrict__ F,
+__global__ __launch_bounds__(BX*(TR + 2)) void k_resrestrict19(const T* __restrict__ X, const T* __restrict__ F,
                                                                Geom G, T ih2, T* __restrict__ Fc, Geom Gc,
                                                                double* __restrict__ partial, int mbase) {
-  constexpr int RRY = TR + 1;  // thread rows
+  constexpr int RRY = TR + 1;  // thread rows over fine rows; thread row RRY forms the halo residuals
   constexpr int RTROWS = RRY + 6;
   static_assert(TR % 2 == 0, "coarse rows whole within a block");
   static_assert(BX * RRY >= 8 * RTROWS, "one halo-column cell per thread");
+  static_assert(RRY <= BX, "one halo-wavefront lane per row");
   __shared__ T tile[2][RTROWS][4][TCOLS];
   __shared__ T srx[2][RRY][2][BX];
-  __shared__ T hz[RRY][8];  // the first lane's halo window, ring over planes
+  __shared__ T hres[2][RRY];  // residual at position 3 of compact column m0-1, per row
   int bx, by, bz;
   xcd_block(bx, by, bz);
   const int tx = threadIdx.x, ty = threadIdx.y;
   const int tid = ty * BX + tx;
+  const bool hw = ty == RRY;  // the halo wavefront
   const int m0 = mbase + bx * BX;
-  const int m = m0 + tx;
+  const int mh = m0 - 1;
+  const int m = hw ? mh : m0 + tx;
   const int b0 = G.g + by * TR;
-  const int b = b0 + ty;
+  const int b = b0 + (hw ? tx : ty);
   const int last = G.g + G.n - 2;
   const int kz = planes_per_block(G);
   const int k0 = G.g + bz * kz;
   const int k1 = min(k0 + kz - 1, last);
   const int kend = min(k1 + 1, last);
   const bool colok = m < G.W;
-  const bool rowok = b < G.M;
+  const bool rowok = b < G.M && (!hw || tx < RRY);
   const long long plane = (long long)G.M * G.W;
   const long long cb = (long long)b * G.W + m;
   auto load = [&](int bb, int kk, int mm, int q) -> T {
@@ -764,35 +770,34 @@ __global__ __launch_bounds__(BX*(TR + 1)) void k_resrestrict19(const T* __restri
   const int ctc = cside ? BX + 1 : 0;
   const bool hcell = tid < 8 * RTROWS;
   const bool hcol = hcell && chb >= 0 && chb < G.M && chm >= 0 && chm < G.W;
-  // the first lane also keeps a window at position 3 of compact column m0-1
-  const int mh = m0 - 1;
-  const bool halo = tx == 0 && rowok && mh >= 0;
+  // the window: four positions of the lane's compact column (the halo
+  // wavefront: position 3 only, of column m0-1)
   T win[7][4];
 #pragma unroll
-  for (int d = -3; d <= 2; ++d) {
+  for (int d = -3; d <= 2; ++d)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) win[d + 3][q] = (colok && rowok) ? load(b, k0 + d, m, q) : (T)0;
-    if (halo) hz[ty][(k0 + d) & 7] = load(b, k0 + d, mh, 3);
-  }
-  const bool live = m <= G.mhi() && b <= last;
-  const bool own = live && ty < TR;  // the block's own rows: their residuals enter the norm
-  T hr[4], hc, fq[4], wn[4], hwn, fhn;
+    for (int q = 0; q < 4; ++q)
+      win[d + 3][q] = (colok && rowok && (!hw || q == 3)) ? load(b, k0 + d, m, q) : (T)0;
+  const bool live = m <= G.mhi() && b <= last && rowok;
+  const bool own = live && !hw && ty < TR;  // the block's own rows: their residuals enter the norm
+  const bool col0 = hw && live && tx < TR && mh == 0 && G.inner(3);  // compact column 0's unknown
+  const bool hlive = hw && live && G.inner(4 * mh + 3);
+  T hr[4], hc, fq[4], wn[4];
   auto fetch = [&](int k) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) hr[q] = hrow ? load(hb, k, m, q) : (T)0;
     hc = hcol ? load(chb, k, chm, cq) : (T)0;
     const int s = (b + k + G.off) & 3;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) fq[q] = live ? F[(long long)((q + s) & 3) * G.cs + k * plane + cb] : (T)0;
+    for (int q = 0; q < 4; ++q)
+      fq[q] = (live && (!hw || q == 3)) ? F[(long long)((q + s) & 3) * G.cs + k * plane + cb] : (T)0;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) wn[q] = (colok && rowok) ? load(b, k + 3, m, q) : (T)0;
-    hwn = halo ? load(b, k + 3, mh, 3) : (T)0;
-    fhn = halo ? F[(long long)((3 + s) & 3) * G.cs + k * plane + (long long)b * G.W + mh] : (T)0;
+    for (int q = 0; q < 4; ++q) wn[q] = (colok && rowok && (!hw || q == 3)) ? load(b, k + 3, m, q) : (T)0;
   };
   fetch(k0);
   const T q4 = (T)0.25, h2 = (T)0.5;
   const int Alo = Gc.g, Ahi = Gc.g + Gc.n - 2;
-  const bool centre = ((b & 1) == 0) && ty > 0 && ty < RRY - 1;  // fine row 2B-2 of coarse row B
+  const bool centre = !hw && ((b & 1) == 0) && ty > 0 && ty < RRY - 1;  // fine row 2B-2 of coarse row B
   const int B = (b + 2) >> 1;
   T acc0 = (T)0, acc2 = (T)0;
   double nrm = 0.0;
@@ -801,7 +806,10 @@ __global__ __launch_bounds__(BX*(TR + 1)) void k_resrestrict19(const T* __restri
   auto ycombine = [&](int p) {
     if (!centre) return;
     const int pb = p & 1;
-    const T ry0 = q4 * srx[pb][ty - 1][0][tx] + h2 * srx[pb][ty][0][tx] + q4 * srx[pb][ty + 1][0][tx];
+    auto sx0 = [&](int row) -> T {
+      return tx == 0 ? q4 * hres[pb][row] + srx[pb][row][0][0] : srx[pb][row][0][tx];
+    };
+    const T ry0 = q4 * sx0(ty - 1) + h2 * sx0(ty) + q4 * sx0(ty + 1);
     const T ry2 = q4 * srx[pb][ty - 1][1][tx] + h2 * srx[pb][ty][1][tx] + q4 * srx[pb][ty + 1][1][tx];
     if (p & 1) {
       if (p > k0) {
@@ -828,10 +836,11 @@ __global__ __launch_bounds__(BX*(TR + 1)) void k_resrestrict19(const T* __restri
     for (int q = 0; q < 4; ++q) {
       win[6][q] = wn[q];
       fc[q] = fq[q];
-      tile[buf][ty + 3][q][tx + 1] = win[3][q];
     }
-    if (halo) hz[ty][(k + 3) & 7] = hwn;
-    const T fh = fhn;
+    if (!hw) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tile[buf][ty + 3][q][tx + 1] = win[3][q];
+    }
     if (ty < 6) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) tile[buf][htr][q][tx + 1] = hr[q];
@@ -841,9 +850,8 @@ __global__ __launch_bounds__(BX*(TR + 1)) void k_resrestrict19(const T* __restri
     if (k < kend) fetch(k + 1);
     if (k > k0) ycombine(k - 1);
     const int s = (b + k + G.off) & 3;
-    const int r0 = ty + 3;
-    // staged-order 19-point residual at position q of the tile column tc
-    auto res_at = [&](int q, int tc, const T* w, T f) -> T {
+    // staged-order 19-point residual at position q of the tile column tc, row r0
+    auto res_at = [&](int r0, int q, int tc, const T* w, T f) -> T {
       T sd[3];
 #pragma unroll
       for (int d = 1; d <= 3; ++d) {
@@ -855,31 +863,38 @@ __global__ __launch_bounds__(BX*(TR + 1)) void k_resrestrict19(const T* __restri
       const T lap = ((T)(3.0 * kC0) * w[3] + (T)kC1 * sd[0] + (T)kC2 * sd[1] + (T)kC3 * sd[2]) * ih2;
       return f - lap;
     };
-    T r[4];
+    if (hw) {
+      if (tx < RRY) {
+        T rh = (T)0;
+        if (hlive) {
+          T w[7];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      r[q] = (T)0;
-      if (live && G.inner(4 * m + q)) {
-        T w[7];
-#pragma unroll
-        for (int d = 0; d < 7; ++d) w[d] = win[d][q];
-        r[q] = res_at(q, tx + 1, w, fc[q]);
-        if (own && k <= k1) nrm += (double)r[q] * (double)r[q];
+          for (int d = 0; d < 7; ++d) w[d] = win[d][3];
+          rh = res_at(tx + 3, 3, 0, w, fc[3]);
+          if (col0 && k <= k1) nrm += (double)rh * (double)rh;
+          if (SKIPLAST && ((3 + s) & 3) == 3) rh = (T)0;
+        }
+        hres[buf][tx] = rh;
       }
-      if (SKIPLAST && ((q + s) & 3) == 3) r[q] = (T)0;
-    }
-    T left = __shfl_up(r[3], 1, 64);
-    if (tx == 0) {
-      left = (T)0;
-      if (halo && b <= last && G.inner(4 * mh + 3) && !(SKIPLAST && ((3 + s) & 3) == 3)) {
-        T w[7];
+    } else {
+      T r[4];
 #pragma unroll
-        for (int d = 0; d < 7; ++d) w[d] = hz[ty][(k + d - 3) & 7];
-        left = res_at(3, 0, w, fh);
+      for (int q = 0; q < 4; ++q) {
+        r[q] = (T)0;
+        if (live && G.inner(4 * m + q)) {
+          T w[7];
+#pragma unroll
+          for (int d = 0; d < 7; ++d) w[d] = win[d][q];
+          r[q] = res_at(ty + 3, q, tx + 1, w, fc[q]);
+          if (own && k <= k1) nrm += (double)r[q] * (double)r[q];
+        }
+        if (SKIPLAST && ((q + s) & 3) == 3) r[q] = (T)0;
       }
+      const T left = __shfl_up(r[3], 1, 64);
+      // the first lane's halo term is added when its rows are combined
+      srx[buf][ty][0][tx] = tx == 0 ? h2 * r[0] + q4 * r[1] : q4 * left + h2 * r[0] + q4 * r[1];
+      srx[buf][ty][1][tx] = q4 * r[1] + h2 * r[2] + q4 * r[3];
     }
-    srx[buf][ty][0][tx] = q4 * left + h2 * r[0] + q4 * r[1];
-    srx[buf][ty][1][tx] = q4 * r[1] + h2 * r[2] + q4 * r[3];
 #pragma unroll
     for (int d = 0; d < 6; ++d)
 #pragma unroll
@@ -2303,37 +2318,28 @@ bool resrestrict19_ok(const Geom& Gf) {
   return Gf.C == 4 && Gf.g == 3 && Gf.n >= 128 && staged_mbase(Gf) == 1 && (Gf.n % 2) == 0;
 }
 
-// Own rows per block of the fused kernel: the residual kernel's 8, or 14 on
-// FP32 levels from 512 intervals, where one block of 15 waves fills the wave
-// slots of a CU (FP32: 4 per SIMD) and loads fewer halo rows per row (517
-// against 589 us at 511^3; FP64 with 10 rows and the smaller levels were not
-// faster).
+// Own rows per block of the fused kernel: the residual kernel's 8.  Taller
+// blocks that fill more of a CU's wave slots with one block (FP32 at 511^3:
+// 12 or 14 rows, FP64: 10) were not faster with the halo wavefront.
 template <typename T, int TR>
 static int resrestrict19_tr(const T* phi, const T* f, const Geom& Gf, T* f_coarse, const Geom& Gc, double* partial,
                             bool last_zero, hipStream_t st) {
   const dim3 sg0 = staged_grid(Gf);
-  const dim3 sg(sg0.x, (Gf.n - 1 + TR - 1) / TR, sg0.z), blk(BX, TR + 1);
+  const dim3 sg(sg0.x, (Gf.n - 1 + TR - 1) / TR, sg0.z), blk(BX, TR + 2);
   const T ih2 = (T)(1.0 / (Gf.h * Gf.h));
   const int mb = staged_mbase(Gf);
   if (last_zero)
     k_resrestrict19<T, true, TR><<<sg, blk, 0, st>>>(phi, f, Gf, ih2, f_coarse, Gc, partial, mb);
   else
     k_resrestrict19<T, false, TR><<<sg, blk, 0, st>>>(phi, f, Gf, ih2, f_coarse, Gc, partial, mb);
-  // the norm of column 0's unknowns (their residuals enter the restriction
-  // through the first lane's halo window)
-  if (partial && staged_col0(Gf))
-    k_res19_col0<T, T, false><<<col0_blocks(Gf), 256, 0, st>>>(phi, f, (T*)nullptr, Gf, ih2, partial, nblocks(sg));
-  return (int)(nblocks(sg) + col0_blocks(Gf));
+  return (int)nblocks(sg);
 }
 
 int resrestrict19(const void* phi, const void* f, bool f32, const Geom& Gf, void* f_coarse, const Geom& Gc,
                   double* partial, bool last_zero, hipStream_t st) {
-  if (f32) {
-    auto x = (const float*)phi, y = (const float*)f;
-    auto c = (float*)f_coarse;
-    return Gf.n >= 512 ? resrestrict19_tr<float, 14>(x, y, Gf, c, Gc, partial, last_zero, st)
-                       : resrestrict19_tr<float, TBY>(x, y, Gf, c, Gc, partial, last_zero, st);
-  }
+  if (f32)
+    return resrestrict19_tr<float, TBY>((const float*)phi, (const float*)f, Gf, (float*)f_coarse, Gc, partial,
+                                        last_zero, st);
   return resrestrict19_tr<double, TBY>((const double*)phi, (const double*)f, Gf, (double*)f_coarse, Gc, partial,
                                        last_zero, st);
 }

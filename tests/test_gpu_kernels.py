@@ -141,10 +141,10 @@ F32TOL = 1e-5
 @pytest.mark.parametrize("order,n", [(2, 64), (2, 256), (6, 64), (6, 128), (6, 256), (6, 512)])
 def test_restricted_residual_fp32(order, n):
     """The mixed plan's FP32 residual and restriction (the inner cycles'
-    kernels; at n = 512 the fused kernel's 14-row blocks of the 511^3 mixed
-    solve) against the oracle's residual and full weighting of the same
-    FP32-rounded Phi and rho, and the FP64 sum of squares of the FP32
-    residuals."""
+    kernels; from 128 intervals the fused kernel, at n = 512 in the launch
+    configuration of the 511^3 mixed solve) against the oracle's residual
+    and full weighting of the same FP32-rounded Phi and rho, and the FP64
+    sum of squares of the FP32 residuals."""
     say(f"restricted residual FP32 n={n} order={order}")
     plan, g = _plan(n, order, method="mg_ir32")
     phi, rho = random_cart(n, g, 37)
