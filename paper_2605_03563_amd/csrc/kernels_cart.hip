@@ -736,6 +736,7 @@ __global__ __launch_bounds__(BX*(TR + 2)) void k_resrestrict19(const T* __restri
   static_assert(TR % 2 == 0, "coarse rows whole within a block");
   static_assert(BX * RRY >= 8 * RTROWS, "one halo-column cell per thread");
   static_assert(RRY <= BX, "one halo-wavefront lane per row");
+  static_assert(RRY >= 6, "thread rows 0-5 load the six halo rows");
   __shared__ T tile[2][RTROWS][4][TCOLS];
   __shared__ T srx[2][RRY][2][BX];
   __shared__ T hres[2][RRY];  // residual at position 3 of compact column m0-1, per row
@@ -2318,9 +2319,10 @@ bool resrestrict19_ok(const Geom& Gf) {
   return Gf.C == 4 && Gf.g == 3 && Gf.n >= 128 && staged_mbase(Gf) == 1 && (Gf.n % 2) == 0;
 }
 
-// Own rows per block of the fused kernel: the residual kernel's 8.  Taller
-// blocks that fill more of a CU's wave slots with one block (FP32 at 511^3:
-// 12 or 14 rows, FP64: 10) were not faster with the halo wavefront.
+// Own rows per block of the fused kernel: the residual kernel's 8, or 6 on
+// FP32 levels from 512 intervals, where two blocks of eight wavefronts fill
+// a CU's 16 wave slots (503 against 577 us at 511^3).  Taller blocks (FP32:
+// 12 or 14 rows; FP64: 10) were slower.
 template <typename T, int TR>
 static int resrestrict19_tr(const T* phi, const T* f, const Geom& Gf, T* f_coarse, const Geom& Gc, double* partial,
                             bool last_zero, hipStream_t st) {
@@ -2337,9 +2339,12 @@ static int resrestrict19_tr(const T* phi, const T* f, const Geom& Gf, T* f_coars
 
 int resrestrict19(const void* phi, const void* f, bool f32, const Geom& Gf, void* f_coarse, const Geom& Gc,
                   double* partial, bool last_zero, hipStream_t st) {
-  if (f32)
-    return resrestrict19_tr<float, TBY>((const float*)phi, (const float*)f, Gf, (float*)f_coarse, Gc, partial,
-                                        last_zero, st);
+  if (f32) {
+    auto x = (const float*)phi, y = (const float*)f;
+    auto c = (float*)f_coarse;
+    return Gf.n >= 512 ? resrestrict19_tr<float, 6>(x, y, Gf, c, Gc, partial, last_zero, st)
+                       : resrestrict19_tr<float, TBY>(x, y, Gf, c, Gc, partial, last_zero, st);
+  }
   return resrestrict19_tr<double, TBY>((const double*)phi, (const double*)f, Gf, (double*)f_coarse, Gc, partial,
                                        last_zero, st);
 }
