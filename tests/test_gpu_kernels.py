@@ -108,15 +108,15 @@ def test_four_colour_pass_and_residual_at_511():
     assert n2 == pytest.approx(float(np.sum(rref * rref)), rel=1e-12)
 
 
-@pytest.mark.parametrize("order,n", [(2, 64), (2, 256), (6, 64), (6, 128), (6, 256), (6, 512)])
+@pytest.mark.parametrize("order,n", [(2, 64), (2, 256), (6, 64), (6, 128), (6, 192), (6, 256), (6, 512)])
 def test_restricted_residual(order, n):
     """R (f - L phi) and the fine residual's sum of squares against the
     oracle's residual followed by its full weighting.  On the four-colour
-    levels from 128 intervals one fused kernel forms both (n = 512: the
-    launch configuration of the 511^3 solve's cycle head, here restricting
-    every colour)."""
+    levels from 128 intervals one fused kernel forms both (n = 192: partial
+    blocks along x, y and z; n = 512: the launch configuration of the 511^3
+    solve's cycle head, here restricting every colour)."""
     say(f"restricted residual n={n} order={order}")
-    plan, g = _plan(n, order, method="mg")
+    plan, g = _plan(n, order, method="mg", **({"coarsest": 6} if n == 192 else {}))
     phi, rho = random_cart(n, g, 29)
     rng = np.random.default_rng(31)
     s = slice(g, g + n - 1)
@@ -138,7 +138,7 @@ def test_restricted_residual(order, n):
 F32TOL = 1e-5
 
 
-@pytest.mark.parametrize("order,n", [(2, 64), (2, 256), (6, 64), (6, 128), (6, 256), (6, 512)])
+@pytest.mark.parametrize("order,n", [(2, 64), (2, 256), (6, 64), (6, 128), (6, 192), (6, 256), (6, 512)])
 def test_restricted_residual_fp32(order, n):
     """The mixed plan's FP32 residual and restriction (the inner cycles'
     kernels; from 128 intervals the fused kernel, at n = 512 in the launch
@@ -146,7 +146,7 @@ def test_restricted_residual_fp32(order, n):
     and full weighting of the same FP32-rounded Phi and rho, and the FP64
     sum of squares of the FP32 residuals."""
     say(f"restricted residual FP32 n={n} order={order}")
-    plan, g = _plan(n, order, method="mg_ir32")
+    plan, g = _plan(n, order, method="mg_ir32", **({"coarsest": 6} if n == 192 else {}))
     phi, rho = random_cart(n, g, 37)
     rng = np.random.default_rng(41)
     s = slice(g, g + n - 1)
