@@ -11,15 +11,14 @@ constexpr long long kPartialCap = 1 << 16;  // partial-sum slots per reduction
 // MI355X dispatches consecutive workgroups round-robin over its 8 XCDs, each
 // with a private L2.  Renumber the blocks so that XCD x receives a contiguous
 // run of logical blocks (a contiguous range of planes), keeping the plane
-// neighbours of a stencil inside one L2.
+// neighbours of a stencil inside one L2.  With total = 8q + r blocks, XCD x
+// holds q + (x < r) of them, and its runs start where the previous end.
 __device__ inline void xcd_block(int& bx, int& by, int& bz) {
   const unsigned gx = gridDim.x, gy = gridDim.y, gz = gridDim.z;
   const unsigned total = gx * gy * gz;
   unsigned lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-  if ((total & 7u) == 0u) {
-    const unsigned per = total >> 3;
-    lin = (lin & 7u) * per + (lin >> 3);
-  }
+  const unsigned q = total >> 3, r = total & 7u, x = lin & 7u;
+  lin = x * q + (x < r ? x : r) + (lin >> 3);
   bx = (int)(lin % gx);
   const unsigned t = lin / gx;
   by = (int)(t % gy);
