@@ -2342,8 +2342,12 @@ int resrestrict19(const void* phi, const void* f, bool f32, const Geom& Gf, void
   if (f32) {
     auto x = (const float*)phi, y = (const float*)f;
     auto c = (float*)f_coarse;
-    return Gf.n >= 512 ? resrestrict19_tr<float, 6>(x, y, Gf, c, Gc, partial, last_zero, st)
-                       : resrestrict19_tr<float, TBY>(x, y, Gf, c, Gc, partial, last_zero, st);
+    // 6-row blocks write 4/3 as many partial sums as the 8-row grid, for
+    // which the plan checked the partial-sum capacity
+    const dim3 sg0 = staged_grid(Gf);
+    const bool six = Gf.n >= 512 && (!partial || (long long)sg0.x * ((Gf.n - 1 + 5) / 6) * sg0.z <= kPartialCap);
+    return six ? resrestrict19_tr<float, 6>(x, y, Gf, c, Gc, partial, last_zero, st)
+               : resrestrict19_tr<float, TBY>(x, y, Gf, c, Gc, partial, last_zero, st);
   }
   return resrestrict19_tr<double, TBY>((const double*)phi, (const double*)f, Gf, (double*)f_coarse, Gc, partial,
                                        last_zero, st);
