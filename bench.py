@@ -908,8 +908,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build measures one MI355X; --gpus above 1 is not supported "
-              "(the multi-GPU sharding is a design note, not part of the build)", file=sys.stderr)
+        print("bench.py: the solver runs on one MI355X; --gpus above 1 is not supported "
+              "(sharding over several GPUs is designed but not implemented)", file=sys.stderr)
         sys.exit(2)
 
     if args.kernels_only:
